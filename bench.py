@@ -1,0 +1,172 @@
+"""Benchmark: certified FJ index solves per second on one MI355X.
+
+One step = one fj_indices call: the right-hand-side statistics, the
+Jacobi-preconditioned CG solve of (I+L)z = s and the fused index epilogue with
+its certificate (every index within eps = 1e-6 relative), on a graph and an
+opinion vector already resident in HBM; the per-graph fj_prepare runs once
+before timing and is reported separately.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cl4m]
+
+Prints one JSON line. Inputs are seeded synthetic stand-ins for the paper's
+KONECT / Network Repository graphs (see paper_2101_08143_amd/workloads.py).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FJ index solves/sec at 1e-6 rel err; achieved HBM GB/s; serving p50/p99 ms"
+PEAK_HBM_GBS = 8000.0
+
+WORKLOAD_META = {
+    "ba10k": dict(graph="Barabasi-Albert", n=10_000, m_per_node=3, weights="unit", opinions="U[0,1]"),
+    "cl1m": dict(graph="Chung-Lu", n=1_000_000, gamma=2.5, mean_degree=10, weights="unit", opinions="U[0,1]"),
+    "cl4m": dict(graph="Chung-Lu", n=4_000_000, gamma=2.2, mean_degree=30, weights="float32 U[0.5,2]",
+                 opinions="Exp(1) min-max scaled"),
+}
+
+
+def spmv_bytes(n: int, nnz: int, val_bytes: int) -> int:
+    """Algorithmic bytes of one CG SpMV launch (k_cg_spmv): col and val once,
+    row_ptr once, the direction p once (an ideal gather), the residual r and
+    the preconditioner (f32) once for the fused dot products, and q written once."""
+    return nnz * (4 + val_bytes) + 4 * (n + 1) + 8 * n + 8 * n + 4 * n + 8 * n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cl4m", choices=sorted(WORKLOAD_META))
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed for cpu_baseline (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2101_08143_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_2101_08143_amd import fj
+    from paper_2101_08143_amd import workloads as W
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g, s, spec = W.workload(args.workload)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] workload {args.workload}: n={g.n} nnz={g.nnz} generated in {t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    G = fj.Graph.from_csr(g, device=dev, validate=False)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    sd = torch.from_numpy(s).to(dev)
+    opts = fj.make_opts(eps=args.eps, rtol=spec["rtol"])
+    popts = fj.make_opts(eps=args.eps, rtol=spec["rtol"], flags=fj.FJ_PROFILE)
+    ws = G.workspace(1, opts)
+
+    for _ in range(args.warmup):
+        fj.fj_indices(G, sd, opts, ws=ws)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_spmv = 0.0
+    n_spmv = 0
+    iters = 0
+    last = None
+    for _ in range(args.steps):
+        vals, infos, rc = fj.fj_indices(G, sd, popts, ws=ws)
+        ms_spmv += infos[0].ms_spmv
+        n_spmv += infos[0].n_spmv
+        iters += infos[0].iters
+        last = (vals[0], infos[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+
+    val_bytes = 0 if g.val is None else g.val.dtype.itemsize
+    b_launch = spmv_bytes(g.n, g.nnz, val_bytes)
+    avg_ms = ms_spmv / max(n_spmv, 1)
+    bytes_per_launch = b_launch * iters / max(n_spmv, 1)  # launches after convergence do no work
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    vals, info = last
+    result = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, **WORKLOAD_META[args.workload], "nnz": g.nnz, "eps": args.eps,
+                   "precision": "fp64", "rhs_per_solve": 1},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_cg_spmv",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "launches": n_spmv,
+            "working_launches": iters,
+            "algorithmic_bytes_per_working_launch": b_launch,
+        },
+        "detail": {
+            "iters_per_solve": info.iters,
+            "passes": info.passes,
+            "rel_residual": info.rel_residual,
+            "bounds": list(info.bound),
+            "indices": vals,
+            "prepare_s": t_prep,
+            "generate_s": t_gen,
+        },
+    }
+
+    if args.cpu_solves > 0:
+        from oracle import sparse as O
+        t0 = time.perf_counter()
+        ref = None
+        for _ in range(args.cpu_solves):
+            z, oinfo = O.solve(g, s, rtol=opts.rtol if opts.rtol > 0 else args.eps * 1e-2)
+            ref = O.indices_at(g, s, z)
+        t_cpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": args.cpu_solves / t_cpu,
+            "unit": "solves/s",
+            "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{args.cpu_solves} full oracle solves (FP64 Jacobi-PCG in C/OpenMP, same graph and s, "
+                      f"same first-pass residual target) plus the index definitions",
+        }
+        result["detail"]["max_rel_diff_vs_oracle"] = max(
+            abs(vals[k] - ref[k]) / abs(ref[k]) for k in fj.INDEX_NAMES)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

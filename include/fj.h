@@ -1,0 +1,173 @@
+/*
+ * fj.h -- C ABI of libfjgpu: Friedkin-Johnsen equilibrium and opinion indices
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Xu, Bao, Zhang, "Fast Evaluation for Relevant Quantities
+ * of Opinion Dynamics", WWW 2021):
+ *   - the equilibrium expressed opinions z = (I + L)^{-1} s of the FJ model
+ *     (Section 3.1, Eq. FJmodel02), where L = D - A is the Laplacian of a
+ *     weighted undirected graph (Section 2.1) and s in [0,1]^n are the
+ *     internal opinions;
+ *   - the five indices of Section 3.2 (Definitions; Proposition 1;
+ *     Lemma 4.1), each to a certified relative error eps, which is the
+ *     eps-approximation guarantee of the Theorem in Section 4 (the output of
+ *     Algorithm 1, Approxim(G, s, eps)).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless it
+ *     is documented as host. The library never allocates device memory: the
+ *     caller provides the plan and the workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every call is ordered on that stream. Calls that return results to host
+ *     memory (fj_indices, fj_solve's info) synchronise with the stream before
+ *     returning.
+ *   - Every function returns an int status (FJ_OK = 0 on success). No C++
+ *     exception crosses the ABI and the library never aborts the process.
+ *   - Calls are thread-safe when concurrent calls use distinct workspaces.
+ *     A plan may be shared by concurrent calls once fj_prepare has completed.
+ *   - Per calling thread and device the library keeps a small pinned host
+ *     block (about 2 KiB) and a few HIP events, created on first use.
+ */
+#ifndef FJ_H
+#define FJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FJ_OK                 0
+#define FJ_ERR_INVALID_ARG    1  /* a null pointer, n < 0, eps outside (0, 1/2), ... */
+#define FJ_ERR_INVALID_GRAPH  2  /* FJ_VALIDATE_GRAPH found a violation of the CSR contract */
+#define FJ_ERR_OPINION_RANGE  3  /* some s_i is NaN or outside [0,1] (Section 3.1 assumes s in [0,1]) */
+#define FJ_ERR_WORKSPACE      4  /* plan or workspace smaller than the queried size, or misaligned */
+#define FJ_ERR_NOT_CONVERGED  5  /* max_iter reached; results and bounds are still written */
+#define FJ_ERR_BREAKDOWN      6  /* CG breakdown (p^T (I+L) p <= 0 or not finite) */
+#define FJ_ERR_UNCERTIFIABLE  7  /* an index is too close to 0 for a relative bound; bounds are written */
+#define FJ_ERR_HIP            8  /* a HIP runtime call failed */
+
+/* ---- graph -------------------------------------------------------------- */
+#define FJ_VAL_UNIT 0  /* every edge has weight 1; val must be NULL */
+#define FJ_VAL_F32  1  /* val is float[nnz] */
+#define FJ_VAL_F64  2  /* val is double[nnz] */
+
+/*
+ * Weighted undirected simple graph G = (V, E, w) of Section 2.1 in CSR form,
+ * both directions of every edge stored: entry (i, j) with weight w_ij and
+ * entry (j, i) with the same weight. Column indices strictly increasing inside
+ * each row (no repeated edges), no self-loops, weights finite and > 0.
+ * Isolated nodes are allowed (the paper assumes a connected graph; I + L is
+ * positive definite regardless, so the equilibrium is still unique).
+ * Limits: 0 <= n, nnz < 2^31 (int32 row pointers).
+ */
+typedef struct fj_csr {
+    int32_t n;                /* number of nodes */
+    int64_t nnz;              /* stored entries = 2 * number of edges = row_ptr[n] */
+    const int32_t *row_ptr;   /* device, n + 1 entries, row_ptr[0] = 0 */
+    const int32_t *col_idx;   /* device, nnz entries */
+    const void *val;          /* device, nnz entries of float/double, or NULL (FJ_VAL_UNIT) */
+    int32_t val_type;         /* FJ_VAL_UNIT, FJ_VAL_F32 or FJ_VAL_F64 */
+} fj_csr;
+
+/* ---- options ------------------------------------------------------------ */
+#define FJ_FP64  0  /* FP64 operator, vectors and reductions throughout */
+#define FJ_MIXED 1  /* FP32 inner CG wrapped in FP64 residual-and-correction refinement */
+
+#define FJ_TWO_SOLVE       1u  /* Algorithm 1 literally: solve for s and for the centred s too */
+#define FJ_NO_RANGE_CHECK  2u  /* accept opinions outside [0,1] (the algebra holds for any real s) */
+#define FJ_VALIDATE_GRAPH  4u  /* fj_prepare checks the CSR contract (synchronises) */
+#define FJ_PROFILE         8u  /* time every SpMV launch with HIP events (fills fj_info.ms_*) */
+
+typedef struct fj_opts {
+    double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */
+    double rtol;          /* relative residual ||s-(I+L)z||/||s|| of the first CG pass; 0 = eps * 1e-2 */
+    int32_t max_iter;     /* CG iterations over all passes; 0 = 2000 */
+    int32_t precision;    /* FJ_FP64 or FJ_MIXED */
+    uint32_t flags;       /* FJ_* flags above */
+    int32_t reserved;     /* must be 0 */
+} fj_opts;
+
+/* Fill *opts with the defaults: eps = 1e-6, rtol = 0, max_iter = 0, FJ_FP64, no flags. */
+void fj_default_opts(fj_opts *opts);
+
+/* ---- results ------------------------------------------------------------ */
+/* Section 3.2 indices; dc_index is reported through its equal form s^T z. */
+typedef struct fj_indices_t {
+    double internal_conflict;  /* C_I  = sum_i (z_i - s_i)^2 = ||L z||^2        */
+    double disagreement;       /* D    = sum_{(i,j) in E} w_ij (z_i - z_j)^2     */
+    double polarization;       /* P    = sum_i (z_i - mean(z))^2                 */
+    double controversy;        /* C    = sum_i z_i^2                             */
+    double dc_index;           /* I_dc = D + C = s^T z                           */
+} fj_indices_t;
+
+typedef struct fj_info {
+    int32_t status;        /* per-column status (same codes as the return value) */
+    int32_t iters;         /* CG iterations over all passes */
+    int32_t passes;        /* CG passes (each pass restarts from the true residual) */
+    int32_t outer_iters;   /* FJ_MIXED refinement steps (0 for FJ_FP64) */
+    double rel_residual;   /* ||s - (I+L) z||_2 / ||s||_2, true residual in FP64 */
+    double bound[5];       /* certified relative error bound of each index, order of fj_indices_t */
+    double ms_spmv;        /* FJ_PROFILE: total milliseconds inside the CG SpMV kernel */
+    int32_t n_spmv;        /* FJ_PROFILE: number of CG SpMV launches timed */
+    int32_t reserved;
+} fj_info;
+
+/* ---- entry points ------------------------------------------------------- */
+
+/* Human-readable name of a status code (static string). */
+const char *fj_status_string(int status);
+
+/* Detail of the last FJ_ERR_HIP or FJ_ERR_INVALID_GRAPH on the calling thread
+ * ("" if none). The string stays valid until the thread's next call. */
+const char *fj_last_error(void);
+
+/* Bytes of device memory fj_prepare needs for the per-graph plan of g. */
+size_t fj_plan_bytes(const fj_csr *g);
+
+/*
+ * One-time set-up of the operator I + L for graph g (Section 2.1): the
+ * Jacobi preconditioner diag(I + D)^{-1} and the row-window partition that
+ * balances the sparse passes. Writes `plan` (device, >= fj_plan_bytes, 256-byte
+ * aligned). Asynchronous on `stream` unless opts->flags has FJ_VALIDATE_GRAPH,
+ * which also checks the CSR contract and synchronises. opts may be NULL.
+ */
+int fj_prepare(const fj_csr *g, const fj_opts *opts, void *plan, size_t plan_bytes, void *stream);
+
+/* Bytes of device workspace a solve of k right-hand sides needs. */
+size_t fj_workspace_bytes(const fj_csr *g, int32_t k, const fj_opts *opts);
+
+/*
+ * y = (I + L) x (Section 2.1, L = D - A), FP64. x, y: device double[n],
+ * distinct. Asynchronous on `stream`.
+ */
+int fj_apply(const fj_csr *g, const void *plan, const double *x, double *y, void *stream);
+
+/*
+ * Z ~= (I + L)^{-1} S (Eq. FJmodel02) for k columns. S and Z are node-major:
+ * column c of node i is S[i * lds + c] (lds >= k), likewise Z with ldz.
+ * Stops when the true relative residual is <= opts->rtol (0 means eps*1e-2).
+ * info: host array of k entries (may be NULL). Synchronises before returning.
+ */
+int fj_solve(const fj_csr *g, const void *plan, int32_t k, const double *S, int64_t lds,
+             double *Z, int64_t ldz, const fj_opts *opts, void *ws, size_t ws_bytes,
+             void *stream, fj_info *info);
+
+/*
+ * Algorithm 1 (Approxim): the five indices of Section 3.2 for each of k
+ * opinion vectors, each certified to relative error <= opts->eps. S as in
+ * fj_solve. out and info are host arrays of k entries (info may be NULL).
+ * Returns FJ_OK only when every index of every column is certified.
+ * Synchronises before returning.
+ */
+int fj_indices(const fj_csr *g, const void *plan, int32_t k, const double *S, int64_t lds,
+               const fj_opts *opts, void *ws, size_t ws_bytes, void *stream,
+               fj_indices_t *out, fj_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FJ_H */

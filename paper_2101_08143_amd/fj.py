@@ -1,0 +1,260 @@
+"""Thin ctypes binding of libfjgpu (include/fj.h). Argument marshalling only:
+every step of the computation runs in the library's HIP kernels.
+
+PyTorch provides device memory (plan, workspace, vectors) and the stream
+(torch.cuda.current_stream()). The binding raises if the library has not been
+built; there is no fallback of any kind.
+
+Entry points keep the C names: fj_plan_bytes, fj_prepare, fj_workspace_bytes,
+fj_apply, fj_solve, fj_indices, fj_status_string, fj_default_opts. The Graph
+class and indices()/solve() wrap them for tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfjgpu.so")
+
+FJ_OK = 0
+FJ_ERR_INVALID_ARG = 1
+FJ_ERR_INVALID_GRAPH = 2
+FJ_ERR_OPINION_RANGE = 3
+FJ_ERR_WORKSPACE = 4
+FJ_ERR_NOT_CONVERGED = 5
+FJ_ERR_BREAKDOWN = 6
+FJ_ERR_UNCERTIFIABLE = 7
+FJ_ERR_HIP = 8
+
+FJ_VAL_UNIT, FJ_VAL_F32, FJ_VAL_F64 = 0, 1, 2
+FJ_FP64, FJ_MIXED = 0, 1
+FJ_TWO_SOLVE, FJ_NO_RANGE_CHECK, FJ_VALIDATE_GRAPH, FJ_PROFILE = 1, 2, 4, 8
+
+INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
+
+# Every function declared in include/fj.h, in declaration order.
+EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
+           "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_indices")
+
+
+class fj_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val_type", ctypes.c_int32)]
+
+
+class fj_opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class fj_indices_t(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in INDEX_NAMES]
+
+
+class fj_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("outer_iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("bound", ctypes.c_double * 5), ("ms_spmv", ctypes.c_double),
+                ("n_spmv", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class FJError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = fj_status_string(status)
+        extra = last_error()
+        super().__init__(f"{where}: {msg} (status {status})" + (f" [{extra}]" if extra else ""))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2101_08143_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.fj_default_opts.argtypes = [P(fj_opts)]
+        L.fj_default_opts.restype = None
+        L.fj_status_string.argtypes = [ctypes.c_int]
+        L.fj_status_string.restype = ctypes.c_char_p
+        L.fj_last_error.argtypes = []
+        L.fj_last_error.restype = ctypes.c_char_p
+        L.fj_plan_bytes.argtypes = [P(fj_csr)]
+        L.fj_plan_bytes.restype = sz
+        L.fj_prepare.argtypes = [P(fj_csr), P(fj_opts), vp, sz, vp]
+        L.fj_workspace_bytes.argtypes = [P(fj_csr), i32, P(fj_opts)]
+        L.fj_workspace_bytes.restype = sz
+        L.fj_apply.argtypes = [P(fj_csr), vp, vp, vp, vp]
+        L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
+        L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
+                                 P(fj_info)]
+        for name in ("fj_prepare", "fj_apply", "fj_solve", "fj_indices"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def fj_status_string(status: int) -> str:
+    return lib().fj_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().fj_last_error().decode()
+
+
+def fj_default_opts() -> fj_opts:
+    o = fj_opts()
+    lib().fj_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(eps=1e-6, rtol=0.0, max_iter=0, precision=FJ_FP64, flags=0) -> fj_opts:
+    o = fj_default_opts()
+    o.eps, o.rtol, o.max_iter, o.precision, o.flags = eps, rtol, max_iter, precision, flags
+    return o
+
+
+def _stream_handle(torch, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _aligned_empty(torch, nbytes, device):
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+@dataclass
+class Graph:
+    """A graph resident in HBM with its prepared plan (fj_prepare)."""
+
+    n: int
+    nnz: int
+    row_ptr: object
+    col: object
+    val: object
+    val_type: int
+    plan: object
+    csr: fj_csr
+    device: object
+
+    @classmethod
+    def from_csr(cls, g, device="cuda", validate=True, stream=None) -> "Graph":
+        """g: a workloads.CSRGraph (numpy arrays). Copies to the device and prepares."""
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int32)).to(device)
+        col = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).to(device)
+        if g.val is None:
+            val, vt = None, FJ_VAL_UNIT
+        elif g.val.dtype == np.float32:
+            val, vt = torch.from_numpy(np.ascontiguousarray(g.val)).to(device), FJ_VAL_F32
+        else:
+            val, vt = torch.from_numpy(np.ascontiguousarray(g.val, dtype=np.float64)).to(device), FJ_VAL_F64
+        return cls.from_tensors(g.n, rp, col, val, vt, validate=validate, stream=stream)
+
+    @classmethod
+    def from_tensors(cls, n, row_ptr, col, val, val_type, validate=True, stream=None) -> "Graph":
+        import torch
+        nnz = int(col.numel())
+        csr = fj_csr(n=int(n), nnz=nnz, row_ptr=_ptr(row_ptr), col_idx=_ptr(col) if nnz else None,
+                     val=_ptr(val) if val is not None else None, val_type=val_type)
+        device = row_ptr.device
+        nbytes = lib().fj_plan_bytes(ctypes.byref(csr))
+        plan = _aligned_empty(torch, nbytes, device)
+        o = make_opts(flags=FJ_VALIDATE_GRAPH if validate else 0)
+        rc = lib().fj_prepare(ctypes.byref(csr), ctypes.byref(o), _ptr(plan), nbytes,
+                              _stream_handle(torch, stream))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_prepare")
+        return cls(n=int(n), nnz=nnz, row_ptr=row_ptr, col=col, val=val, val_type=val_type, plan=plan,
+                   csr=csr, device=device)
+
+    def workspace(self, k=1, opts: Optional[fj_opts] = None):
+        import torch
+        o = opts or fj_default_opts()
+        nbytes = lib().fj_workspace_bytes(ctypes.byref(self.csr), int(k), ctypes.byref(o))
+        return _aligned_empty(torch, nbytes, self.device)
+
+
+def fj_apply(graph: Graph, x, y=None, stream=None):
+    """y = (I + L) x for a device float64 vector x."""
+    import torch
+    assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == graph.n
+    if y is None:
+        y = torch.empty_like(x)
+    rc = lib().fj_apply(ctypes.byref(graph.csr), _ptr(graph.plan), _ptr(x), _ptr(y),
+                        _stream_handle(torch, stream))
+    if rc != FJ_OK:
+        raise FJError(rc, "fj_apply")
+    return y
+
+
+def _check_block(graph, S, name):
+    import torch
+    if S.dtype != torch.float64 or S.device != graph.device:
+        raise ValueError(f"{name} must be float64 on {graph.device}")
+    if S.dim() == 1:
+        S = S.view(-1, 1)
+    if S.dim() != 2 or S.shape[0] != graph.n or S.stride(1) != 1:
+        raise ValueError(f"{name} must be n x k with unit column stride")
+    return S, S.shape[1], S.stride(0)
+
+
+def fj_solve(graph: Graph, S, opts: Optional[fj_opts] = None, ws=None, Z=None, stream=None,
+             check=True):
+    """Z ~= (I+L)^{-1} S. Returns (Z, [fj_info]*k, status)."""
+    import torch
+    S2, k, lds = _check_block(graph, S, "S")
+    o = opts or fj_default_opts()
+    if Z is None:
+        Z = torch.empty((graph.n, k), dtype=torch.float64, device=graph.device)
+    Z2, kz, ldz = _check_block(graph, Z, "Z")
+    assert kz == k
+    if ws is None:
+        ws = graph.workspace(k, o)
+    info = (fj_info * k)()
+    rc = lib().fj_solve(ctypes.byref(graph.csr), _ptr(graph.plan), k, _ptr(S2), lds, _ptr(Z2), ldz,
+                        ctypes.byref(o), _ptr(ws), ws.numel(), _stream_handle(torch, stream), info)
+    if check and rc not in (FJ_OK,):
+        raise FJError(rc, "fj_solve")
+    return (Z.view(-1) if S.dim() == 1 else Z), list(info), rc
+
+
+def fj_indices(graph: Graph, S, opts: Optional[fj_opts] = None, ws=None, stream=None, check=True):
+    """Algorithm 1: the five indices per column. Returns (list of dicts, [fj_info]*k, status)."""
+    import torch
+    S2, k, lds = _check_block(graph, S, "S")
+    o = opts or fj_default_opts()
+    if ws is None:
+        ws = graph.workspace(k, o)
+    out = (fj_indices_t * k)()
+    info = (fj_info * k)()
+    rc = lib().fj_indices(ctypes.byref(graph.csr), _ptr(graph.plan), k, _ptr(S2), lds, ctypes.byref(o),
+                          _ptr(ws), ws.numel(), _stream_handle(torch, stream), out, info)
+    if check and rc != FJ_OK:
+        raise FJError(rc, "fj_indices")
+    vals = [{name: getattr(out[c], name) for name in INDEX_NAMES} for c in range(k)]
+    return vals, list(info), rc
+
+
+def info_dict(inf: fj_info) -> dict:
+    return dict(status=inf.status, iters=inf.iters, passes=inf.passes, outer_iters=inf.outer_iters,
+                rel_residual=inf.rel_residual, bound=list(inf.bound), ms_spmv=inf.ms_spmv,
+                n_spmv=inf.n_spmv)

@@ -1,0 +1,134 @@
+"""Host-side checks that need no GPU: the library loads, exports every
+function include/fj.h declares, rejects bad arguments before touching the
+device, and the row-window partition the kernels assume holds on the
+generated workloads."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2101_08143_amd import build as B
+from paper_2101_08143_amd import fj
+from paper_2101_08143_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fj.h")
+KERNELS = os.path.join(ROOT, "paper_2101_08143_amd", "csrc", "fj_kernels.hpp")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if B.stale():
+        B.build()
+    return fj.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fj_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(fj.EXPORTS) == declared_functions()
+
+
+def test_library_exports_every_declared_function(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(0, 9):
+        assert fj.fj_status_string(code) not in ("", "unknown status")
+    assert fj.fj_status_string(99) == "unknown status"
+
+
+def test_sizes_are_pure_host_functions(lib):
+    csr = fj.fj_csr(n=1000, nnz=5000, row_ptr=1, col_idx=1, val=None, val_type=fj.FJ_VAL_UNIT)
+    pb = lib.fj_plan_bytes(ctypes.byref(csr))
+    o = fj.fj_default_opts()
+    wb1 = lib.fj_workspace_bytes(ctypes.byref(csr), 1, ctypes.byref(o))
+    assert pb > 1000 * 4 and pb % 256 == 0
+    assert wb1 >= 4 * 8 * 1000 and wb1 % 256 == 0
+    bad = fj.fj_csr(n=-1, nnz=0, row_ptr=None, col_idx=None, val=None, val_type=0)
+    assert lib.fj_plan_bytes(ctypes.byref(bad)) == 0
+    assert lib.fj_workspace_bytes(ctypes.byref(csr), 0, ctypes.byref(o)) == 0
+
+
+def test_argument_errors_are_caught_on_the_host(lib):
+    """Each of these returns before any HIP call, so it runs without a GPU."""
+    csr = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=None, val_type=fj.FJ_VAL_UNIT)
+    o = fj.fj_default_opts()
+    out = (fj.fj_indices_t * 1)()
+    info = (fj.fj_info * 1)()
+    call = lambda c, o_, k=1, lds=1: lib.fj_indices(ctypes.byref(c), ctypes.c_void_p(256), k,
+                                                   ctypes.c_void_p(256), lds, ctypes.byref(o_),
+                                                   ctypes.c_void_p(256), 1 << 30, None, out, info)
+    for eps in (0.0, 0.5, -1.0, float("nan")):
+        oo = fj.fj_default_opts()
+        oo.eps = eps
+        assert call(csr, oo) == fj.FJ_ERR_INVALID_ARG
+    oo = fj.fj_default_opts()
+    oo.reserved = 1
+    assert call(csr, oo) == fj.FJ_ERR_INVALID_ARG
+    assert call(csr, o, k=1, lds=0) == fj.FJ_ERR_INVALID_ARG
+    badval = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=1024, val_type=fj.FJ_VAL_UNIT)
+    assert call(badval, o) == fj.FJ_ERR_INVALID_ARG
+    badtype = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=1024, val_type=7)
+    assert call(badtype, o) == fj.FJ_ERR_INVALID_ARG
+    nonodes = fj.fj_csr(n=0, nnz=4, row_ptr=256, col_idx=512, val=None, val_type=0)
+    assert lib.fj_prepare(ctypes.byref(nonodes), None, ctypes.c_void_p(256), 1 << 20, None) == \
+        fj.FJ_ERR_INVALID_GRAPH
+    # misaligned or undersized plan
+    assert lib.fj_prepare(ctypes.byref(csr), None, ctypes.c_void_p(257), 1 << 20, None) == fj.FJ_ERR_WORKSPACE
+    assert lib.fj_prepare(ctypes.byref(csr), None, ctypes.c_void_p(256), 16, None) == fj.FJ_ERR_WORKSPACE
+
+
+def _constants():
+    src = open(KERNELS).read()
+    get = lambda name: int(re.search(rf"constexpr int {name} = (\d+)", src).group(1))
+    return get("WIN"), get("LONGROW")
+
+
+def _windows(g, WIN):
+    key = g.row_ptr[:-1].astype(np.int64) + np.arange(g.n)
+    K = (g.n + g.nnz + WIN - 1) // WIN
+    blk = np.searchsorted(key, np.arange(K + 1, dtype=np.int64) * WIN, side="left")
+    blk[-1] = g.n
+    return K, blk
+
+
+@pytest.mark.parametrize("name", ["ba", "cl_unit", "cl_weighted", "star", "isolated"])
+def test_window_partition_invariants(name):
+    """Rows per window <= WIN and staged entries < WIN + LONGROW: the LDS
+    capacity the window pass relies on (mirrors k_windows on the CPU)."""
+    WIN, LONGROW = _constants()
+    if name == "ba":
+        g = W.barabasi_albert(5000, 3, 1)
+    elif name == "cl_unit":
+        g = W.chung_lu(200_000, 2.1, 20.0, 2)
+    elif name == "cl_weighted":
+        g = W.chung_lu(100_000, 2.2, 30.0, 3, weighted=True)
+    elif name == "star":
+        g = W.csr_from_edges(6001, [(0, j) for j in range(1, 6001)])
+    else:
+        edges = [(i, i + 1) for i in range(3000, 3500)]
+        g = W.csr_from_edges(9000, edges)
+    K, blk = _windows(g, WIN)
+    rp = g.row_ptr.astype(np.int64)
+    covered = 0
+    for k in range(K):
+        r0, r1 = blk[k], blk[k + 1]
+        assert r0 <= r1
+        if r0 == r1:
+            continue
+        covered += r1 - r0
+        assert r1 - r0 <= WIN
+        elast, eend = rp[r1 - 1], rp[r1]
+        long_last = eend - elast > LONGROW
+        ns = (elast if long_last else eend) - rp[r0]
+        assert 0 <= ns < WIN + LONGROW
+    assert covered == g.n

@@ -1,0 +1,237 @@
+"""GPU path vs the CPU oracle, through the C ABI (libfjgpu via the ctypes
+binding). Every case prints its name before touching the GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sparse as O
+from paper_2101_08143_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
+EPS = 1e-6
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_fj():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_08143_amd import fj
+    fj.lib()
+    return torch, fj
+
+
+def small_graphs():
+    """Graphs that span several windows, ragged tails, hubs longer than the
+    LDS stage, isolated nodes and empty rows at both ends."""
+    iso_edges = [(i, i + 1) for i in range(3000, 3500)] + [(3000, j) for j in range(3600, 4700)]
+    return {
+        "path5": W.path_graph(5),
+        "ba3000": W.barabasi_albert(3000, 3, 11),
+        "gnp500_f64": W.random_graph(500, 0.02, 12, weighted=True),
+        "gnp400_f32": W.random_graph(400, 0.03, 13, weighted=True, val_dtype=np.float32),
+        "cl100k_unit": W.chung_lu(100_000, 2.1, 20.0, 14),
+        "cl50k_f32": W.chung_lu(50_000, 2.2, 30.0, 15, weighted=True),
+        "star6001": W.csr_from_edges(6001, [(0, j) for j in range(1, 6001)]),
+        "isolated9000": W.csr_from_edges(9000, iso_edges),
+        "cycle4099_w": W.cycle_graph(4099, 0.8),
+    }
+
+
+@pytest.fixture(scope="module")
+def graphs(torch_fj):
+    torch, fj = torch_fj
+    out = {}
+    for name, g in small_graphs().items():
+        say(f"prepare {name} n={g.n} nnz={g.nnz}")
+        out[name] = (g, fj.Graph.from_csr(g, device="cuda:0", validate=True))
+    torch.cuda.synchronize()
+    return out
+
+
+def _tolerance_apply(g, x):
+    w = np.abs(g.weights_f64())
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    mag = np.abs(x) * (1 + np.bincount(rows, weights=w, minlength=g.n))
+    mag += np.bincount(rows, weights=w * np.abs(x[g.col]), minlength=g.n)
+    return 1e-13 * mag + 1e-300
+
+
+@pytest.mark.parametrize("name", list(small_graphs().keys()))
+def test_apply_matches_oracle(torch_fj, graphs, name):
+    torch, fj = torch_fj
+    g, G = graphs[name]
+    say(f"apply {name}")
+    x = np.random.default_rng(1).standard_normal(g.n)
+    y = fj.fj_apply(G, torch.from_numpy(x).to("cuda:0")).cpu().numpy()
+    ref = O.apply(g, x)
+    assert np.all(np.abs(y - ref) <= _tolerance_apply(g, x))
+
+
+@pytest.mark.parametrize("name", [n for n in small_graphs() if n not in ("path5",)])
+@pytest.mark.parametrize("kind", ["uniform", "exp"])
+def test_indices_match_oracle(torch_fj, graphs, name, kind):
+    torch, fj = torch_fj
+    g, G = graphs[name]
+    s = W.opinions(kind, g.n, 21)
+    say(f"indices {name} {kind}")
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(s).to("cuda:0"), fj.make_opts(eps=EPS), check=False)
+    ref, _, oinfo = O.indices(g, s)
+    assert oinfo["status"] == 0 and oinfo["certified"]
+    assert rc == fj.FJ_OK, (fj.fj_status_string(rc), fj.info_dict(infos[0]))
+    for c, k in enumerate(NAMES):
+        err = abs(vals[0][k] - ref[k]) / abs(ref[k])
+        assert err <= EPS, (k, vals[0][k], ref[k], err)
+        assert err <= infos[0].bound[c] + 1e-12, (k, err, infos[0].bound[c])
+
+
+@pytest.mark.parametrize("name", ["ba3000", "cl100k_unit", "cl50k_f32", "star6001", "isolated9000"])
+def test_solve_matches_oracle(torch_fj, graphs, name):
+    torch, fj = torch_fj
+    g, G = graphs[name]
+    s = W.opinions("uniform", g.n, 22)
+    say(f"solve {name}")
+    rtol = 1e-11
+    z, infos, rc = fj.fj_solve(G, torch.from_numpy(s).to("cuda:0"), fj.make_opts(rtol=rtol))
+    z = z.cpu().numpy()
+    zref, oinfo = O.solve(g, s, rtol=1e-14)
+    assert infos[0].rel_residual <= rtol
+    # ||z - z_true|| <= ||s - (I+L) z|| because I <= I + L
+    bound = infos[0].rel_residual * np.linalg.norm(s) + 1e-13 * np.linalg.norm(s)
+    assert np.linalg.norm(z - zref) <= bound
+    assert np.abs(z.sum() - s.sum()) <= 1e-9 * s.sum()
+
+
+def test_p5_solve_reproduces_printed_forest_matrix(torch_fj, graphs):
+    """Section 2.2 worked example: (I+L)^{-1} e_j for P5 is column j of the printed Omega."""
+    torch, fj = torch_fj
+    g, G = graphs["path5"]
+    import oracle_pins
+    total, _, M = oracle_pins.load_p5_golden()
+    say("p5 columns")
+    for j in range(5):
+        s = np.eye(5)[:, j]
+        z, _, _ = fj.fj_solve(G, torch.from_numpy(s).to("cuda:0"), fj.make_opts(rtol=1e-14))
+        assert np.allclose(z.cpu().numpy() * total, M[:, j], rtol=0, atol=1e-11)
+
+
+def test_bitwise_deterministic(torch_fj, graphs):
+    torch, fj = torch_fj
+    g, G = graphs["cl100k_unit"]
+    s = torch.from_numpy(W.opinions("uniform", g.n, 23)).to("cuda:0")
+    say("determinism")
+    a = fj.fj_indices(G, s)[0][0]
+    b = fj.fj_indices(G, s)[0][0]
+    assert a == b
+    z1 = fj.fj_solve(G, s)[0].cpu().numpy()
+    z2 = fj.fj_solve(G, s)[0].cpu().numpy()
+    assert np.array_equal(z1, z2)
+
+
+def test_degenerate_cases(torch_fj, graphs):
+    torch, fj = torch_fj
+    dev = "cuda:0"
+    # constant opinions: z = s and P = D = C_I = 0, so no relative bound exists
+    g, G = graphs["ba3000"]
+    say("constant s")
+    s = np.full(g.n, 0.4)
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(s).to(dev), check=False)
+    assert rc == fj.FJ_ERR_UNCERTIFIABLE
+    assert abs(vals[0]["controversy"] - g.n * 0.16) <= 1e-9 * g.n * 0.16
+    assert abs(vals[0]["dc_index"] - g.n * 0.16) <= 1e-9 * g.n * 0.16
+    for k in ("internal_conflict", "disagreement", "polarization"):
+        assert vals[0][k] <= 1e-20
+    # edgeless graph: z = s, D = C_I = 0
+    ge = W.csr_from_edges(257, np.zeros((0, 2), dtype=np.int64))
+    say("edgeless")
+    Ge = fj.Graph.from_csr(ge, device=dev)
+    s = W.opinions("uniform", 257, 3)
+    vals, infos, rc = fj.fj_indices(Ge, torch.from_numpy(s).to(dev), check=False)
+    assert rc == fj.FJ_ERR_UNCERTIFIABLE
+    sb = s - s.mean()
+    assert abs(vals[0]["polarization"] - sb @ sb) <= 1e-12 * (sb @ sb)
+    assert abs(vals[0]["controversy"] - s @ s) <= 1e-12 * (s @ s)
+    assert vals[0]["disagreement"] == 0.0 and vals[0]["internal_conflict"] == 0.0
+    # one node
+    g1 = W.csr_from_edges(1, np.zeros((0, 2), dtype=np.int64))
+    say("single node")
+    G1 = fj.Graph.from_csr(g1, device=dev)
+    z, _, rc = fj.fj_solve(G1, torch.tensor([0.3], dtype=torch.float64, device=dev))
+    assert rc == fj.FJ_OK and z.cpu().numpy()[0] == 0.3
+
+
+def test_error_paths(torch_fj, graphs):
+    torch, fj = torch_fj
+    dev = "cuda:0"
+    g, G = graphs["ba3000"]
+    s = W.opinions("uniform", g.n, 4)
+    say("opinion range")
+    bad = s.copy()
+    bad[17] = 1.5
+    _, _, rc = fj.fj_indices(G, torch.from_numpy(bad).to(dev), check=False)
+    assert rc == fj.FJ_ERR_OPINION_RANGE
+    bad[17] = np.nan
+    _, _, rc = fj.fj_indices(G, torch.from_numpy(bad).to(dev), check=False)
+    assert rc == fj.FJ_ERR_OPINION_RANGE
+    say("no range check")
+    shifted = s * 3.0 - 1.0
+    vals, _, rc = fj.fj_indices(G, torch.from_numpy(shifted).to(dev),
+                                fj.make_opts(flags=fj.FJ_NO_RANGE_CHECK), check=False)
+    ref, _, _ = O.indices(g, shifted)
+    assert rc == fj.FJ_OK
+    for k in NAMES:
+        assert abs(vals[0][k] - ref[k]) <= EPS * abs(ref[k])
+    say("iteration cap")
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(s).to(dev), fj.make_opts(max_iter=1), check=False)
+    assert rc == fj.FJ_ERR_NOT_CONVERGED and infos[0].iters == 1
+    say("workspace too small")
+    ws = torch.empty(1024, dtype=torch.uint8, device=dev)
+    _, _, rc = fj.fj_indices(G, torch.from_numpy(s).to(dev), ws=ws, check=False)
+    assert rc == fj.FJ_ERR_WORKSPACE
+    say("invalid graphs")
+    for rp, col in (([0, 1, 1, 1], [1]),            # asymmetric
+                    ([0, 1, 2, 2], [0, 0]),         # self-loop
+                    ([0, 1, 2, 2], [5, 0])):        # column out of range
+        bad_g = W.CSRGraph(n=3, row_ptr=np.array(rp, np.int32), col=np.array(col, np.int32))
+        with pytest.raises(fj.FJError) as e:
+            fj.Graph.from_csr(bad_g, device=dev)
+        assert e.value.status == fj.FJ_ERR_INVALID_GRAPH
+
+
+# ---------------------------------------------------------------- full sizes
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["ba10k", "cl1m", "cl4m"])
+def test_full_size_workloads(torch_fj, name):
+    """The configured workloads at full size: all five indices within 1e-6 of
+    the oracle, the reported bounds valid, and z elementwise within the
+    certified residual."""
+    torch, fj = torch_fj
+    g, s, spec = W.workload(name)
+    say(f"full {name} n={g.n} nnz={g.nnz}")
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    opts = fj.make_opts(eps=EPS, rtol=spec["rtol"])
+    sd = torch.from_numpy(s).to("cuda:0")
+    vals, infos, rc = fj.fj_indices(G, sd, opts, check=False)
+    assert rc == fj.FJ_OK, fj.info_dict(infos[0])
+    say(f"oracle {name}")
+    ref, zref, oinfo = O.indices(g, s)
+    assert oinfo["certified"], oinfo
+    for c, k in enumerate(NAMES):
+        err = abs(vals[0][k] - ref[k]) / abs(ref[k])
+        assert err <= EPS, (k, err)
+        assert err <= infos[0].bound[c] + 1e-12
+    z, zinfo, rc = fj.fj_solve(G, sd, opts)
+    assert rc == fj.FJ_OK
+    diff = np.linalg.norm(z.cpu().numpy() - zref)
+    assert diff <= (zinfo[0].rel_residual + 1e-13) * np.linalg.norm(s)
+    del G
+    torch.cuda.empty_cache()
