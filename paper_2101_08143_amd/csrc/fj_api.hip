@@ -1,7 +1,10 @@
 // fj_api.hip -- the extern "C" entry points of libfjgpu (declared in include/fj.h).
 //
 // Host side of the hot path: argument checks, plan and workspace carving,
-// kernel launches on the caller's stream, and the CG driver. The driver
+// kernel launches on the caller's stream, and the CG driver. One CG
+// iteration is four launches: the SpMV with its dot products, a one-workgroup
+// kernel that forms alpha and beta, the fused vector update, and a
+// one-workgroup kernel that forms the new residual norms. The driver
 // enqueues CG iterations in chunks and copies the 1 KiB control block to
 // pinned host memory after each chunk; while the GPU runs one chunk the host
 // reads the status of the previous one and, from the residual history,
@@ -54,6 +57,7 @@ void set_error(const char* what, hipError_t e) {
 struct PlanLayout {
     int K;            // number of row windows
     size_t blk_row;   // int[K + 1]
+    size_t desc;      // WinDesc[K]
     size_t minv;      // float[n]
     size_t flags;     // int[64] scratch for validation
     size_t total;
@@ -66,6 +70,8 @@ PlanLayout plan_layout(const fj_csr* g) {
     size_t off = 0;
     L.blk_row = off;
     off = align_up(off + sizeof(int) * (static_cast<size_t>(L.K) + 1));
+    L.desc = off;
+    off = align_up(off + sizeof(WinDesc) * static_cast<size_t>(L.K));
     L.minv = off;
     off = align_up(off + sizeof(float) * static_cast<size_t>(g->n));
     L.flags = off;
@@ -165,11 +171,11 @@ template <typename F>
 int with_graph(const fj_csr* g, F&& f) {
     switch (g->val_type) {
         case FJ_VAL_UNIT:
-            return f(Csr<Unit>{g->n, g->row_ptr, g->col_idx, nullptr});
+            return f(Csr<Unit>{g->n, static_cast<int>(g->nnz), g->row_ptr, g->col_idx, nullptr});
         case FJ_VAL_F32:
-            return f(Csr<float>{g->n, g->row_ptr, g->col_idx, static_cast<const float*>(g->val)});
+            return f(Csr<float>{g->n, static_cast<int>(g->nnz), g->row_ptr, g->col_idx, static_cast<const float*>(g->val)});
         case FJ_VAL_F64:
-            return f(Csr<double>{g->n, g->row_ptr, g->col_idx, static_cast<const double*>(g->val)});
+            return f(Csr<double>{g->n, static_cast<int>(g->nnz), g->row_ptr, g->col_idx, static_cast<const double*>(g->val)});
         default:
             return FJ_ERR_INVALID_ARG;
     }
@@ -230,7 +236,7 @@ struct Solver {
     double* q() const { return reinterpret_cast<double*>(ws + wl.q); }
     double* part() const { return reinterpret_cast<double*>(ws + wl.part); }
     Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + wl.ctrl); }
-    const int* blk_row() const { return reinterpret_cast<const int*>(plan + pl.blk_row); }
+    const WinDesc* desc() const { return reinterpret_cast<const WinDesc*>(plan + pl.desc); }
     const float* minv() const { return reinterpret_cast<const float*>(plan + pl.minv); }
 
     int setup() {
@@ -247,8 +253,10 @@ struct Solver {
             k_ctrl_reset<<<1, WG, 0, st>>>(ctrl(), 1);
             HIPCHK(hipGetLastError());
         }
-        k_cg_init<<<grid_vec, WG, 0, st>>>(g->n, s, lds, x(), r(), p(), minv(), mode, rtol * rtol, max_iter,
-                                           range_check ? 1 : 0, part(), ctrl());
+        k_cg_init<<<grid_vec, WG, 0, st>>>(g->n, s, lds, x(), r(), p(), minv(), mode, part());
+        HIPCHK(hipGetLastError());
+        k_fin_init<<<1, WG, 0, st>>>(grid_vec, g->n, part(), mode, rtol * rtol, max_iter, range_check ? 1 : 0,
+                                     ctrl());
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
@@ -260,7 +268,7 @@ struct Solver {
                 if (int e = profile_events(*hs, n_prof + 1)) return e;
                 HIPCHK(hipEventRecord(hs->prof[2 * n_prof], st));
             }
-            k_cg_spmv<Vc><<<grid_win, WG, 0, st>>>(G, blk_row(), pl.K, p(), r(), minv(), q(), part(), ctrl());
+            k_cg_spmv<Vc><<<grid_win, WG, 0, st>>>(G, desc(), pl.K, p(), r(), minv(), q(), part(), ctrl());
             HIPCHK(hipGetLastError());
             if (profile) {
                 HIPCHK(hipEventRecord(hs->prof[2 * n_prof + 1], st));
@@ -269,7 +277,11 @@ struct Solver {
             return FJ_OK;
         });
         if (rc) return rc;
+        k_fin_spmv<<<1, WG, 0, st>>>(grid_win, part(), ctrl());
+        HIPCHK(hipGetLastError());
         k_cg_update<<<grid_vec, WG, 0, st>>>(g->n, x(), r(), p(), q(), minv(), part(), ctrl());
+        HIPCHK(hipGetLastError());
+        k_fin_update<<<1, WG, 0, st>>>(grid_vec, part(), ctrl());
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
@@ -339,11 +351,13 @@ struct Solver {
     int epilogue(const double* s, int64_t lds, Ctrl* out) {
         int rc = with_graph(g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
-            k_epilogue<Vc><<<grid_win, WG, 0, st>>>(G, blk_row(), pl.K, x(), s, lds, r(), part(), ctrl());
+            k_epilogue<Vc><<<grid_win, WG, 0, st>>>(G, desc(), pl.K, x(), s, lds, r(), part(), ctrl());
             HIPCHK(hipGetLastError());
             return FJ_OK;
         });
         if (rc) return rc;
+        k_fin_epilogue<<<1, WG, 0, st>>>(grid_win, g->n, part(), ctrl());
+        HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&hs->h[NSLOT], ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         std::memcpy(out, &hs->h[NSLOT], sizeof(Ctrl));
@@ -510,6 +524,7 @@ int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_byt
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* P = static_cast<char*>(plan);
     int* blk_row = reinterpret_cast<int*>(P + pl.blk_row);
+    WinDesc* desc = reinterpret_cast<WinDesc*>(P + pl.desc);
     float* minv = reinterpret_cast<float*>(P + pl.minv);
     int* flags = reinterpret_cast<int*>(P + pl.flags);
     if (g->n == 0) return FJ_OK;
@@ -536,12 +551,14 @@ int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_byt
         const int grid = static_cast<int>(std::min<int64_t>((pl.K + 1 + WG - 1) / WG, 4096));
         k_windows<<<grid, WG, 0, st>>>(g->n, g->row_ptr, pl.K, blk_row);
         HIPCHK(hipGetLastError());
+        k_window_desc<<<grid, WG, 0, st>>>(g->n, g->row_ptr, pl.K, blk_row, desc);
+        HIPCHK(hipGetLastError());
     }
     return with_graph(g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
         int grid = 1;
         if (int rc = grid_for(k_diag<Vc>, pl.K, &grid)) return rc;
-        k_diag<Vc><<<grid, WG, 0, st>>>(G, blk_row, pl.K, minv);
+        k_diag<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, minv);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     });
@@ -553,13 +570,13 @@ int fj_apply(const fj_csr* g, const void* plan, const double* x, double* y, void
     if (g->n == 0) return FJ_OK;
     if (!x || !y || x == y) return FJ_ERR_INVALID_ARG;
     const PlanLayout pl = plan_layout(g);
-    const int* blk_row = reinterpret_cast<const int*>(static_cast<const char*>(plan) + pl.blk_row);
+    const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(plan) + pl.desc);
     hipStream_t st = static_cast<hipStream_t>(stream);
     return with_graph(g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
         int grid = 1;
         if (int rc = grid_for(k_apply<Vc>, pl.K, &grid)) return rc;
-        k_apply<Vc><<<grid, WG, 0, st>>>(G, blk_row, pl.K, x, y);
+        k_apply<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, x, y);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     });

@@ -29,19 +29,23 @@ namespace fj {
 
 constexpr int WG = 256;               // threads per workgroup: four wave64
 constexpr int NWAVE = WG / 64;
-constexpr int WIN = 1024;             // window width in (rows + entries)
-constexpr int LONGROW = 512;          // a longer last row takes the workgroup-wide path
+#ifndef FJ_WIN
+#define FJ_WIN 1024
+#endif
+constexpr int WIN = FJ_WIN;           // window width in (rows + entries)
+constexpr int LONGROW = WIN / 2;      // a longer last row takes the workgroup-wide path
 constexpr int STAGE = WIN + LONGROW;  // LDS staging capacity in entries
 constexpr int STAGE_PER_THREAD = STAGE / WG;
 constexpr int ROWS_PER_THREAD = WIN / WG;
+constexpr int LONG_UNROLL = 8;        // loads in flight per thread on a long row
 constexpr int NPART = 16;             // sums per workgroup in the partials buffer
 constexpr int GMAX = 4096;            // largest persistent grid
 constexpr int HIST = 64;              // residual history slots
 
 static_assert(STAGE % WG == 0 && WIN % WG == 0, "window sizes must be multiples of the workgroup");
 
-// Control block in the workspace. Written only by the last workgroup of a
-// kernel; read by later kernels (kernel boundaries order the accesses) and
+// Control block in the workspace. Written only by the one-workgroup finalize
+// kernels; read by later kernels (kernel boundaries order the accesses) and
 // copied to the host between CG chunks.
 struct Ctrl {
     double alpha, beta;   // CG step length and direction update of this iteration
@@ -55,9 +59,8 @@ struct Ctrl {
     int32_t done;         // 0 running, 1 converged, 2 iteration cap, 3 breakdown, 4 bad input
     int32_t iters;        // CG iterations so far (all passes)
     int32_t max_iter;
-    int32_t bad;          // bit 0: NaN in s, bit 1: s outside [0,1]
-    uint32_t ticket;      // arrival counter of the last-workgroup reduction
-    int32_t pad[3];
+    int32_t bad;          // 2 when some s_i is NaN or outside [0,1]
+    int32_t pad[4];
 };
 
 enum Done : int32_t { RUNNING = 0, CONVERGED = 1, ITER_CAP = 2, BREAKDOWN = 3, BAD_INPUT = 4 };
@@ -68,6 +71,7 @@ template <typename V>
 struct Csr {
     using value_type = V;
     int n;
+    int nnz;
     const int* __restrict__ row_ptr;
     const int* __restrict__ col;
     const V* __restrict__ val;
@@ -122,39 +126,30 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
     __syncthreads();
 }
 
-__device__ __forceinline__ double load_coherent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Each workgroup publishes its N sums; the last workgroup to arrive adds all
-// of them in workgroup order and returns true with the grand totals in v.
-// Every thread of every workgroup must call it (it synchronises).
+// Workgroup partial sums go to part[blockIdx.x * NPART + c]; a one-workgroup
+// finalize kernel adds them up in workgroup order. Publishing through a
+// kernel boundary needs no cross-workgroup fence inside the kernel.
 template <int N>
-__device__ bool last_block_total(double (&v)[N], double* __restrict__ part, Ctrl* ctrl,
-                                 double* red, int* flag) {
+__device__ __forceinline__ void store_partials(const double (&v)[N], double* __restrict__ part) {
     static_assert(N <= NPART, "too many partial sums");
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < N; ++c) part[blockIdx.x * NPART + c] = v[c];
-        __threadfence();
-        const uint32_t t = atomicAdd(&ctrl->ticket, 1u);
-        *flag = (t == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!*flag) return false;
-    __threadfence();
-    double acc[N];
+}
+
+// Totals of N partial sums over G workgroups, in workgroup order, for a
+// finalize kernel (one workgroup). Every thread receives the totals.
+template <int N>
+__device__ __forceinline__ void total_partials(int G, const double* __restrict__ part, double (&v)[N],
+                                               double* red) {
 #pragma unroll
-    for (int c = 0; c < N; ++c) acc[c] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += WG) {
+    for (int c = 0; c < N; ++c) v[c] = 0.0;
+    for (int b = threadIdx.x; b < G; b += WG) {
 #pragma unroll
-        for (int c = 0; c < N; ++c) acc[c] += load_coherent(&part[b * NPART + c]);
+        for (int c = 0; c < N; ++c) v[c] += part[b * NPART + c];
     }
-    block_sum<N>(acc, red);
-#pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = acc[c];
-    if (threadIdx.x == 0) ctrl->ticket = 0u;
-    return true;
+    block_sum<N>(v, red);
 }
 
 // ------------------------------------------------------------ window pass
@@ -164,147 +159,381 @@ struct AccLin   { static constexpr bool X = true,  SQ = false, DEG = false; };  
 struct AccLinSq { static constexpr bool X = true,  SQ = true,  DEG = false; };  // sum w d, sum w d^2
 struct AccDeg   { static constexpr bool X = false, SQ = false, DEG = true;  };  // sum w
 
-template <typename T, typename V>
+// Entry slot STAGE - 1 and row slot WIN are never read: a window stages at
+// most STAGE - 1 entries and WIN rows. Lanes with nothing to stage write
+// there, so that every lane executes the same stores (no load is ever moved
+// into a predicated block, which would stall the pipeline below).
+template <typename T, typename V, typename In>
 struct Stage {
-    T x[STAGE];
-    V w[STAGE];
+    T x[STAGE];          // x_j of every staged entry
+    V w[STAGE];          // w_ij of every staged entry
+    T xrow[WIN + 1];     // x_i of every row of the window
+    int rend[WIN + 1];   // end of each row, relative to the window's first entry
+    In rin[WIN + 1];     // the operation's per-row inputs
+    int crow[WG];        // row a thread's item range ends inside of (-1: none)
+    double clin[WG];     // that row's partial sums from the thread
+    double csq[WG];
 };
-template <typename T>
-struct Stage<T, Unit> {
+template <typename T, typename In>
+struct Stage<T, Unit, In> {
     T x[STAGE];
+    T xrow[WIN + 1];
+    int rend[WIN + 1];
+    In rin[WIN + 1];
+    int crow[WG];
+    double clin[WG];
+    double csq[WG];
 };
 
+// Row window k, precomputed by fj_prepare (k_window_desc). Window k holds the
+// rows whose key row_ptr[i] + i lies in [k*WIN, (k+1)*WIN).
+struct WinDesc {
+    int r0, r1;     // rows [r0, r1)
+    int e0;         // row_ptr[r0]
+    int elast;      // row_ptr[r1 - 1] (e0 for an empty window)
+    int eend;       // row_ptr[r1]
+    int nrs;        // rows walked from LDS: r1 - r0, less a long last row
+    int ns;         // entries of those rows (< STAGE)
+    int long_last;  // 1 when the last row has more than LONGROW entries
+};
+static_assert(sizeof(WinDesc) == 32, "WinDesc is two 16-byte loads");
+
+template <typename P>
+__device__ __forceinline__ P stream_load(const P* p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <typename V> struct WeightReg { using type = V; };
+template <> struct WeightReg<Unit> { using type = float; };  // unused placeholder
+
+// Registers holding one window's staged entries: column indices and weights.
+template <typename V>
+struct EntryRegs {
+    int j[STAGE_PER_THREAD];
+    typename WeightReg<V>::type w[STAGE_PER_THREAD];
+};
+
+// Streaming loads of a window's col (and val) into registers. Every lane
+// issues the same loads, so the compiler can keep them in flight: a lane past
+// the window's entries re-reads the window's last entry (a line already being
+// fetched) and records column 0, so its gather below touches one hot line
+// shared by all such lanes instead of a random one.
+template <typename V>
+__device__ __forceinline__ void load_entries(const Csr<V>& g, const WinDesc& d, int last_e, EntryRegs<V>& R) {
+    const int elim = min(d.e0 + max(d.ns, 1) - 1, last_e);
+#pragma unroll
+    for (int u = 0; u < STAGE_PER_THREAD; ++u) {
+        const int e = static_cast<int>(threadIdx.x) + u * WG;
+        const int idx = min(d.e0 + e, elim);
+        const int c = stream_load(&g.col[idx]);
+        R.j[u] = e < d.ns ? c : 0;
+        if constexpr (!std::is_same<V, Unit>::value) R.w[u] = stream_load(&g.val[idx]);
+    }
+}
+
+// Reduce one window whose entries, row ends, own values and per-row inputs
+// are staged in LDS: calls op.row(i, x_i, sum_j w_ij (x_i - x_j),
+// sum_j w_ij (x_i - x_j)^2, in_i) exactly once for every row of the window,
+// from a thread fixed by the data layout (so per-thread partial sums are
+// reproducible).
+//
+// Rows other than a long last row are reduced by a merge-path walk: the
+// window's row ends and entries form one ordered list of items (each row's
+// entries, then its end marker), and thread t walks items
+// [t*ipt, (t+1)*ipt). A row finished inside one thread is emitted at once; a
+// row that began in earlier threads is emitted by the thread holding its end,
+// after adding the partial sums those threads left behind, in thread order.
+// Every thread therefore handles at most ceil(items / WG) items, whatever the
+// row lengths. A long last row is reduced by the whole workgroup from HBM.
 template <typename T, typename V, typename Acc, typename Op>
-__device__ __forceinline__ void window_pass(const Csr<V>& g, const int* __restrict__ blk_row, int k,
-                                            const T* __restrict__ x, Op& op, Stage<T, V>& st,
-                                            double* red) {
+__device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d, const T* __restrict__ x,
+                                              Op& op, Stage<T, V, typename Op::In>& st, double* red) {
+    constexpr bool WEIGHTED = !std::is_same<V, Unit>::value;
     const int tid = threadIdx.x;
-    const int r0 = blk_row[k];
-    const int r1 = blk_row[k + 1];
-    if (r0 >= r1) return;  // workgroup-uniform: an empty window
-    const int e0 = g.row_ptr[r0];
-    const int elast = g.row_ptr[r1 - 1];
-    const int eend = g.row_ptr[r1];
-    const bool long_last = (eend - elast) > LONGROW;
-    const int rs_end = long_last ? r1 - 1 : r1;
-    const int ns = (long_last ? elast : eend) - e0;  // < STAGE by construction of the windows
-
-    // Phase 1: coalesced loads of col (and val), gathers of x_j, into LDS.
-    if constexpr (Acc::X || !std::is_same<V, Unit>::value) {
-        int jj[STAGE_PER_THREAD];
-#pragma unroll
-        for (int u = 0; u < STAGE_PER_THREAD; ++u) {
-            const int e = tid + u * WG;
-            jj[u] = (e < ns) ? g.col[e0 + e] : 0;
-        }
-        if constexpr (Acc::X) {
-            T xv[STAGE_PER_THREAD];
-#pragma unroll
-            for (int u = 0; u < STAGE_PER_THREAD; ++u) {
-                const int e = tid + u * WG;
-                if (e < ns) xv[u] = x[jj[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < STAGE_PER_THREAD; ++u) {
-                const int e = tid + u * WG;
-                if (e < ns) st.x[e] = xv[u];
-            }
-        }
-        if constexpr (!std::is_same<V, Unit>::value) {
-#pragma unroll
-            for (int u = 0; u < STAGE_PER_THREAD; ++u) {
-                const int e = tid + u * WG;
-                if (e < ns) st.w[e] = g.val[e0 + e];
-            }
-        }
-        __syncthreads();
+    const int nrs = d.nrs, ns = d.ns;
+    const int total = nrs + ns;
+    const int ipt = (total + WG - 1) / WG;
+    const int d0 = min(tid * ipt, total);
+    const int d1 = min(d0 + ipt, total);
+    int lo = 0, hi = nrs;
+    while (lo < hi) {  // a0 = number of row ends before item d0 (row a's end is item rend[a] + a)
+        const int mid = (lo + hi) >> 1;
+        if (st.rend[mid] + mid < d0) lo = mid + 1;
+        else hi = mid;
     }
-
-    // Phase 2: one thread per row, reduced from LDS.
-#pragma unroll
-    for (int u = 0; u < ROWS_PER_THREAD; ++u) {
-        const int i = r0 + tid + u * WG;
-        if (i < rs_end) {
-            const int a = g.row_ptr[i] - e0;
-            const int b = min(g.row_ptr[i + 1] - e0, STAGE);  // the min only guards malformed input
-            const T xi = Acc::X ? x[i] : T(0);
-            double lin = 0.0, sq = 0.0;
-            if constexpr (Acc::DEG && std::is_same<V, Unit>::value) {
-                lin = static_cast<double>(b - a);
-            } else {
-                for (int e = a; e < b; ++e) {
-                    double w = 1.0;
-                    if constexpr (!std::is_same<V, Unit>::value) w = static_cast<double>(st.w[e]);
-                    if constexpr (Acc::DEG) {
-                        lin += w;
-                    } else {
-                        const double d = static_cast<double>(xi) - static_cast<double>(st.x[e]);
-                        lin += w * d;
-                        if constexpr (Acc::SQ) sq += w * d * d;
-                    }
-                }
-            }
-            op.row(i, xi, lin, sq);
-        }
-    }
-
-    // Phase 3: a long last row, reduced by the whole workgroup from HBM.
-    if (long_last) {
-        const int i = r1 - 1;
-        const T xi = Acc::X ? x[i] : T(0);
-        double v[2] = {0.0, 0.0};
-        for (int e = elast + tid; e < eend; e += WG) {
-            const double w = weight_at<V>(g.val, e);
+    const int a0 = lo;
+    int a = a0;
+    int j = d0 - a0;
+    const bool continued = (d0 < d1) && (j > (a0 > 0 ? st.rend[a0 - 1] : 0));
+    int row_end = (a < nrs) ? st.rend[a] : 0;
+    double xa = (Acc::X && a < nrs) ? static_cast<double>(st.xrow[a]) : 0.0;
+    double lin = 0.0, sq = 0.0, first_lin = 0.0, first_sq = 0.0;
+    bool first_pending = false, open = false;
+    for (int dd = d0; dd < d1; ++dd) {
+        if (j < row_end) {  // entry j of row a
+            double w = 1.0;
+            if constexpr (WEIGHTED) w = static_cast<double>(st.w[j]);
             if constexpr (Acc::DEG) {
-                v[0] += w;
+                lin += w;
             } else {
-                const double d = static_cast<double>(xi) - static_cast<double>(x[g.col[e]]);
-                v[0] += w * d;
-                if constexpr (Acc::SQ) v[1] += w * d * d;
+                const double diff = xa - static_cast<double>(st.x[j]);
+                lin += w * diff;
+                if constexpr (Acc::SQ) sq += w * diff * diff;
+            }
+            ++j;
+            open = true;
+        } else {  // end of row a
+            if (a == a0 && continued) {
+                first_pending = true;
+                first_lin = lin;
+                first_sq = sq;
+            } else {
+                op.row(d.r0 + a, static_cast<T>(xa), lin, sq, st.rin[a]);
+            }
+            lin = 0.0;
+            sq = 0.0;
+            open = false;
+            ++a;
+            if (a < nrs) {
+                row_end = st.rend[a];
+                if constexpr (Acc::X) xa = static_cast<double>(st.xrow[a]);
+            }
+        }
+    }
+    st.crow[tid] = open ? a : -1;
+    st.clin[tid] = lin;
+    st.csq[tid] = sq;
+    __syncthreads();
+    if (first_pending) {
+        double L = first_lin, S = first_sq;
+        for (int t = tid - 1; t >= 0 && st.crow[t] == a0; --t) {
+            L += st.clin[t];
+            S += st.csq[t];
+        }
+        op.row(d.r0 + a0, st.xrow[a0], L, S, st.rin[a0]);
+    }
+
+    if (d.long_last) {
+        const T xi_t = st.xrow[nrs];
+        const double xi = Acc::X ? static_cast<double>(xi_t) : 0.0;
+        double v[2] = {0.0, 0.0};
+        for (int base = d.elast + tid; base < d.eend; base += WG * LONG_UNROLL) {
+            int jj[LONG_UNROLL];
+            double ww[LONG_UNROLL];
+#pragma unroll
+            for (int u = 0; u < LONG_UNROLL; ++u) {  // clamped, unconditional loads
+                const int e = base + u * WG;
+                const int ec = min(e, d.eend - 1);
+                jj[u] = stream_load(&g.col[ec]);
+                double w = 1.0;
+                if constexpr (WEIGHTED) w = static_cast<double>(stream_load(&g.val[ec]));
+                ww[u] = (e < d.eend) ? w : 0.0;
+            }
+            if constexpr (Acc::DEG) {
+#pragma unroll
+                for (int u = 0; u < LONG_UNROLL; ++u) v[0] += ww[u];
+            } else {
+                double xv[LONG_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LONG_UNROLL; ++u) xv[u] = static_cast<double>(x[jj[u]]);
+#pragma unroll
+                for (int u = 0; u < LONG_UNROLL; ++u) {
+                    const double diff = xi - xv[u];
+                    v[0] += ww[u] * diff;
+                    if constexpr (Acc::SQ) v[1] += ww[u] * diff * diff;
+                }
             }
         }
         block_sum<2>(v, red);
-        if (tid == 0) op.row(i, xi, v[0], v[1]);
+        if (tid == 0) op.row(d.r1 - 1, xi_t, v[0], v[1], st.rin[nrs]);
     }
-    __syncthreads();  // LDS is reused by the next window
+}
+
+// Window descriptors are loaded into vector registers and moved to scalar
+// registers (the window index is uniform across the workgroup) only when the
+// window comes up, so no load has to complete early.
+struct RawDesc {
+    int4 lo, hi;
+};
+__device__ __forceinline__ RawDesc load_raw_desc(const WinDesc* __restrict__ p) {
+    return RawDesc{reinterpret_cast<const int4*>(p)[0], reinterpret_cast<const int4*>(p)[1]};
+}
+__device__ __forceinline__ WinDesc to_scalar(const RawDesc& r) {
+    WinDesc d;
+    d.r0 = __builtin_amdgcn_readfirstlane(r.lo.x);
+    d.r1 = __builtin_amdgcn_readfirstlane(r.lo.y);
+    d.e0 = __builtin_amdgcn_readfirstlane(r.lo.z);
+    d.elast = __builtin_amdgcn_readfirstlane(r.lo.w);
+    d.eend = __builtin_amdgcn_readfirstlane(r.hi.x);
+    d.nrs = __builtin_amdgcn_readfirstlane(r.hi.y);
+    d.ns = __builtin_amdgcn_readfirstlane(r.hi.z);
+    d.long_last = __builtin_amdgcn_readfirstlane(r.hi.w);
+    return d;
+}
+
+// Loads of one window that the reduction needs in registers: the gathered
+// x_j and the weights of its staged entries, and the row ends, own values and
+// per-row inputs of its rows (row a of a window is loaded by thread a % WG).
+template <typename T, typename V, typename In>
+struct WindowRegs {
+    T xv[STAGE_PER_THREAD];
+    typename WeightReg<V>::type w[STAGE_PER_THREAD];
+    int re[ROWS_PER_THREAD];
+    T xr[ROWS_PER_THREAD];
+    In in[ROWS_PER_THREAD];
+};
+
+// The windows k0, k0 + G, k0 + 2G, ... (k0 = blockIdx.x, G = gridDim.x) of one
+// workgroup, software-pipelined three deep: while window t is staged and
+// reduced, the gathers and row loads of window t+1, the col/val loads of
+// window t+2 and the descriptor of window t+3 are in flight, so the reduction
+// never waits on memory it did not ask for a whole window earlier. Striding
+// by G spreads the costly windows (hub rows) evenly over the workgroups.
+// All loads and LDS stores are unconditional (clamped to valid addresses and
+// dummy slots) so that the loads stay in flight across the loop body.
+// ENTRIES is false only for a graph without edges, whose col/val may be null.
+template <typename T, typename V, typename Acc, bool ENTRIES, typename Op>
+__device__ __forceinline__ void window_range(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
+                                             const T* __restrict__ x, Op& op,
+                                             Stage<T, V, typename Op::In>& st, double* red) {
+    constexpr bool WEIGHTED = !std::is_same<V, Unit>::value;
+    constexpr bool LOADS = ENTRIES && (Acc::X || WEIGHTED);
+    using In = typename Op::In;
+    const int G = gridDim.x;
+    const int k0 = blockIdx.x;
+    if (k0 >= K) return;
+    const int tid = threadIdx.x;
+    const int last_e = g.nnz > 0 ? g.nnz - 1 : 0;
+    const int klast = k0 + (K - 1 - k0) / G * G;  // this workgroup's last window
+
+    auto issue_window = [&](const WinDesc& d, const EntryRegs<V>& E, WindowRegs<T, V, In>& W) {
+        if constexpr (Acc::X) {
+#pragma unroll
+            for (int u = 0; u < STAGE_PER_THREAD; ++u) W.xv[u] = x[E.j[u]];
+        }
+        if constexpr (WEIGHTED) {
+#pragma unroll
+            for (int u = 0; u < STAGE_PER_THREAD; ++u) W.w[u] = E.w[u];
+        }
+        const int ilim = min(max(d.r1 - 1, d.r0), g.n - 1);  // lanes past the rows re-read the last one
+#pragma unroll
+        for (int u = 0; u < ROWS_PER_THREAD; ++u) {
+            const int i = min(d.r0 + tid + u * WG, ilim);
+            W.re[u] = g.row_ptr[i + 1];
+            if constexpr (Acc::X) W.xr[u] = x[i];
+            W.in[u] = op.load(i);
+        }
+    };
+
+    WinDesc d_cur = to_scalar(load_raw_desc(desc + k0));
+    WinDesc d_nxt = to_scalar(load_raw_desc(desc + min(k0 + G, klast)));
+    WinDesc d_nn = to_scalar(load_raw_desc(desc + min(k0 + 2 * G, klast)));
+    EntryRegs<V> E{};
+    if constexpr (LOADS) load_entries(g, d_cur, last_e, E);
+    WindowRegs<T, V, In> Wc;
+    issue_window(d_cur, E, Wc);
+    EntryRegs<V> En = E;
+    if constexpr (LOADS) load_entries(g, d_nxt, last_e, En);
+
+    for (int k = k0; k < K; k += G) {
+        const RawDesc a3 = load_raw_desc(desc + min(k + 3 * G, klast));
+        // window t+1: gathers and row loads; window t+2: col/val loads
+        WindowRegs<T, V, In> Wn;
+        issue_window(d_nxt, En, Wn);
+        EntryRegs<V> Enn = En;
+        if constexpr (LOADS) load_entries(g, d_nn, last_e, Enn);
+        // stage window t
+        const int nrows = d_cur.r1 - d_cur.r0;
+#pragma unroll
+        for (int u = 0; u < STAGE_PER_THREAD; ++u) {
+            const int e = tid + u * WG;
+            const int slot = e < d_cur.ns ? e : STAGE - 1;
+            if constexpr (Acc::X) st.x[slot] = Wc.xv[u];
+            if constexpr (WEIGHTED) st.w[slot] = Wc.w[u];
+        }
+#pragma unroll
+        for (int u = 0; u < ROWS_PER_THREAD; ++u) {
+            const int a = tid + u * WG;
+            const int slot = a < nrows ? a : WIN;
+            st.rend[slot] = Wc.re[u] - d_cur.e0;
+            if constexpr (Acc::X) st.xrow[slot] = Wc.xr[u];
+            st.rin[slot] = Wc.in[u];
+        }
+        __syncthreads();
+        if (nrows > 0) window_reduce<T, V, Acc>(g, d_cur, x, op, st, red);
+        __syncthreads();  // LDS is reused by the next window
+        d_cur = d_nxt;
+        d_nxt = d_nn;
+        d_nn = to_scalar(a3);
+        Wc = Wn;
+        En = Enn;
+    }
+}
+
+template <typename T, typename V, typename Acc, typename Op>
+__device__ __forceinline__ void my_windows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
+                                           const T* __restrict__ x, Op& op,
+                                           Stage<T, V, typename Op::In>& st, double* red) {
+    if (g.nnz > 0) window_range<T, V, Acc, true>(g, desc, K, x, op, st, red);
+    else window_range<T, V, Acc, false>(g, desc, K, x, op, st, red);
 }
 
 // ------------------------------------------------------------ row operations
+// Each operation names the per-row inputs it needs (In, fetched by load(i)
+// with the window's other loads) and finishes row i in row(i, x_i, lin, sq, in)
+// with lin = ((L x)_i) and sq = sum_j w_ij (x_i - x_j)^2.
+
+struct NoIn {
+    char unused;
+};
 
 struct OpDiag {  // Jacobi preconditioner M^{-1} = diag(1 + d_i)^{-1}
+    using In = NoIn;
     float* __restrict__ minv;
+    __device__ In load(int) const { return {}; }
     template <typename T>
-    __device__ void row(int i, T, double deg, double) { minv[i] = static_cast<float>(1.0 / (1.0 + deg)); }
+    __device__ void row(int i, T, double deg, double, const In&) { minv[i] = static_cast<float>(1.0 / (1.0 + deg)); }
 };
 
 struct OpApply {  // y = (I + L) x
+    using In = NoIn;
     double* __restrict__ y;
-    __device__ void row(int i, double xi, double lin, double) { y[i] = xi + lin; }
+    __device__ In load(int) const { return {}; }
+    __device__ void row(int i, double xi, double lin, double, const In&) { y[i] = xi + lin; }
 };
 
 struct OpCgSpmv {  // q = (I + L) p and the three dot products the CG scalars need
+    struct In {
+        double r;
+        float m;
+    };
     const double* __restrict__ r;
     const float* __restrict__ minv;
     double* __restrict__ q;
     double pq = 0.0, rmq = 0.0, qmq = 0.0;
-    __device__ void row(int i, double pi, double lin, double) {
+    __device__ In load(int i) const { return {r[i], minv[i]}; }
+    __device__ void row(int i, double pi, double lin, double, const In& in) {
         const double qi = pi + lin;
         q[i] = qi;
-        const double mq = static_cast<double>(minv[i]) * qi;
+        const double mq = static_cast<double>(in.m) * qi;
         pq += pi * qi;
-        rmq += r[i] * mq;
+        rmq += in.r * mq;
         qmq += qi * mq;
     }
 };
 
 struct OpEpilogue {  // one pass over z: every index, the true residual and diagnostics
+    struct In {
+        double s;
+    };
     const double* __restrict__ s;
     int64_t lds;
     double mu;
     double* __restrict__ rbuf;
     double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    __device__ void row(int i, double zi, double t, double dsq) {
-        const double si = s[static_cast<int64_t>(i) * lds];
+    __device__ In load(int i) const { return {s[static_cast<int64_t>(i) * lds]}; }
+    __device__ void row(int i, double zi, double t, double dsq, const In& in) {
+        const double si = in.s;
         const double ri = si - zi - t;  // t = (L z)_i, so r = s - (I + L) z
         rbuf[i] = ri;
         const double dm = zi - mu;
@@ -338,47 +567,69 @@ __global__ void __launch_bounds__(WG) k_windows(int n, const int* __restrict__ r
     }
 }
 
+__global__ void __launch_bounds__(WG) k_window_desc(int n, const int* __restrict__ row_ptr, int K,
+                                                    const int* __restrict__ blk_row, WinDesc* __restrict__ desc) {
+    for (int k = blockIdx.x * WG + threadIdx.x; k < K; k += gridDim.x * WG) {
+        WinDesc d;
+        d.r0 = blk_row[k];
+        d.r1 = blk_row[k + 1];
+        d.e0 = row_ptr[d.r0];
+        d.eend = row_ptr[d.r1];
+        d.elast = d.r1 > d.r0 ? row_ptr[d.r1 - 1] : d.e0;
+        d.long_last = (d.r1 > d.r0) && (d.eend - d.elast > LONGROW);
+        d.nrs = d.r1 - d.r0 - d.long_last;
+        d.ns = (d.long_last ? d.elast : d.eend) - d.e0;
+        desc[k] = d;
+    }
+}
+
 template <typename V>
-__global__ void __launch_bounds__(WG) k_diag(Csr<V> g, const int* __restrict__ blk_row, int K,
+__global__ void __launch_bounds__(WG) k_diag(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                              float* __restrict__ minv) {
-    __shared__ Stage<double, V> st;
+    __shared__ Stage<double, V, OpDiag::In> st;
     __shared__ double red[NWAVE * 2];
     OpDiag op{minv};
-    for (int k = blockIdx.x; k < K; k += gridDim.x)
-        window_pass<double, V, AccDeg>(g, blk_row, k, static_cast<const double*>(nullptr), op, st, red);
+    my_windows<double, V, AccDeg>(g, desc, K, static_cast<const double*>(nullptr), op, st, red);
 }
 
 template <typename V>
-__global__ void __launch_bounds__(WG) k_apply(Csr<V> g, const int* __restrict__ blk_row, int K,
+__global__ void __launch_bounds__(WG) k_apply(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                               const double* __restrict__ x, double* __restrict__ y) {
-    __shared__ Stage<double, V> st;
+    __shared__ Stage<double, V, OpApply::In> st;
     __shared__ double red[NWAVE * 2];
     OpApply op{y};
-    for (int k = blockIdx.x; k < K; k += gridDim.x)
-        window_pass<double, V, AccLin>(g, blk_row, k, x, op, st, red);
+    my_windows<double, V, AccLin>(g, desc, K, x, op, st, red);
 }
 
-// CG step, part 1: q = (I+L) p with p^T q, r^T M^{-1} q and q^T M^{-1} q.
-// The last workgroup forms alpha = rz / p^T q and, from the recurrence
-// r' = r - alpha q, rz' = rz - 2 alpha r^T M^{-1} q + alpha^2 q^T M^{-1} q and
-// beta = rz' / rz, so that the update kernel can also move the direction.
+// CG step, part 1: q = (I+L) p with the partial sums of p^T q, r^T M^{-1} q
+// and q^T M^{-1} q.
 template <typename V>
-__global__ void __launch_bounds__(WG) k_cg_spmv(Csr<V> g, const int* __restrict__ blk_row, int K,
+__global__ void __launch_bounds__(WG) k_cg_spmv(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                 const double* __restrict__ p,
                                                 const double* __restrict__ r,
                                                 const float* __restrict__ minv,
                                                 double* __restrict__ q, double* __restrict__ part,
-                                                Ctrl* __restrict__ ctrl) {
+                                                const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ Stage<double, V> st;
+    __shared__ Stage<double, V, OpCgSpmv::In> st;
     __shared__ double red[NWAVE * 4];
-    __shared__ int flag;
     OpCgSpmv op{r, minv, q};
-    for (int k = blockIdx.x; k < K; k += gridDim.x)
-        window_pass<double, V, AccLin>(g, blk_row, k, p, op, st, red);
+    my_windows<double, V, AccLin>(g, desc, K, p, op, st, red);
     double v[3] = {op.pq, op.rmq, op.qmq};
     block_sum<3>(v, red);
-    if (last_block_total<3>(v, part, ctrl, red, &flag) && threadIdx.x == 0) {
+    store_partials<3>(v, part);
+}
+
+// alpha = rz / p^T q; from the recurrence r' = r - alpha q,
+// rz' = rz - 2 alpha r^T M^{-1} q + alpha^2 q^T M^{-1} q and beta = rz' / rz,
+// so that the update kernel can also move the direction in the same pass.
+__global__ void __launch_bounds__(WG) k_fin_spmv(int G, const double* __restrict__ part,
+                                                 Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ double red[NWAVE * 3];
+    double v[3];
+    total_partials<3>(G, part, v, red);
+    if (threadIdx.x == 0) {
         const double rz = ctrl->rz;
         const double pq = v[0];
         if (rz == 0.0) {
@@ -395,37 +646,47 @@ __global__ void __launch_bounds__(WG) k_cg_spmv(Csr<V> g, const int* __restrict_
 }
 
 // CG step, part 2: x += alpha p, r -= alpha q, z = M^{-1} r, p = z + beta p, and
-// the exact r^T M^{-1} r (next alpha) and r^T r (stopping test).
+// the partial sums of the exact r^T M^{-1} r (next alpha) and r^T r (stopping test).
+__device__ __forceinline__ void cg_update_pair(int t, double alpha, double beta, double* __restrict__ x,
+                                               double* __restrict__ r, double* __restrict__ p,
+                                               const double* __restrict__ q,
+                                               const float* __restrict__ minv, double (&v)[2]) {
+    double2 xv = reinterpret_cast<double2*>(x)[t];
+    double2 rv = reinterpret_cast<double2*>(r)[t];
+    double2 pv = reinterpret_cast<double2*>(p)[t];
+    const double2 qv = reinterpret_cast<const double2*>(q)[t];
+    const float2 mv = reinterpret_cast<const float2*>(minv)[t];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    rv.x -= alpha * qv.x;
+    rv.y -= alpha * qv.y;
+    const double zx = static_cast<double>(mv.x) * rv.x;
+    const double zy = static_cast<double>(mv.y) * rv.y;
+    pv.x = zx + beta * pv.x;
+    pv.y = zy + beta * pv.y;
+    v[0] += rv.x * zx + rv.y * zy;
+    v[1] += rv.x * rv.x + rv.y * rv.y;
+    reinterpret_cast<double2*>(x)[t] = xv;
+    reinterpret_cast<double2*>(r)[t] = rv;
+    reinterpret_cast<double2*>(p)[t] = pv;
+}
+
 __global__ void __launch_bounds__(WG) k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                   double* __restrict__ p, const double* __restrict__ q,
                                                   const float* __restrict__ minv,
-                                                  double* __restrict__ part, Ctrl* __restrict__ ctrl) {
+                                                  double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
     __shared__ double red[NWAVE * 2];
-    __shared__ int flag;
     const double alpha = ctrl->alpha, beta = ctrl->beta;
     double v[2] = {0.0, 0.0};
     const int npair = n >> 1;
-    for (int t = blockIdx.x * WG + threadIdx.x; t < npair; t += gridDim.x * WG) {
-        double2 xv = reinterpret_cast<double2*>(x)[t];
-        double2 rv = reinterpret_cast<double2*>(r)[t];
-        double2 pv = reinterpret_cast<double2*>(p)[t];
-        const double2 qv = reinterpret_cast<const double2*>(q)[t];
-        const float2 mv = reinterpret_cast<const float2*>(minv)[t];
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        rv.x -= alpha * qv.x;
-        rv.y -= alpha * qv.y;
-        const double zx = static_cast<double>(mv.x) * rv.x;
-        const double zy = static_cast<double>(mv.y) * rv.y;
-        pv.x = zx + beta * pv.x;
-        pv.y = zy + beta * pv.y;
-        v[0] += rv.x * zx + rv.y * zy;
-        v[1] += rv.x * rv.x + rv.y * rv.y;
-        reinterpret_cast<double2*>(x)[t] = xv;
-        reinterpret_cast<double2*>(r)[t] = rv;
-        reinterpret_cast<double2*>(p)[t] = pv;
+    const int stride = gridDim.x * WG;
+    int t = blockIdx.x * WG + threadIdx.x;
+    for (; t + stride < npair; t += 2 * stride) {  // two pairs per thread in flight
+        cg_update_pair(t, alpha, beta, x, r, p, q, minv, v);
+        cg_update_pair(t + stride, alpha, beta, x, r, p, q, minv, v);
     }
+    if (t < npair) cg_update_pair(t, alpha, beta, x, r, p, q, minv, v);
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         const int i = n - 1;
         x[i] += alpha * p[i];
@@ -436,7 +697,16 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, double* __restrict__ x,
         v[1] += r[i] * r[i];
     }
     block_sum<2>(v, red);
-    if (last_block_total<2>(v, part, ctrl, red, &flag) && threadIdx.x == 0) {
+    store_partials<2>(v, part);
+}
+
+__global__ void __launch_bounds__(WG) k_fin_update(int G, const double* __restrict__ part,
+                                                   Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ double red[NWAVE * 2];
+    double v[2];
+    total_partials<2>(G, part, v, red);
+    if (threadIdx.x == 0) {
         const int it = ctrl->iters + 1;
         ctrl->iters = it;
         ctrl->rz = v[0];
@@ -450,16 +720,14 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, double* __restrict__ x,
 
 // CG start. mode 0: x = 0, r = s, plus the statistics of s (mean, ||s||^2,
 // range). mode 1: restart from the current x with r already holding the true
-// residual (written by the epilogue). Both: p = M^{-1} r, rz, rr, and the
-// stopping threshold tol2 = rtol2 * ||s||^2.
+// residual (written by the epilogue). Both: p = M^{-1} r and the partial sums
+// of rz and rr. Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 min s, 6 max s.
 __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict__ s, int64_t lds,
                                                 double* __restrict__ x, double* __restrict__ r,
                                                 double* __restrict__ p, const float* __restrict__ minv,
-                                                int mode, double rtol2, int max_iter, int range_check,
-                                                double* __restrict__ part, Ctrl* __restrict__ ctrl) {
+                                                int mode, double* __restrict__ part) {
     __shared__ double red[NWAVE * 8];
-    __shared__ int flag;
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // rz, rr, ss, sum s, bad count
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double smin = INFINITY, smax = -INFINITY;
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
         double ri;
@@ -482,7 +750,6 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
         v[1] += ri * ri;
     }
     block_sum<5>(v, red);
-    // workgroup min / max, published beside the sums
     smin = wave_min(smin);
     smax = wave_max(smax);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -497,16 +764,25 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
             a = fmin(a, red[NWAVE * 5 + w]);
             b = fmax(b, red[NWAVE * 6 + w]);
         }
-        part[blockIdx.x * NPART + 5] = a;
-        part[blockIdx.x * NPART + 6] = b;
+        double* out = part + blockIdx.x * NPART;
+        for (int c = 0; c < 5; ++c) out[c] = v[c];
+        out[5] = a;
+        out[6] = b;
     }
-    __syncthreads();
-    if (last_block_total<5>(v, part, ctrl, red, &flag) && threadIdx.x == 0) {
+}
+
+__global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __restrict__ part, int mode,
+                                                 double rtol2, int max_iter, int range_check,
+                                                 Ctrl* __restrict__ ctrl) {
+    __shared__ double red[NWAVE * 5];
+    double v[5];
+    total_partials<5>(G, part, v, red);
+    if (threadIdx.x == 0) {
         if (mode == 0) {
             double a = INFINITY, b = -INFINITY;
-            for (int k = 0; k < (int)gridDim.x; ++k) {
-                a = fmin(a, load_coherent(&part[k * NPART + 5]));
-                b = fmax(b, load_coherent(&part[k * NPART + 6]));
+            for (int k = 0; k < G; ++k) {
+                a = fmin(a, part[k * NPART + 5]);
+                b = fmax(b, part[k * NPART + 6]);
             }
             ctrl->smin = a;
             ctrl->smax = b;
@@ -529,30 +805,36 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
 }
 
 // Epilogue: one pass over the CSR at z. Writes r = s - (I+L)z (for a restart)
-// and the control block's results:
+// and the partial sums of OpEpilogue; k_fin_epilogue turns them into
 //   res[0] C_I  = ||L z||^2           res[5] ||r||_2
 //   res[1] D    = half the row sums    res[6] ||s||_2
 //   res[2] P    = sum (z - mean z)^2   res[7] sum (z_i - s_i)^2
 //   res[3] C    = ||z||^2              res[8] sum z
 //   res[4] I_dc = s^T z                res[9] z^T r
-// and bound[] (relative error bounds, see below).
+// and bound[] (relative error bounds, see k_fin_epilogue).
 template <typename V>
-__global__ void __launch_bounds__(WG) k_epilogue(Csr<V> g, const int* __restrict__ blk_row, int K,
+__global__ void __launch_bounds__(WG) k_epilogue(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                  const double* __restrict__ z, const double* __restrict__ s,
                                                  int64_t lds, double* __restrict__ rbuf,
-                                                 double* __restrict__ part, Ctrl* __restrict__ ctrl) {
-    __shared__ Stage<double, V> st;
-    __shared__ double red[NWAVE * 10];
-    __shared__ int flag;
+                                                 double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    __shared__ Stage<double, V, OpEpilogue::In> st;
+    __shared__ double red[NWAVE * 9];
     OpEpilogue op{s, lds, ctrl->mu, rbuf};
-    for (int k = blockIdx.x; k < K; k += gridDim.x)
-        window_pass<double, V, AccLinSq>(g, blk_row, k, z, op, st, red);
+    my_windows<double, V, AccLinSq>(g, desc, K, z, op, st, red);
     double v[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) v[c] = op.v[c];
     block_sum<9>(v, red);
-    if (last_block_total<9>(v, part, ctrl, red, &flag) && threadIdx.x == 0) {
-        const double n = static_cast<double>(g.n);
+    store_partials<9>(v, part);
+}
+
+__global__ void __launch_bounds__(WG) k_fin_epilogue(int G, int n_nodes, const double* __restrict__ part,
+                                                     Ctrl* __restrict__ ctrl) {
+    __shared__ double red[NWAVE * 9];
+    double v[9];
+    total_partials<9>(G, part, v, red);
+    if (threadIdx.x == 0) {
+        const double n = static_cast<double>(n_nodes);
         const double dev = v[4] - n * ctrl->mu;  // n (mean z - mu)
         double idx[5];
         idx[0] = v[0];

@@ -19,7 +19,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfjgpu.so")
+# FJGPU_LIB selects another build of the same library (for tuning experiments).
+LIB_PATH = os.environ.get("FJGPU_LIB", os.path.join(_HERE, "libfjgpu.so"))
 
 FJ_OK = 0
 FJ_ERR_INVALID_ARG = 1

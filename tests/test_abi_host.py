@@ -89,8 +89,9 @@ def test_argument_errors_are_caught_on_the_host(lib):
 
 def _constants():
     src = open(KERNELS).read()
-    get = lambda name: int(re.search(rf"constexpr int {name} = (\d+)", src).group(1))
-    return get("WIN"), get("LONGROW")
+    win = int(re.search(r"#define FJ_WIN (\d+)", src).group(1))
+    assert "constexpr int LONGROW = WIN / 2;" in src
+    return win, win // 2
 
 
 def _windows(g, WIN):
