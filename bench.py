@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--workload", default="cl4m", choices=sorted(WORKLOAD_META))
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
@@ -65,6 +67,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 8, "launches": 3}))
+        return
     t0 = time.perf_counter()
     g, s, spec = W.workload(args.workload)
     t_gen = time.perf_counter() - t0

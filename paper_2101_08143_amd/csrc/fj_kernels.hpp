@@ -775,14 +775,26 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
                                                  double rtol2, int max_iter, int range_check,
                                                  Ctrl* __restrict__ ctrl) {
     __shared__ double red[NWAVE * 5];
+    __shared__ double mm[2 * NWAVE];
     double v[5];
     total_partials<5>(G, part, v, red);
+    double a = INFINITY, b = -INFINITY;
+    for (int k = threadIdx.x; k < G; k += WG) {
+        a = fmin(a, part[k * NPART + 5]);
+        b = fmax(b, part[k * NPART + 6]);
+    }
+    a = wave_min(a);
+    b = wave_max(b);
+    if ((threadIdx.x & 63) == 0) {
+        mm[threadIdx.x >> 6] = a;
+        mm[NWAVE + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         if (mode == 0) {
-            double a = INFINITY, b = -INFINITY;
-            for (int k = 0; k < G; ++k) {
-                a = fmin(a, part[k * NPART + 5]);
-                b = fmax(b, part[k * NPART + 6]);
+            for (int w = 1; w < NWAVE; ++w) {
+                a = fmin(a, mm[w]);
+                b = fmax(b, mm[NWAVE + w]);
             }
             ctrl->smin = a;
             ctrl->smax = b;
