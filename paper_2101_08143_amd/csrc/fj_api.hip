@@ -81,19 +81,31 @@ PlanLayout plan_layout(const fj_csr* g) {
 }
 
 struct WsLayout {
-    size_t x, r, p, q, part, ctrl, total;
+    size_t x, r, p, q;          // FP64 vectors (p, q only for FJ_FP64)
+    size_t x32, r32, p32, q32;  // FP32 vectors of the inner solve (FJ_MIXED only)
+    size_t part, ctrl, total;   // partial sums; control blocks (outer, inner)
 };
 
-WsLayout ws_layout(const fj_csr* g, int k) {
+WsLayout ws_layout(const fj_csr* g, int k, int precision) {
     WsLayout L{};
-    const size_t vec = align_up(sizeof(double) * static_cast<size_t>(g->n) * static_cast<size_t>(k));
+    const size_t nk = static_cast<size_t>(g->n) * static_cast<size_t>(k);
+    const size_t v64 = align_up(sizeof(double) * nk);
+    const size_t v32 = align_up(sizeof(float) * nk);
+    const bool mixed = precision == FJ_MIXED;
     size_t off = 0;
-    L.x = off; off += vec;
-    L.r = off; off += vec;
-    L.p = off; off += vec;
-    L.q = off; off += vec;
+    L.x = off; off += v64;
+    L.r = off; off += v64;
+    if (!mixed) {
+        L.p = off; off += v64;
+        L.q = off; off += v64;
+    } else {
+        L.x32 = off; off += v32;
+        L.r32 = off; off += v32;
+        L.p32 = off; off += v32;
+        L.q32 = off; off += v32;
+    }
     L.part = off; off = align_up(off + sizeof(double) * GMAX * NPART);
-    L.ctrl = off; off = align_up(off + sizeof(Ctrl) * static_cast<size_t>(k));
+    L.ctrl = off; off = align_up(off + sizeof(Ctrl) * 2 * static_cast<size_t>(k));
     L.total = off;
     return L;
 }
@@ -202,7 +214,7 @@ int check_opts(const fj_opts* o) {
     if (!(o->eps > 0.0 && o->eps < 0.5)) return FJ_ERR_INVALID_ARG;
     if (!(o->rtol >= 0.0 && o->rtol < 1.0)) return FJ_ERR_INVALID_ARG;
     if (o->max_iter < 0 || o->reserved != 0) return FJ_ERR_INVALID_ARG;
-    if (o->precision != FJ_FP64) return FJ_ERR_INVALID_ARG;  // FJ_MIXED: see the mixed driver
+    if (o->precision != FJ_FP64 && o->precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
     return FJ_OK;
 }
 
@@ -218,151 +230,26 @@ int status_of(int done) {
 
 // ---------------------------------------------------------------- one solve
 
-struct Solver {
+// One CG state: vectors of type T, its control block, the shared partials.
+template <typename T>
+struct CgState {
+    T *x, *r, *p, *q;
+    Ctrl* ctrl;
+    double* part;
+};
+
+// What every launch of a solve needs.
+struct Ctx {
     const fj_csr* g;
     PlanLayout pl;
     const char* plan;
-    WsLayout wl;
-    char* ws;
     hipStream_t st;
     HostSlots* hs;
     bool profile;
-    int grid_win = 1, grid_vec = 1;
-    size_t n_prof = 0;  // event pairs used
-
-    double* x() const { return reinterpret_cast<double*>(ws + wl.x); }
-    double* r() const { return reinterpret_cast<double*>(ws + wl.r); }
-    double* p() const { return reinterpret_cast<double*>(ws + wl.p); }
-    double* q() const { return reinterpret_cast<double*>(ws + wl.q); }
-    double* part() const { return reinterpret_cast<double*>(ws + wl.part); }
-    Ctrl* ctrl() const { return reinterpret_cast<Ctrl*>(ws + wl.ctrl); }
+    size_t n_prof = 0;  // FJ_PROFILE event pairs used
+    int grid_vec = 1;
     const WinDesc* desc() const { return reinterpret_cast<const WinDesc*>(plan + pl.desc); }
     const float* minv() const { return reinterpret_cast<const float*>(plan + pl.minv); }
-
-    int setup() {
-        int rc = with_graph(g, [&](auto G) -> int {
-            using Vc = typename decltype(G)::value_type;
-            return grid_for(k_cg_spmv<Vc>, pl.K, &grid_win);
-        });
-        if (rc) return rc;
-        return grid_for(k_cg_update, (static_cast<int64_t>(g->n) + 2 * WG - 1) / (2 * WG), &grid_vec);
-    }
-
-    int init(const double* s, int64_t lds, int mode, double rtol, int max_iter, bool range_check) {
-        if (mode == 0) {
-            k_ctrl_reset<<<1, WG, 0, st>>>(ctrl(), 1);
-            HIPCHK(hipGetLastError());
-        }
-        k_cg_init<<<grid_vec, WG, 0, st>>>(g->n, s, lds, x(), r(), p(), minv(), mode, part());
-        HIPCHK(hipGetLastError());
-        k_fin_init<<<1, WG, 0, st>>>(grid_vec, g->n, part(), mode, rtol * rtol, max_iter, range_check ? 1 : 0,
-                                     ctrl());
-        HIPCHK(hipGetLastError());
-        return FJ_OK;
-    }
-
-    int launch_iteration() {
-        int rc = with_graph(g, [&](auto G) -> int {
-            using Vc = typename decltype(G)::value_type;
-            if (profile) {
-                if (int e = profile_events(*hs, n_prof + 1)) return e;
-                HIPCHK(hipEventRecord(hs->prof[2 * n_prof], st));
-            }
-            k_cg_spmv<Vc><<<grid_win, WG, 0, st>>>(G, desc(), pl.K, p(), r(), minv(), q(), part(), ctrl());
-            HIPCHK(hipGetLastError());
-            if (profile) {
-                HIPCHK(hipEventRecord(hs->prof[2 * n_prof + 1], st));
-                ++n_prof;
-            }
-            return FJ_OK;
-        });
-        if (rc) return rc;
-        k_fin_spmv<<<1, WG, 0, st>>>(grid_win, part(), ctrl());
-        HIPCHK(hipGetLastError());
-        k_cg_update<<<grid_vec, WG, 0, st>>>(g->n, x(), r(), p(), q(), minv(), part(), ctrl());
-        HIPCHK(hipGetLastError());
-        k_fin_update<<<1, WG, 0, st>>>(grid_vec, part(), ctrl());
-        HIPCHK(hipGetLastError());
-        return FJ_OK;
-    }
-
-    // Run CG until the control block says done. `start` = iterations already
-    // done before this pass. Leaves the final status copy in *out.
-    int run(int start, int max_iter, Ctrl* out) {
-        int queued = start;
-        int slot_next = 0;
-        std::deque<int> pending;
-        auto enqueue = [&](int cnt) -> int {
-            for (int t = 0; t < cnt; ++t)
-                if (int rc = launch_iteration()) return rc;
-            queued += cnt;
-            const int sl = slot_next++ % NSLOT;
-            HIPCHK(hipMemcpyAsync(&hs->h[sl], ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipEventRecord(hs->ev[sl], st));
-            pending.push_back(sl);
-            return FJ_OK;
-        };
-        for (int c = 0; c < 2 && queued < max_iter; ++c)
-            if (int rc = enqueue(std::min(FIRST_CHUNK, max_iter - queued))) return rc;
-        if (pending.empty()) {  // nothing to do: report the state after init
-            HIPCHK(hipMemcpyAsync(out, ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            return FJ_OK;
-        }
-        while (!pending.empty()) {
-            const int sl = pending.front();
-            pending.pop_front();
-            HIPCHK(hipEventSynchronize(hs->ev[sl]));
-            const Ctrl& c = hs->h[sl];
-            if (c.done != RUNNING || c.iters >= max_iter) {
-                std::memcpy(out, &c, sizeof(Ctrl));
-                // later chunks are empty launches; let them drain before returning
-                HIPCHK(hipStreamSynchronize(st));
-                if (!pending.empty()) std::memcpy(out, &hs->h[pending.back()], sizeof(Ctrl));
-                return FJ_OK;
-            }
-            int need = predict(c, start);
-            need = std::min(need, max_iter);
-            if (need > queued) {
-                if (int rc = enqueue(need - queued)) return rc;
-            } else if (pending.empty() && queued < max_iter) {
-                if (int rc = enqueue(1)) return rc;
-            }
-        }
-        HIPCHK(hipMemcpyAsync(out, ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        return FJ_OK;
-    }
-
-    // Absolute iteration count at which rr is expected to reach tol2, from the
-    // geometric rate of the last few iterations.
-    static int predict(const Ctrl& c, int start) {
-        const int t = c.iters;
-        const int m = std::min(4, t - start);
-        if (m <= 0 || !(c.rr > 0.0)) return t + FIRST_CHUNK;
-        const double prev = c.hist[(t - m) % HIST];
-        const double f = std::pow(c.rr / prev, 1.0 / m);
-        if (!(f < 0.999) || !(f > 0.0)) return t + FIRST_CHUNK;
-        const double more = std::ceil(std::log(c.tol2 / c.rr) / std::log(f));
-        if (!(more >= 1.0)) return t + 1;
-        return t + static_cast<int>(std::min(more, 200.0));
-    }
-
-    int epilogue(const double* s, int64_t lds, Ctrl* out) {
-        int rc = with_graph(g, [&](auto G) -> int {
-            using Vc = typename decltype(G)::value_type;
-            k_epilogue<Vc><<<grid_win, WG, 0, st>>>(G, desc(), pl.K, x(), s, lds, r(), part(), ctrl());
-            HIPCHK(hipGetLastError());
-            return FJ_OK;
-        });
-        if (rc) return rc;
-        k_fin_epilogue<<<1, WG, 0, st>>>(grid_win, g->n, part(), ctrl());
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&hs->h[NSLOT], ctrl(), sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        std::memcpy(out, &hs->h[NSLOT], sizeof(Ctrl));
-        return FJ_OK;
-    }
 
     int profile_total(fj_info* info) {
         if (!profile || !info) return FJ_OK;
@@ -378,8 +265,129 @@ struct Solver {
     }
 };
 
+template <typename T>
+int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, double rtol, int max_iter,
+            bool range_check) {
+    const int n = c.g->n;
+    if (mode != 1) {
+        k_ctrl_reset<<<1, WG, 0, c.st>>>(S.ctrl, 1);
+        HIPCHK(hipGetLastError());
+    }
+    k_cg_init<T><<<c.grid_vec, WG, 0, c.st>>>(n, s, lds, S.x, S.r, S.p, c.minv(), mode, S.part);
+    HIPCHK(hipGetLastError());
+    k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, mode, rtol * rtol, max_iter, range_check ? 1 : 0,
+                                   S.ctrl);
+    HIPCHK(hipGetLastError());
+    return FJ_OK;
+}
+
+template <typename T>
+int cg_iteration(Ctx& c, CgState<T>& S) {
+    int grid_win = 1;
+    int rc = with_graph(c.g, [&](auto G) -> int {
+        using Vc = typename decltype(G)::value_type;
+        if (int e = grid_for(k_cg_spmv<Vc, T>, c.pl.K, &grid_win)) return e;
+        if (c.profile) {
+            if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
+            HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
+        }
+        k_cg_spmv<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.r, c.minv(), S.q, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        if (c.profile) {
+            HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
+            ++c.n_prof;
+        }
+        return FJ_OK;
+    });
+    if (rc) return rc;
+    k_fin_spmv<<<1, WG, 0, c.st>>>(grid_win, S.part, S.ctrl);
+    HIPCHK(hipGetLastError());
+    k_cg_update<T><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, S.q, c.minv(), S.part, S.ctrl);
+    HIPCHK(hipGetLastError());
+    k_fin_update<<<1, WG, 0, c.st>>>(c.grid_vec, S.part, S.ctrl);
+    HIPCHK(hipGetLastError());
+    return FJ_OK;
+}
+
+// Absolute iteration count at which rr is expected to reach tol2, from the
+// geometric rate of the last few iterations.
+int predict(const Ctrl& c, int start) {
+    const int t = c.iters;
+    const int m = std::min(4, t - start);
+    if (m <= 0 || !(c.rr > 0.0)) return t + FIRST_CHUNK;
+    const double prev = c.hist[(t - m) % HIST];
+    const double f = std::pow(c.rr / prev, 1.0 / m);
+    if (!(f < 0.999) || !(f > 0.0)) return t + FIRST_CHUNK;
+    const double more = std::ceil(std::log(c.tol2 / c.rr) / std::log(f));
+    if (!(more >= 1.0)) return t + 1;
+    return t + static_cast<int>(std::min(more, 200.0));
+}
+
+// Run CG until its control block says done. `start` = iterations already done
+// before this pass. Leaves the final control block in *out.
+template <typename T>
+int cg_run(Ctx& c, CgState<T>& S, int start, int max_iter, Ctrl* out) {
+    int queued = start;
+    int slot_next = 0;
+    std::deque<int> pending;
+    auto enqueue = [&](int cnt) -> int {
+        for (int t = 0; t < cnt; ++t)
+            if (int rc = cg_iteration(c, S)) return rc;
+        queued += cnt;
+        const int sl = slot_next++ % NSLOT;
+        HIPCHK(hipMemcpyAsync(&c.hs->h[sl], S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipEventRecord(c.hs->ev[sl], c.st));
+        pending.push_back(sl);
+        return FJ_OK;
+    };
+    for (int k = 0; k < 2 && queued < max_iter; ++k)
+        if (int rc = enqueue(std::min(FIRST_CHUNK, max_iter - queued))) return rc;
+    while (!pending.empty()) {
+        const int sl = pending.front();
+        pending.pop_front();
+        HIPCHK(hipEventSynchronize(c.hs->ev[sl]));
+        const Ctrl& cc = c.hs->h[sl];
+        if (cc.done != RUNNING || cc.iters >= max_iter) {
+            std::memcpy(out, &cc, sizeof(Ctrl));
+            // later chunks are empty launches; let them drain before returning
+            HIPCHK(hipStreamSynchronize(c.st));
+            if (!pending.empty()) std::memcpy(out, &c.hs->h[pending.back()], sizeof(Ctrl));
+            return FJ_OK;
+        }
+        const int need = std::min(predict(cc, start), max_iter);
+        if (need > queued) {
+            if (int rc = enqueue(need - queued)) return rc;
+        } else if (pending.empty() && queued < max_iter) {
+            if (int rc = enqueue(1)) return rc;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(out, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    return FJ_OK;
+}
+
+// Epilogue at z = S.x: residual into S.r, indices and bounds into S.ctrl;
+// synchronises and copies the control block to *out.
+int epilogue(Ctx& c, CgState<double>& S, const double* s, int64_t lds, Ctrl* out) {
+    int grid_win = 1;
+    int rc = with_graph(c.g, [&](auto G) -> int {
+        using Vc = typename decltype(G)::value_type;
+        if (int e = grid_for(k_epilogue<Vc>, c.pl.K, &grid_win)) return e;
+        k_epilogue<Vc><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.x, s, lds, S.r, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
+    });
+    if (rc) return rc;
+    k_fin_epilogue<<<1, WG, 0, c.st>>>(grid_win, c.g->n, S.part, S.ctrl);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&c.hs->h[NSLOT], S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    std::memcpy(out, &c.hs->h[NSLOT], sizeof(Ctrl));
+    return FJ_OK;
+}
+
 // Smallest residual norm for which every index still meets eps/2, from the
-// current index values (inverse of the certificate in k_epilogue).
+// current index values (inverse of the certificate in k_fin_epilogue).
 double needed_rho(const Ctrl& c, double eps) {
     double need = INFINITY;
     const double scale[4] = {1.0, 2.0, 1.0, 1.0};  // D's error is bounded by rho / 2
@@ -391,57 +399,19 @@ double needed_rho(const Ctrl& c, double eps) {
     return need;
 }
 
-// FP64 single right-hand side: PCG passes until certified (indices) or until
-// the true relative residual meets rtol (solve).
-int solve_fp64(Solver& S, const double* s, int64_t lds, const fj_opts& o, bool want_indices,
-               fj_indices_t* out, fj_info* info) {
-    const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
-    double rtol = o.rtol > 0.0 ? o.rtol : o.eps * 1e-2;
-    const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
-    Ctrl c{};
-    int passes = 0;
-    int status = FJ_OK;
-    double prev_rho = INFINITY;
-    if (int rc = S.init(s, lds, 0, rtol, max_iter, range_check)) return rc;
-    for (;;) {
-        ++passes;
-        if (int rc = S.run(passes == 1 ? 0 : c.iters, max_iter, &c)) return rc;
-        if (c.done == BAD_INPUT || c.done == BREAKDOWN) {
-            status = status_of(c.done);
-            break;
-        }
-        if (int rc = S.epilogue(s, lds, &c)) return rc;
-        const double snorm = c.res[6];
-        const double rho = c.res[5];
-        const double rel = snorm > 0.0 ? rho / snorm : 0.0;
-        bool ok;
-        if (want_indices) {
-            ok = true;
-            for (int i = 0; i < 5; ++i) ok = ok && (c.bound[i] <= o.eps);
-        } else {
-            ok = rel <= rtol;
-        }
-        if (ok) {
-            status = FJ_OK;
-            break;
-        }
-        if (c.done == ITER_CAP || c.iters >= max_iter) {
-            status = FJ_ERR_NOT_CONVERGED;
-            break;
-        }
-        if (passes >= MAX_PASSES || !(rho < 0.5 * prev_rho)) {
-            // the residual no longer drops: an index is too close to zero
-            bool any_inf = false;
-            for (int i = 0; i < 5; ++i) any_inf = any_inf || !(c.bound[i] < INFINITY);
-            status = (want_indices && any_inf) ? FJ_ERR_UNCERTIFIABLE : FJ_ERR_NOT_CONVERGED;
-            break;
-        }
-        prev_rho = rho;
-        double next = rtol * 0.1;
-        if (want_indices && snorm > 0.0) next = std::min(next, 0.5 * needed_rho(c, o.eps) / snorm);
-        rtol = std::max(next, 1e-16);
-        if (int rc = S.init(s, lds, 1, rtol, max_iter, range_check)) return rc;
-    }
+bool certified(const Ctrl& c, double eps) {
+    for (int i = 0; i < 5; ++i)
+        if (!(c.bound[i] <= eps)) return false;
+    return true;
+}
+
+int stalled_status(const Ctrl& c, bool want_indices) {
+    bool any_inf = false;
+    for (int i = 0; i < 5; ++i) any_inf = any_inf || !(c.bound[i] < INFINITY);
+    return (want_indices && any_inf) ? FJ_ERR_UNCERTIFIABLE : FJ_ERR_NOT_CONVERGED;
+}
+
+void fill_outputs(const Ctrl& c, int status, int passes, int outer, fj_indices_t* out, fj_info* info) {
     if (out) {
         out->internal_conflict = c.res[0];
         out->disagreement = c.res[1];
@@ -453,27 +423,162 @@ int solve_fp64(Solver& S, const double* s, int64_t lds, const fj_opts& o, bool w
         info->status = status;
         info->iters = c.iters;
         info->passes = passes;
-        info->outer_iters = 0;
+        info->outer_iters = outer;
         info->rel_residual = c.res[6] > 0.0 ? c.res[5] / c.res[6] : 0.0;
         for (int i = 0; i < 5; ++i) info->bound[i] = c.bound[i];
-        if (int rc = S.profile_total(info)) return rc;
     }
+}
+
+// FP64: PCG passes until certified (indices) or until the true relative
+// residual meets rtol (solve); each further pass restarts from the true
+// residual with a tighter target.
+int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const fj_opts& o, bool want_indices,
+               fj_indices_t* out, fj_info* info) {
+    const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
+    double rtol = o.rtol > 0.0 ? o.rtol : o.eps * 1e-2;
+    const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
+    Ctrl cc{};
+    int passes = 0;
+    int status = FJ_OK;
+    double prev_rho = INFINITY;
+    if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check)) return rc;
+    for (;;) {
+        ++passes;
+        if (int rc = cg_run(c, S, passes == 1 ? 0 : cc.iters, max_iter, &cc)) return rc;
+        if (cc.done == BAD_INPUT || cc.done == BREAKDOWN) {
+            status = status_of(cc.done);
+            break;
+        }
+        if (int rc = epilogue(c, S, s, lds, &cc)) return rc;
+        const double snorm = cc.res[6];
+        const double rho = cc.res[5];
+        const double rel = snorm > 0.0 ? rho / snorm : 0.0;
+        if (want_indices ? certified(cc, o.eps) : rel <= rtol) {
+            status = FJ_OK;
+            break;
+        }
+        if (cc.done == ITER_CAP || cc.iters >= max_iter) {
+            status = FJ_ERR_NOT_CONVERGED;
+            break;
+        }
+        if (passes >= MAX_PASSES || !(rho < 0.5 * prev_rho)) {  // the residual no longer drops
+            status = stalled_status(cc, want_indices);
+            break;
+        }
+        prev_rho = rho;
+        double next = rtol * 0.1;
+        if (want_indices && snorm > 0.0) next = std::min(next, 0.5 * needed_rho(cc, o.eps) / snorm);
+        rtol = std::max(next, 1e-16);
+        if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check)) return rc;
+    }
+    fill_outputs(cc, status, passes, 0, out, info);
+    if (info)
+        if (int rc = c.profile_total(info)) return rc;
     return status;
 }
 
-int make_solver(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k, void* stream,
-                const fj_opts* o, Solver* S) {
+// FJ_MIXED: FP64 residual-and-correction refinement around FP32 inner CG.
+// Outer step: r32 = f32(r / ||r||); inner CG on (I+L) d = r32 to relative
+// residual tau; z += ||r|| d in FP64; FP64 epilogue (true residual, indices,
+// certificate). tau is chosen so that the next step should certify.
+int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, int64_t lds, const fj_opts& o,
+                bool want_indices, fj_indices_t* out, fj_info* info) {
+    const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
+    const double target = o.rtol > 0.0 ? o.rtol : o.eps * 1e-2;  // solve: relative residual to reach
+    const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
+    const int n = c.g->n;
+    Ctrl cc{}, ci{};
+    // FP64 start: x = 0, r = s and the statistics of s (no CG iteration runs on it)
+    if (int rc = cg_init(c, S, s, lds, 0, 1.0, max_iter, range_check)) return rc;
+    HIPCHK(hipMemcpyAsync(&cc, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    if (cc.done == BAD_INPUT) {
+        fill_outputs(cc, FJ_ERR_OPINION_RANGE, 0, 0, out, info);
+        return FJ_ERR_OPINION_RANGE;
+    }
+    const double snorm = std::sqrt(cc.ss);
+    double rho = snorm;
+    double tau = 1e-4;
+    int inner_total = 0, outer = 0, status = FJ_ERR_NOT_CONVERGED;
+    while (outer < 8 && inner_total < max_iter) {
+        ++outer;
+        const int mode = outer == 1 ? 0 : 1;
+        k_mixed_cast<<<c.grid_vec, WG, 0, c.st>>>(n, S.r, I.r, mode, S.ctrl);
+        HIPCHK(hipGetLastError());
+        if (int rc = cg_init(c, I, nullptr, 0, 2, tau, max_iter - inner_total, false)) return rc;
+        if (int rc = cg_run(c, I, 0, max_iter - inner_total, &ci)) return rc;
+        inner_total += ci.iters;
+        if (ci.done == BREAKDOWN) {
+            status = FJ_ERR_BREAKDOWN;
+            break;
+        }
+        k_mixed_refine<<<c.grid_vec, WG, 0, c.st>>>(n, S.x, I.x, mode, S.ctrl);
+        HIPCHK(hipGetLastError());
+        if (int rc = epilogue(c, S, s, lds, &cc)) return rc;
+        const double new_rho = cc.res[5];
+        const bool ok = want_indices ? certified(cc, o.eps) : (snorm == 0.0 || new_rho <= target * snorm);
+        if (ok) {
+            status = FJ_OK;
+            break;
+        }
+        if (!(new_rho < 0.5 * rho)) {  // refinement no longer reduces the residual
+            status = stalled_status(cc, want_indices);
+            break;
+        }
+        rho = new_rho;
+        const double goal = want_indices ? needed_rho(cc, o.eps) : target * snorm;
+        tau = std::min(1e-2, std::max(1e-5, 0.5 * goal / rho));
+    }
+    cc.iters = inner_total;
+    fill_outputs(cc, status, outer, outer, out, info);
+    if (info)
+        if (int rc = c.profile_total(info)) return rc;
+    return status;
+}
+
+int make_ctx(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k, void* stream,
+             const fj_opts* o, Ctx* c, WsLayout* wl) {
     if (!plan || !ws || !aligned(plan) || !aligned(ws)) return FJ_ERR_WORKSPACE;
-    S->g = g;
-    S->pl = plan_layout(g);
-    S->plan = static_cast<const char*>(plan);
-    S->wl = ws_layout(g, k);
-    if (ws_bytes < S->wl.total) return FJ_ERR_WORKSPACE;
-    S->ws = static_cast<char*>(ws);
-    S->st = static_cast<hipStream_t>(stream);
-    S->profile = (o->flags & FJ_PROFILE) != 0;
-    if (int rc = host_slots(&S->hs)) return rc;
-    return S->setup();
+    c->g = g;
+    c->pl = plan_layout(g);
+    c->plan = static_cast<const char*>(plan);
+    *wl = ws_layout(g, k, o->precision);
+    if (ws_bytes < wl->total) return FJ_ERR_WORKSPACE;
+    c->st = static_cast<hipStream_t>(stream);
+    c->profile = (o->flags & FJ_PROFILE) != 0;
+    if (int rc = host_slots(&c->hs)) return rc;
+    return grid_for(k_cg_update<double>, (static_cast<int64_t>(g->n) + 2 * WG - 1) / (2 * WG), &c->grid_vec);
+}
+
+// Single right-hand side, either precision. Z (may be null) receives z.
+int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, double* Z, int64_t ldz,
+              const fj_opts& o, void* ws, size_t ws_bytes, void* stream, bool want_indices, fj_indices_t* out,
+              fj_info* info) {
+    Ctx c{};
+    WsLayout wl{};
+    if (int rc = make_ctx(g, plan, ws, ws_bytes, 1, stream, &o, &c, &wl)) return rc;
+    char* W = static_cast<char*>(ws);
+    Ctrl* ctrls = reinterpret_cast<Ctrl*>(W + wl.ctrl);
+    double* part = reinterpret_cast<double*>(W + wl.part);
+    const bool mixed = o.precision == FJ_MIXED;  // FP64 side of FJ_MIXED keeps only x and r
+    CgState<double> S64{reinterpret_cast<double*>(W + wl.x), reinterpret_cast<double*>(W + wl.r),
+                        mixed ? nullptr : reinterpret_cast<double*>(W + wl.p),
+                        mixed ? nullptr : reinterpret_cast<double*>(W + wl.q), &ctrls[0], part};
+    int status;
+    if (o.precision == FJ_MIXED) {
+        CgState<float> S32{reinterpret_cast<float*>(W + wl.x32), reinterpret_cast<float*>(W + wl.r32),
+                           reinterpret_cast<float*>(W + wl.p32), reinterpret_cast<float*>(W + wl.q32), &ctrls[1],
+                           part};
+        status = solve_mixed(c, S64, S32, S, lds, o, want_indices, out, info);
+    } else {
+        status = solve_fp64(c, S64, S, lds, o, want_indices, out, info);
+    }
+    if (Z && status != FJ_ERR_HIP && status != FJ_ERR_OPINION_RANGE) {
+        HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, S64.x, sizeof(double), sizeof(double), g->n,
+                                hipMemcpyDeviceToDevice, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+    }
+    return status;
 }
 
 }  // namespace
@@ -512,9 +617,8 @@ size_t fj_plan_bytes(const fj_csr* g) {
 }
 
 size_t fj_workspace_bytes(const fj_csr* g, int32_t k, const fj_opts* opts) {
-    (void)opts;
     if (check_graph_args(g) || k < 1) return 0;
-    return ws_layout(g, k).total;
+    return ws_layout(g, k, opts ? opts->precision : FJ_FP64).total;
 }
 
 int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_bytes, void* stream) {
@@ -588,14 +692,7 @@ int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int6
     if (int rc = check_opts(opts)) return rc;
     if (k != 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
     if (g->n == 0) return FJ_OK;
-    Solver sv{};
-    if (int rc = make_solver(g, plan, ws, ws_bytes, k, stream, opts, &sv)) return rc;
-    const int status = solve_fp64(sv, S, lds, *opts, false, nullptr, info);
-    if (status == FJ_ERR_HIP || status == FJ_ERR_OPINION_RANGE) return status;
-    HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, sv.x(), sizeof(double), sizeof(double), g->n,
-                            hipMemcpyDeviceToDevice, sv.st));
-    HIPCHK(hipStreamSynchronize(sv.st));
-    return status;
+    return solve_one(g, plan, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
 }
 
 int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, int64_t lds,
@@ -605,9 +702,7 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
     if (int rc = check_opts(opts)) return rc;
     if (k != 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
     if (g->n == 0) return FJ_ERR_INVALID_ARG;
-    Solver sv{};
-    if (int rc = make_solver(g, plan, ws, ws_bytes, k, stream, opts, &sv)) return rc;
-    return solve_fp64(sv, S, lds, *opts, true, out, info);
+    return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
 }
 
 }  // extern "C"

@@ -502,22 +502,28 @@ struct OpApply {  // y = (I + L) x
     __device__ void row(int i, double xi, double lin, double, const In&) { y[i] = xi + lin; }
 };
 
-struct OpCgSpmv {  // q = (I + L) p and the three dot products the CG scalars need
+// q = (I + L) p and the three dot products the CG scalars need. T is the
+// vector precision (double, or float for the inner solve of FJ_MIXED); the
+// row sums and the dot products are accumulated in double, and the dots use q
+// as stored.
+template <typename T>
+struct OpCgSpmv {
     struct In {
-        double r;
+        T r;
         float m;
     };
-    const double* __restrict__ r;
+    const T* __restrict__ r;
     const float* __restrict__ minv;
-    double* __restrict__ q;
+    T* __restrict__ q;
     double pq = 0.0, rmq = 0.0, qmq = 0.0;
     __device__ In load(int i) const { return {r[i], minv[i]}; }
-    __device__ void row(int i, double pi, double lin, double, const In& in) {
-        const double qi = pi + lin;
-        q[i] = qi;
+    __device__ void row(int i, T pi, double lin, double, const In& in) {
+        const T qt = static_cast<T>(static_cast<double>(pi) + lin);
+        q[i] = qt;
+        const double qi = static_cast<double>(qt);
         const double mq = static_cast<double>(in.m) * qi;
-        pq += pi * qi;
-        rmq += in.r * mq;
+        pq += static_cast<double>(pi) * qi;
+        rmq += static_cast<double>(in.r) * mq;
         qmq += qi * mq;
     }
 };
@@ -603,18 +609,16 @@ __global__ void __launch_bounds__(WG) k_apply(Csr<V> g, const WinDesc* __restric
 
 // CG step, part 1: q = (I+L) p with the partial sums of p^T q, r^T M^{-1} q
 // and q^T M^{-1} q.
-template <typename V>
+template <typename V, typename T>
 __global__ void __launch_bounds__(WG) k_cg_spmv(Csr<V> g, const WinDesc* __restrict__ desc, int K,
-                                                const double* __restrict__ p,
-                                                const double* __restrict__ r,
-                                                const float* __restrict__ minv,
-                                                double* __restrict__ q, double* __restrict__ part,
-                                                const Ctrl* __restrict__ ctrl) {
+                                                const T* __restrict__ p, const T* __restrict__ r,
+                                                const float* __restrict__ minv, T* __restrict__ q,
+                                                double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ Stage<double, V, OpCgSpmv::In> st;
+    __shared__ Stage<T, V, typename OpCgSpmv<T>::In> st;
     __shared__ double red[NWAVE * 4];
-    OpCgSpmv op{r, minv, q};
-    my_windows<double, V, AccLin>(g, desc, K, p, op, st, red);
+    OpCgSpmv<T> op{r, minv, q};
+    my_windows<T, V, AccLin>(g, desc, K, p, op, st, red);
     double v[3] = {op.pq, op.rmq, op.qmq};
     block_sum<3>(v, red);
     store_partials<3>(v, part);
@@ -646,55 +650,71 @@ __global__ void __launch_bounds__(WG) k_fin_spmv(int G, const double* __restrict
 }
 
 // CG step, part 2: x += alpha p, r -= alpha q, z = M^{-1} r, p = z + beta p, and
-// the partial sums of the exact r^T M^{-1} r (next alpha) and r^T r (stopping test).
-__device__ __forceinline__ void cg_update_pair(int t, double alpha, double beta, double* __restrict__ x,
-                                               double* __restrict__ r, double* __restrict__ p,
-                                               const double* __restrict__ q,
-                                               const float* __restrict__ minv, double (&v)[2]) {
-    double2 xv = reinterpret_cast<double2*>(x)[t];
-    double2 rv = reinterpret_cast<double2*>(r)[t];
-    double2 pv = reinterpret_cast<double2*>(p)[t];
-    const double2 qv = reinterpret_cast<const double2*>(q)[t];
-    const float2 mv = reinterpret_cast<const float2*>(minv)[t];
-    xv.x += alpha * pv.x;
-    xv.y += alpha * pv.y;
-    rv.x -= alpha * qv.x;
-    rv.y -= alpha * qv.y;
-    const double zx = static_cast<double>(mv.x) * rv.x;
-    const double zy = static_cast<double>(mv.y) * rv.y;
-    pv.x = zx + beta * pv.x;
-    pv.y = zy + beta * pv.y;
-    v[0] += rv.x * zx + rv.y * zy;
-    v[1] += rv.x * rv.x + rv.y * rv.y;
-    reinterpret_cast<double2*>(x)[t] = xv;
-    reinterpret_cast<double2*>(r)[t] = rv;
-    reinterpret_cast<double2*>(p)[t] = pv;
+// the partial sums of the exact r^T M^{-1} r (next alpha) and r^T r (stopping
+// test). Each thread moves 16-byte packs of every vector (2 doubles or 4
+// floats); arithmetic is in double, rounded once when stored.
+template <typename T> struct Pack;
+template <> struct Pack<double> { using type = double2; using mtype = float2; static constexpr int N = 2; };
+template <> struct Pack<float> { using type = float4; using mtype = float4; static constexpr int N = 4; };
+
+template <typename T>
+__device__ __forceinline__ void cg_update_elem(double alpha, double beta, T& x, T& r, T& p, T q, float m,
+                                               double (&v)[2]) {
+    x = static_cast<T>(static_cast<double>(x) + alpha * static_cast<double>(p));
+    r = static_cast<T>(static_cast<double>(r) - alpha * static_cast<double>(q));
+    const double rd = static_cast<double>(r);
+    const double z = static_cast<double>(m) * rd;
+    p = static_cast<T>(z + beta * static_cast<double>(p));
+    v[0] += rd * z;
+    v[1] += rd * rd;
 }
 
-__global__ void __launch_bounds__(WG) k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
-                                                  double* __restrict__ p, const double* __restrict__ q,
+template <typename T>
+__device__ __forceinline__ void cg_update_pack(int t, double alpha, double beta, T* __restrict__ x,
+                                               T* __restrict__ r, T* __restrict__ p,
+                                               const T* __restrict__ q, const float* __restrict__ minv,
+                                               double (&v)[2]) {
+    using P = typename Pack<T>::type;
+    using M = typename Pack<T>::mtype;
+    constexpr int N = Pack<T>::N;
+    P xv = reinterpret_cast<P*>(x)[t];
+    P rv = reinterpret_cast<P*>(r)[t];
+    P pv = reinterpret_cast<P*>(p)[t];
+    const P qv = reinterpret_cast<const P*>(q)[t];
+    const M mv = reinterpret_cast<const M*>(minv)[t];
+    T* xs = reinterpret_cast<T*>(&xv);
+    T* rs = reinterpret_cast<T*>(&rv);
+    T* ps = reinterpret_cast<T*>(&pv);
+    const T* qs = reinterpret_cast<const T*>(&qv);
+    const float* ms = reinterpret_cast<const float*>(&mv);
+#pragma unroll
+    for (int e = 0; e < N; ++e) cg_update_elem(alpha, beta, xs[e], rs[e], ps[e], qs[e], ms[e], v);
+    reinterpret_cast<P*>(x)[t] = xv;
+    reinterpret_cast<P*>(r)[t] = rv;
+    reinterpret_cast<P*>(p)[t] = pv;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_cg_update(int n, T* __restrict__ x, T* __restrict__ r,
+                                                  T* __restrict__ p, const T* __restrict__ q,
                                                   const float* __restrict__ minv,
                                                   double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
     __shared__ double red[NWAVE * 2];
+    constexpr int N = Pack<T>::N;
     const double alpha = ctrl->alpha, beta = ctrl->beta;
     double v[2] = {0.0, 0.0};
-    const int npair = n >> 1;
+    const int npack = n / N;
     const int stride = gridDim.x * WG;
     int t = blockIdx.x * WG + threadIdx.x;
-    for (; t + stride < npair; t += 2 * stride) {  // two pairs per thread in flight
-        cg_update_pair(t, alpha, beta, x, r, p, q, minv, v);
-        cg_update_pair(t + stride, alpha, beta, x, r, p, q, minv, v);
+    for (; t + stride < npack; t += 2 * stride) {  // two packs per thread in flight
+        cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
+        cg_update_pack(t + stride, alpha, beta, x, r, p, q, minv, v);
     }
-    if (t < npair) cg_update_pair(t, alpha, beta, x, r, p, q, minv, v);
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-        const int i = n - 1;
-        x[i] += alpha * p[i];
-        r[i] -= alpha * q[i];
-        const double zi = static_cast<double>(minv[i]) * r[i];
-        p[i] = zi + beta * p[i];
-        v[0] += r[i] * zi;
-        v[1] += r[i] * r[i];
+    if (t < npack) cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
+    if (blockIdx.x == 0 && threadIdx.x < n - npack * N) {
+        const int i = npack * N + threadIdx.x;
+        cg_update_elem(alpha, beta, x[i], r[i], p[i], q[i], minv[i], v);
     }
     block_sum<2>(v, red);
     store_partials<2>(v, part);
@@ -720,12 +740,14 @@ __global__ void __launch_bounds__(WG) k_fin_update(int G, const double* __restri
 
 // CG start. mode 0: x = 0, r = s, plus the statistics of s (mean, ||s||^2,
 // range). mode 1: restart from the current x with r already holding the true
-// residual (written by the epilogue). Both: p = M^{-1} r and the partial sums
-// of rz and rr. Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 min s, 6 max s.
+// residual (written by the epilogue). mode 2: x = 0 with r given (the inner
+// solve of FJ_MIXED). All: p = M^{-1} r and the partial sums of rz and rr.
+// Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 min s, 6 max s.
+template <typename T>
 __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict__ s, int64_t lds,
-                                                double* __restrict__ x, double* __restrict__ r,
-                                                double* __restrict__ p, const float* __restrict__ minv,
-                                                int mode, double* __restrict__ part) {
+                                                T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
+                                                const float* __restrict__ minv, int mode,
+                                                double* __restrict__ part) {
     __shared__ double red[NWAVE * 8];
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double smin = INFINITY, smax = -INFINITY;
@@ -733,20 +755,21 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
         double ri;
         if (mode == 0) {
             const double si = s[static_cast<int64_t>(i) * lds];
-            x[i] = 0.0;
-            ri = si;
-            r[i] = si;
+            x[i] = T(0);
+            r[i] = static_cast<T>(si);
+            ri = static_cast<double>(r[i]);
             v[2] += si * si;
             v[3] += si;
             if (!(si >= 0.0 && si <= 1.0)) v[4] += 1.0;
             smin = fmin(smin, si);
             smax = fmax(smax, si);
         } else {
-            ri = r[i];
+            if (mode == 2) x[i] = T(0);
+            ri = static_cast<double>(r[i]);
         }
-        const double zi = static_cast<double>(minv[i]) * ri;
-        p[i] = zi;
-        v[0] += ri * zi;
+        const T zt = static_cast<T>(static_cast<double>(minv[i]) * ri);
+        if (p != nullptr) p[i] = zt;  // null: statistics only (FP64 side of FJ_MIXED)
+        v[0] += ri * static_cast<double>(zt);
         v[1] += ri * ri;
     }
     block_sum<5>(v, red);
@@ -803,6 +826,12 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
             ctrl->bad = v[4] > 0.0 ? 2 : 0;
             ctrl->iters = 0;
             ctrl->max_iter = max_iter;
+        }
+        if (mode == 2) {  // the inner solve of FJ_MIXED: tolerance relative to its own right-hand side
+            ctrl->ss = v[1];
+            ctrl->iters = 0;
+            ctrl->max_iter = max_iter;
+            ctrl->bad = 0;
         }
         ctrl->tol2 = rtol2 * ctrl->ss;
         ctrl->rz = v[0];
@@ -875,6 +904,25 @@ __global__ void __launch_bounds__(WG) k_fin_epilogue(int G, int n_nodes, const d
         const double a = (sqrt(idx[3]) + rho) * rho;
         ctrl->bound[4] = (idx[4] > a) ? a / (idx[4] - a) + 1e-13 : INFINITY;
     }
+}
+
+// FJ_MIXED: the inner right-hand side r32 = f32(r / ||r||). mode 0 takes
+// ||r|| = ||s|| (first step, z = 0 and r = s, from init), mode 1 the epilogue's
+// true residual norm.
+__global__ void __launch_bounds__(WG) k_mixed_cast(int n, const double* __restrict__ r64, float* __restrict__ r32,
+                                                   int mode, const Ctrl* __restrict__ outer) {
+    const double rho = mode == 0 ? sqrt(outer->ss) : outer->res[5];
+    const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG)
+        r32[i] = static_cast<float>(r64[i] * inv);
+}
+
+// FJ_MIXED: the FP64 correction z += ||r|| * f64(d), d the inner solution.
+__global__ void __launch_bounds__(WG) k_mixed_refine(int n, double* __restrict__ z, const float* __restrict__ d,
+                                                     int mode, const Ctrl* __restrict__ outer) {
+    const double rho = mode == 0 ? sqrt(outer->ss) : outer->res[5];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG)
+        z[i] += rho * static_cast<double>(d[i]);
 }
 
 // Clear the control block before a solve (a kernel rather than a memset so
