@@ -25,6 +25,7 @@
 
 #include "../../include/fj.h"
 #include "fj_kernels.hpp"
+#include "fj_batched.hpp"
 
 using namespace fj;
 
@@ -81,14 +82,31 @@ PlanLayout plan_layout(const fj_csr* g) {
 }
 
 struct WsLayout {
+    int kp;                     // columns per block (1, or a power of two 2..KMAX)
     size_t x, r, p, q;          // FP64 vectors (p, q only for FJ_FP64)
     size_t x32, r32, p32, q32;  // FP32 vectors of the inner solve (FJ_MIXED only)
-    size_t part, ctrl, total;   // partial sums; control blocks (outer, inner)
+    size_t sblk;                // FJ_TWO_SOLVE: the block [s, s - mean(s)]
+    size_t part, ctrl, total;   // partial sums; control blocks (outer kp, inner kp)
 };
 
-WsLayout ws_layout(const fj_csr* g, int k, int precision) {
+int padded_columns(int k) {
+    int kp = 2;
+    while (kp < k) kp *= 2;
+    return kp;
+}
+
+// Columns handled by one batched solve: a single right-hand side runs alone
+// (kp = 1) unless Algorithm 1 is asked for literally (two columns); more than
+// KMAX columns are solved KMAX at a time.
+int block_columns(int k, uint32_t flags) {
+    if (k == 1) return (flags & FJ_TWO_SOLVE) ? 2 : 1;
+    return padded_columns(std::min(k, KMAX));
+}
+
+WsLayout ws_layout(const fj_csr* g, int k, int precision, uint32_t flags) {
     WsLayout L{};
-    const size_t nk = static_cast<size_t>(g->n) * static_cast<size_t>(k);
+    L.kp = block_columns(k, flags);
+    const size_t nk = static_cast<size_t>(g->n) * static_cast<size_t>(L.kp);
     const size_t v64 = align_up(sizeof(double) * nk);
     const size_t v32 = align_up(sizeof(float) * nk);
     const bool mixed = precision == FJ_MIXED;
@@ -104,8 +122,12 @@ WsLayout ws_layout(const fj_csr* g, int k, int precision) {
         L.p32 = off; off += v32;
         L.q32 = off; off += v32;
     }
-    L.part = off; off = align_up(off + sizeof(double) * GMAX * NPART);
-    L.ctrl = off; off = align_up(off + sizeof(Ctrl) * 2 * static_cast<size_t>(k));
+    if (k == 1 && (flags & FJ_TWO_SOLVE)) {
+        L.sblk = off;
+        off += align_up(sizeof(double) * 2 * static_cast<size_t>(g->n));
+    }
+    L.part = off; off = align_up(off + sizeof(double) * GMAX * std::max(NPART, BPART * L.kp));
+    L.ctrl = off; off = align_up(off + sizeof(Ctrl) * 2 * static_cast<size_t>(L.kp));
     L.total = off;
     return L;
 }
@@ -149,9 +171,10 @@ int grid_for(Kern kernel, int64_t work_units, int* grid) {
 // ---------------------------------------------------------------- host slots
 
 struct HostSlots {
-    Ctrl* h = nullptr;                 // pinned, NSLOT + 1 control-block copies
+    Ctrl* h = nullptr;                 // pinned, NSLOT + 1 slots of KMAX control blocks
     hipEvent_t ev[NSLOT + 1] = {};
     std::vector<hipEvent_t> prof;      // FJ_PROFILE event pairs
+    Ctrl* slot(int i) { return h + static_cast<size_t>(i) * KMAX; }
 };
 
 thread_local std::map<int, HostSlots> tl_slots;
@@ -161,7 +184,8 @@ int host_slots(HostSlots** out) {
     if (int rc = current_device(&dev)) return rc;
     HostSlots& hs = tl_slots[dev];
     if (!hs.h) {
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hs.h), sizeof(Ctrl) * (NSLOT + 1), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hs.h), sizeof(Ctrl) * KMAX * (NSLOT + 1),
+                             hipHostMallocDefault));
         for (auto& e : hs.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     *out = &hs;
@@ -335,7 +359,7 @@ int cg_run(Ctx& c, CgState<T>& S, int start, int max_iter, Ctrl* out) {
             if (int rc = cg_iteration(c, S)) return rc;
         queued += cnt;
         const int sl = slot_next++ % NSLOT;
-        HIPCHK(hipMemcpyAsync(&c.hs->h[sl], S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipMemcpyAsync(c.hs->slot(sl), S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipEventRecord(c.hs->ev[sl], c.st));
         pending.push_back(sl);
         return FJ_OK;
@@ -346,12 +370,12 @@ int cg_run(Ctx& c, CgState<T>& S, int start, int max_iter, Ctrl* out) {
         const int sl = pending.front();
         pending.pop_front();
         HIPCHK(hipEventSynchronize(c.hs->ev[sl]));
-        const Ctrl& cc = c.hs->h[sl];
+        const Ctrl& cc = *c.hs->slot(sl);
         if (cc.done != RUNNING || cc.iters >= max_iter) {
             std::memcpy(out, &cc, sizeof(Ctrl));
             // later chunks are empty launches; let them drain before returning
             HIPCHK(hipStreamSynchronize(c.st));
-            if (!pending.empty()) std::memcpy(out, &c.hs->h[pending.back()], sizeof(Ctrl));
+            if (!pending.empty()) std::memcpy(out, c.hs->slot(pending.back()), sizeof(Ctrl));
             return FJ_OK;
         }
         const int need = std::min(predict(cc, start), max_iter);
@@ -380,34 +404,37 @@ int epilogue(Ctx& c, CgState<double>& S, const double* s, int64_t lds, Ctrl* out
     if (rc) return rc;
     k_fin_epilogue<<<1, WG, 0, c.st>>>(grid_win, c.g->n, S.part, S.ctrl);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&c.hs->h[NSLOT], S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
-    std::memcpy(out, &c.hs->h[NSLOT], sizeof(Ctrl));
+    std::memcpy(out, c.hs->slot(NSLOT), sizeof(Ctrl));
     return FJ_OK;
 }
 
 // Smallest residual norm for which every index still meets eps/2, from the
 // current index values (inverse of the certificate in k_fin_epilogue).
-double needed_rho(const Ctrl& c, double eps) {
+constexpr unsigned ALL_INDICES = 0x1Fu;
+
+double needed_rho(const Ctrl& c, double eps, unsigned which = ALL_INDICES) {
     double need = INFINITY;
     const double scale[4] = {1.0, 2.0, 1.0, 1.0};  // D's error is bounded by rho / 2
     for (int i = 0; i < 4; ++i) {
         const double x = c.res[i];
-        if (x > 0.0) need = std::min(need, scale[i] * 0.25 * eps * std::sqrt(x));
+        if (((which >> i) & 1u) && x > 0.0) need = std::min(need, scale[i] * 0.25 * eps * std::sqrt(x));
     }
-    if (c.res[4] > 0.0 && c.res[3] > 0.0) need = std::min(need, 0.5 * eps * c.res[4] / std::sqrt(c.res[3]));
+    if ((which & 16u) && c.res[4] > 0.0 && c.res[3] > 0.0)
+        need = std::min(need, 0.5 * eps * c.res[4] / std::sqrt(c.res[3]));
     return need;
 }
 
-bool certified(const Ctrl& c, double eps) {
+bool certified(const Ctrl& c, double eps, unsigned which = ALL_INDICES) {
     for (int i = 0; i < 5; ++i)
-        if (!(c.bound[i] <= eps)) return false;
+        if (((which >> i) & 1u) && !(c.bound[i] <= eps)) return false;
     return true;
 }
 
-int stalled_status(const Ctrl& c, bool want_indices) {
+int stalled_status(const Ctrl& c, bool want_indices, unsigned which = ALL_INDICES) {
     bool any_inf = false;
-    for (int i = 0; i < 5; ++i) any_inf = any_inf || !(c.bound[i] < INFINITY);
+    for (int i = 0; i < 5; ++i) any_inf = any_inf || (((which >> i) & 1u) && !(c.bound[i] < INFINITY));
     return (want_indices && any_inf) ? FJ_ERR_UNCERTIFIABLE : FJ_ERR_NOT_CONVERGED;
 }
 
@@ -542,7 +569,7 @@ int make_ctx(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k
     c->g = g;
     c->pl = plan_layout(g);
     c->plan = static_cast<const char*>(plan);
-    *wl = ws_layout(g, k, o->precision);
+    *wl = ws_layout(g, k, o->precision, o->flags);
     if (ws_bytes < wl->total) return FJ_ERR_WORKSPACE;
     c->st = static_cast<hipStream_t>(stream);
     c->profile = (o->flags & FJ_PROFILE) != 0;
@@ -579,6 +606,425 @@ int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, d
         HIPCHK(hipStreamSynchronize(c.st));
     }
     return status;
+}
+
+// ---------------------------------------------------------------- k columns
+
+template <typename T>
+struct BState {
+    T *X, *R, *P, *Q;
+    Ctrl* ctrl;  // KB control blocks
+    double* part;
+};
+
+// The batched driver for KB columns (see fj_batched.hpp).
+template <int KB>
+struct Batched {
+    Ctx& c;
+    int grid_vec = 1;
+    static constexpr uint64_t ALL = KB >= 64 ? ~0ull : ((1ull << KB) - 1ull);
+
+    int setup() {
+        const int64_t units = (static_cast<int64_t>(c.g->n) * KB + WG - 1) / WG;
+        return grid_for(k_update_batched<double, KB>, units, &grid_vec);
+    }
+
+    template <typename T>
+    int init(BState<T>& S, const double* src, int64_t lds, int k, int kcheck, int mode, uint64_t mask,
+             const double* rtol, int max_iter, bool range_check) {
+        ColumnTol tol{};
+        for (int col = 0; col < KB; ++col) tol.rtol2[col] = rtol[col] * rtol[col];
+        const int n = c.g->n;
+        if (mode != 1) {
+            k_ctrl_reset<<<1, WG, 0, c.st>>>(S.ctrl, KB);
+            HIPCHK(hipGetLastError());
+        }
+        k_init_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(n, k, src, lds, S.X, S.R, S.P, c.minv(), mode, mask, kcheck,
+                                                        S.part);
+        HIPCHK(hipGetLastError());
+        k_fin_init_batched<KB><<<1, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter,
+                                                   range_check ? 1 : 0, S.ctrl);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
+    }
+
+    template <typename T>
+    int iteration(BState<T>& S) {
+        int grid_win = 1;
+        int rc = with_graph(c.g, [&](auto G) -> int {
+            using Vc = typename decltype(G)::value_type;
+            if (int e = grid_for(k_spmm_cg<Vc, T, KB>, c.pl.K, &grid_win)) return e;
+            if (c.profile) {
+                if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
+                HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
+            }
+            k_spmm_cg<Vc, T, KB><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part);
+            HIPCHK(hipGetLastError());
+            if (c.profile) {
+                HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
+                ++c.n_prof;
+            }
+            return FJ_OK;
+        });
+        if (rc) return rc;
+        k_fin_spmm<KB><<<1, WG, 0, c.st>>>(grid_win, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        k_update_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(c.g->n, S.X, S.R, S.P, S.Q, c.minv(), S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        k_fin_update_batched<KB><<<1, WG, 0, c.st>>>(grid_vec, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
+    }
+
+    // Iterate until every column is done; out receives the KB control blocks.
+    template <typename T>
+    int run(BState<T>& S, int k, Ctrl* out) {
+        HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        int start[KMAX];
+        int budget = 0;  // launches the iteration caps still allow
+        bool any = false;
+        for (int col = 0; col < k; ++col) {
+            const Ctrl& cc = c.hs->slot(NSLOT)[col];
+            start[col] = cc.iters;
+            if (cc.done == RUNNING) {
+                any = true;
+                budget = std::max(budget, cc.max_iter - cc.iters);
+            }
+        }
+        if (!any) {
+            std::memcpy(out, c.hs->slot(NSLOT), sizeof(Ctrl) * KB);
+            return FJ_OK;
+        }
+        int queued = 0, slot_next = 0;
+        std::deque<int> pending;
+        auto enqueue = [&](int cnt) -> int {
+            for (int t = 0; t < cnt; ++t)
+                if (int rc = iteration(S)) return rc;
+            queued += cnt;
+            const int sl = slot_next++ % NSLOT;
+            HIPCHK(hipMemcpyAsync(c.hs->slot(sl), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipEventRecord(c.hs->ev[sl], c.st));
+            pending.push_back(sl);
+            return FJ_OK;
+        };
+        for (int t = 0; t < 2 && queued < budget; ++t)
+            if (int rc = enqueue(std::min(FIRST_CHUNK, budget - queued))) return rc;
+        while (!pending.empty()) {
+            const int sl = pending.front();
+            pending.pop_front();
+            HIPCHK(hipEventSynchronize(c.hs->ev[sl]));
+            const Ctrl* cs = c.hs->slot(sl);
+            int need = 0;
+            bool running = false;
+            for (int col = 0; col < k; ++col) {
+                if (cs[col].done == RUNNING && cs[col].iters < cs[col].max_iter) {
+                    running = true;
+                    need = std::max(need, std::min(predict(cs[col], start[col]), cs[col].max_iter) - start[col]);
+                }
+            }
+            if (!running || queued >= budget) {
+                HIPCHK(hipStreamSynchronize(c.st));
+                std::memcpy(out, c.hs->slot(pending.empty() ? sl : pending.back()), sizeof(Ctrl) * KB);
+                return FJ_OK;
+            }
+            need = std::min(need, budget);
+            if (need > queued) {
+                if (int rc = enqueue(need - queued)) return rc;
+            } else if (pending.empty()) {
+                if (int rc = enqueue(1)) return rc;
+            }
+        }
+        HIPCHK(hipMemcpyAsync(out, S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        return FJ_OK;
+    }
+
+    int epilogue(BState<double>& S, const double* src, int64_t lds, int k, Ctrl* out) {
+        int grid_win = 1;
+        int rc = with_graph(c.g, [&](auto G) -> int {
+            using Vc = typename decltype(G)::value_type;
+            if (int e = grid_for(k_epilogue_batched<Vc, KB>, c.pl.K, &grid_win)) return e;
+            k_epilogue_batched<Vc, KB><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, k, S.X, src, lds, S.R, S.part,
+                                                                  S.ctrl);
+            HIPCHK(hipGetLastError());
+            return FJ_OK;
+        });
+        if (rc) return rc;
+        k_fin_epilogue_batched<KB><<<1, WG, 0, c.st>>>(grid_win, c.g->n, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        std::memcpy(out, c.hs->slot(NSLOT), sizeof(Ctrl) * KB);
+        return FJ_OK;
+    }
+
+    // Shared outer logic: after an epilogue, decide per column whether it is
+    // finished (certified / converged, or stalled) and which columns restart.
+    // Returns the columns to run again; status[col] is final for the others.
+    uint64_t triage(const Ctrl* cs, int k, const fj_opts& o, bool want_indices, const unsigned* which,
+                    double* rtol, const double* prev_rho, int* status, bool last) {
+        uint64_t again = 0;
+        for (int col = 0; col < k; ++col) {
+            if (status[col] != FJ_ERR_NOT_CONVERGED) continue;  // already final
+            const Ctrl& cc = cs[col];
+            if (cc.done == BREAKDOWN) {
+                status[col] = FJ_ERR_BREAKDOWN;
+                continue;
+            }
+            const double snorm = cc.res[6], rho = cc.res[5];
+            const bool ok = want_indices ? certified(cc, o.eps, which[col])
+                                         : (snorm == 0.0 || rho <= rtol_target(o) * snorm);
+            if (ok) {
+                status[col] = FJ_OK;
+            } else if (cc.done == ITER_CAP || cc.iters >= cc.max_iter) {
+                status[col] = FJ_ERR_NOT_CONVERGED;
+            } else if (last || !(rho < 0.5 * prev_rho[col])) {
+                status[col] = stalled_status(cc, want_indices, which[col]);
+            } else {
+                again |= 1ull << col;
+                double next = rtol[col] * 0.1;
+                if (want_indices && snorm > 0.0)
+                    next = std::min(next, 0.5 * needed_rho(cc, o.eps, which[col]) / snorm);
+                rtol[col] = std::max(next, 1e-16);
+            }
+        }
+        return again;
+    }
+
+    static double rtol_target(const fj_opts& o) { return o.rtol > 0.0 ? o.rtol : o.eps * 1e-2; }
+
+    // FP64 for every column.
+    int solve_fp64(BState<double>& S, const double* src, int64_t lds, int k, int kcheck, const fj_opts& o,
+                   bool want_indices, const unsigned* which, Ctrl* cs, int* status, int* passes) {
+        const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
+        const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
+        double rtol[KMAX], prev_rho[KMAX];
+        for (int col = 0; col < KMAX; ++col) {
+            rtol[col] = rtol_target(o);
+            prev_rho[col] = INFINITY;
+            if (col < k) status[col] = FJ_ERR_NOT_CONVERGED;
+        }
+        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, rtol, max_iter, range_check)) return rc;
+        *passes = 0;
+        for (;;) {
+            ++*passes;
+            if (int rc = run(S, k, cs)) return rc;
+            for (int col = 0; col < kcheck; ++col)
+                if (cs[col].done == BAD_INPUT) return FJ_ERR_OPINION_RANGE;
+            if (int rc = epilogue(S, src, lds, k, cs)) return rc;
+            const uint64_t again = triage(cs, k, o, want_indices, which, rtol, prev_rho, status, *passes >= MAX_PASSES);
+            if (!again) break;
+            for (int col = 0; col < k; ++col) prev_rho[col] = cs[col].res[5];
+            if (int rc = init(S, src, lds, k, kcheck, 1, again, rtol, max_iter, range_check)) return rc;
+        }
+        return FJ_OK;
+    }
+
+    // FJ_MIXED for every column: FP32 inner CG, FP64 refinement per column.
+    int solve_mixed(BState<double>& S, BState<float>& I, const double* src, int64_t lds, int k, int kcheck,
+                    const fj_opts& o, bool want_indices, const unsigned* which, Ctrl* cs, int* status, int* outer) {
+        const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
+        const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
+        const int n = c.g->n;
+        double prev_rho[KMAX];
+        Ctrl ci[KMAX];
+        double tau[KMAX], ones[KMAX];
+        for (int col = 0; col < KMAX; ++col) {
+            tau[col] = 1e-4;
+            ones[col] = 1.0;
+            if (col < k) status[col] = FJ_ERR_NOT_CONVERGED;
+        }
+        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, ones, max_iter, range_check)) return rc;
+        HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        std::memcpy(cs, c.hs->slot(NSLOT), sizeof(Ctrl) * KB);
+        for (int col = 0; col < kcheck; ++col)
+            if (cs[col].done == BAD_INPUT) return FJ_ERR_OPINION_RANGE;
+        for (int col = 0; col < k; ++col) prev_rho[col] = std::sqrt(cs[col].ss);
+        uint64_t active = 0;
+        for (int col = 0; col < k; ++col) {
+            if (cs[col].ss > 0.0) active |= 1ull << col;
+            else status[col] = FJ_OK;  // s = 0: z = 0 exactly
+        }
+        int inner_total = 0;
+        *outer = 0;
+        while (active && *outer < 8 && inner_total < max_iter) {
+            ++*outer;
+            const int mode = *outer == 1 ? 0 : 1;
+            k_mixed_cast_batched<KB><<<grid_vec, WG, 0, c.st>>>(n, S.R, I.R, mode, active, S.ctrl);
+            HIPCHK(hipGetLastError());
+            if (int rc = init(I, nullptr, 0, k, 0, 2, active, tau, max_iter - inner_total, false)) return rc;
+            if (int rc = run(I, k, ci)) return rc;
+            int most = 0;
+            for (int col = 0; col < k; ++col) most = std::max(most, ci[col].iters);
+            inner_total += most;
+            k_mixed_refine_batched<KB><<<grid_vec, WG, 0, c.st>>>(n, S.X, I.X, mode, active, S.ctrl);
+            HIPCHK(hipGetLastError());
+            if (int rc = epilogue(S, src, lds, k, cs)) return rc;
+            uint64_t again = 0;
+            for (int col = 0; col < k; ++col) {
+                if (!((active >> col) & 1ull)) continue;
+                const Ctrl& cc = cs[col];
+                if (ci[col].done == BREAKDOWN) {
+                    status[col] = FJ_ERR_BREAKDOWN;
+                    continue;
+                }
+                const double snorm = cc.res[6], rho = cc.res[5];
+                const bool ok = want_indices ? certified(cc, o.eps, which[col])
+                                             : (snorm == 0.0 || rho <= rtol_target(o) * snorm);
+                if (ok) {
+                    status[col] = FJ_OK;
+                } else if (!(rho < 0.5 * prev_rho[col])) {
+                    status[col] = stalled_status(cc, want_indices, which[col]);
+                } else {
+                    again |= 1ull << col;
+                    const double goal = want_indices ? needed_rho(cc, o.eps, which[col]) : rtol_target(o) * snorm;
+                    tau[col] = std::min(1e-2, std::max(1e-5, 0.5 * goal / rho));
+                    prev_rho[col] = rho;
+                }
+            }
+            active = again;
+        }
+        for (int col = 0; col < k; ++col) {
+            cs[col].iters = inner_total;
+            if ((active >> col) & 1ull) status[col] = FJ_ERR_NOT_CONVERGED;
+        }
+        return FJ_OK;
+    }
+};
+
+// k columns (or Algorithm 1's two right-hand sides) through one Batched<KB>.
+template <int KB>
+int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t lds, int k, double* Z, int64_t ldz,
+                const fj_opts& o, bool want_indices, fj_indices_t* out, fj_info* info) {
+    Batched<KB> B{c};
+    if (int rc = B.setup()) return rc;
+    const bool mixed = o.precision == FJ_MIXED;
+    const bool two = (o.flags & FJ_TWO_SOLVE) && k == 1;
+    Ctrl* ctrls = reinterpret_cast<Ctrl*>(W + wl.ctrl);
+    double* part = reinterpret_cast<double*>(W + wl.part);
+    BState<double> S64{reinterpret_cast<double*>(W + wl.x), reinterpret_cast<double*>(W + wl.r),
+                       mixed ? nullptr : reinterpret_cast<double*>(W + wl.p),
+                       mixed ? nullptr : reinterpret_cast<double*>(W + wl.q), ctrls, part};
+    const double* src = S;
+    int64_t ld = lds;
+    int kk = k, kcheck = k;
+    unsigned which[KMAX];
+    for (int col = 0; col < KMAX; ++col) which[col] = ALL_INDICES;
+    if (two) {
+        // statistics of s (mean, range) with the single-vector init, then the
+        // block [s, s - mean(s)]; only s itself is range-checked.
+        const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
+        k_ctrl_reset<<<1, WG, 0, c.st>>>(ctrls, 1);
+        HIPCHK(hipGetLastError());
+        k_cg_init<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S, lds, S64.X, S64.R, nullptr, c.minv(), 0, part);
+        HIPCHK(hipGetLastError());
+        k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, part, 0, 1.0, max_iter,
+                                       (o.flags & FJ_NO_RANGE_CHECK) ? 0 : 1, ctrls);
+        HIPCHK(hipGetLastError());
+        Ctrl st0{};
+        HIPCHK(hipMemcpyAsync(&st0, ctrls, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        if (st0.done == BAD_INPUT) return FJ_ERR_OPINION_RANGE;
+        double* blk = reinterpret_cast<double*>(W + wl.sblk);
+        k_two_solve_rhs<<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S, lds, ctrls, blk);
+        HIPCHK(hipGetLastError());
+        src = blk;
+        ld = 2;
+        kk = 2;
+        kcheck = 0;
+        which[0] = 1u | 8u;  // z = Solve(s): internal conflict ||L z||^2 and controversy ||z||^2
+        which[1] = 2u | 8u;  // q = Solve(s - mean s): disagreement and polarization ||q||^2
+    }
+    Ctrl cs[KMAX];
+    int status[KMAX];
+    int passes = 0, outer = 0;
+    int rc;
+    if (mixed) {
+        BState<float> S32{reinterpret_cast<float*>(W + wl.x32), reinterpret_cast<float*>(W + wl.r32),
+                          reinterpret_cast<float*>(W + wl.p32), reinterpret_cast<float*>(W + wl.q32), ctrls + KB, part};
+        rc = B.solve_mixed(S64, S32, src, ld, kk, kcheck, o, want_indices, which, cs, status, &outer);
+    } else {
+        rc = B.solve_fp64(S64, src, ld, kk, kcheck, o, want_indices, which, cs, status, &passes);
+    }
+    if (rc) return rc;
+    int worst = FJ_OK;
+    if (two) {
+        const Ctrl &a = cs[0], &b = cs[1];  // a: z = Solve(s), b: q = Solve(s - mean s)
+        const int st = status[0] != FJ_OK ? status[0] : status[1];
+        if (out) {
+            out[0].internal_conflict = a.res[0];
+            out[0].disagreement = b.res[1];
+            out[0].polarization = b.res[3];
+            out[0].controversy = a.res[3];
+            out[0].dc_index = b.res[1] + a.res[3];  // Algorithm 1: D~ + C~
+        }
+        if (info) {
+            info[0].status = st;
+            info[0].iters = std::max(a.iters, b.iters);
+            info[0].passes = mixed ? outer : passes;
+            info[0].outer_iters = mixed ? outer : 0;
+            info[0].rel_residual = a.res[6] > 0.0 ? a.res[5] / a.res[6] : 0.0;
+            info[0].bound[0] = a.bound[0];
+            info[0].bound[1] = b.bound[1];
+            info[0].bound[2] = b.bound[3];
+            info[0].bound[3] = a.bound[3];
+            info[0].bound[4] = std::max(b.bound[1], a.bound[3]);  // a sum of eps-approximations
+        }
+        worst = st;
+        if (Z) {
+            HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, S64.X, sizeof(double) * 2, sizeof(double), c.g->n,
+                                    hipMemcpyDeviceToDevice, c.st));
+        }
+    } else {
+        for (int col = 0; col < k; ++col) {
+            fill_outputs(cs[col], status[col], mixed ? outer : passes, mixed ? outer : 0, out ? out + col : nullptr,
+                         info ? info + col : nullptr);
+            if (worst == FJ_OK && status[col] != FJ_OK) worst = status[col];
+        }
+        if (Z) {
+            HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, S64.X, sizeof(double) * KB, sizeof(double) * k, c.g->n,
+                                    hipMemcpyDeviceToDevice, c.st));
+        }
+    }
+    if (info) {
+        for (int col = 0; col < (two ? 1 : k); ++col)
+            if (int e = c.profile_total(info + col)) return e;
+    }
+    HIPCHK(hipStreamSynchronize(c.st));
+    return worst;
+}
+
+// Any number of columns: blocks of up to KMAX columns.
+int solve_many(const fj_csr* g, const void* plan, int k, const double* S, int64_t lds, double* Z, int64_t ldz,
+               const fj_opts& o, void* ws, size_t ws_bytes, void* stream, bool want_indices, fj_indices_t* out,
+               fj_info* info) {
+    Ctx c{};
+    WsLayout wl{};
+    if (int rc = make_ctx(g, plan, ws, ws_bytes, k, stream, &o, &c, &wl)) return rc;
+    char* W = static_cast<char*>(ws);
+    int worst = FJ_OK;
+    for (int c0 = 0; c0 < k; c0 += KMAX) {
+        const int kc = std::min(KMAX, k - c0);
+        const int kp = block_columns(kc, o.flags);
+        const double* Sc = S + c0;
+        double* Zc = Z ? Z + c0 : nullptr;
+        fj_indices_t* oc = out ? out + c0 : nullptr;
+        fj_info* ic = info ? info + c0 : nullptr;
+        int rc;
+        switch (kp) {
+            case 2: rc = solve_block<2>(c, wl, W, Sc, lds, kc, Zc, ldz, o, want_indices, oc, ic); break;
+            case 4: rc = solve_block<4>(c, wl, W, Sc, lds, kc, Zc, ldz, o, want_indices, oc, ic); break;
+            case 8: rc = solve_block<8>(c, wl, W, Sc, lds, kc, Zc, ldz, o, want_indices, oc, ic); break;
+            case 16: rc = solve_block<16>(c, wl, W, Sc, lds, kc, Zc, ldz, o, want_indices, oc, ic); break;
+            case 32: rc = solve_block<32>(c, wl, W, Sc, lds, kc, Zc, ldz, o, want_indices, oc, ic); break;
+            default: rc = solve_block<64>(c, wl, W, Sc, lds, kc, Zc, ldz, o, want_indices, oc, ic); break;
+        }
+        if (rc == FJ_ERR_HIP || rc == FJ_ERR_OPINION_RANGE || rc == FJ_ERR_WORKSPACE) return rc;
+        if (worst == FJ_OK && rc != FJ_OK) worst = rc;
+    }
+    return worst;
 }
 
 }  // namespace
@@ -618,7 +1064,7 @@ size_t fj_plan_bytes(const fj_csr* g) {
 
 size_t fj_workspace_bytes(const fj_csr* g, int32_t k, const fj_opts* opts) {
     if (check_graph_args(g) || k < 1) return 0;
-    return ws_layout(g, k, opts ? opts->precision : FJ_FP64).total;
+    return ws_layout(g, k, opts ? opts->precision : FJ_FP64, opts ? opts->flags : 0u).total;
 }
 
 int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_bytes, void* stream) {
@@ -690,9 +1136,11 @@ int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int6
              int64_t ldz, const fj_opts* opts, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
     if (int rc = check_graph_args(g)) return rc;
     if (int rc = check_opts(opts)) return rc;
-    if (k != 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
+    if (k < 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
     if (g->n == 0) return FJ_OK;
-    return solve_one(g, plan, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
+    if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
+        return solve_one(g, plan, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
+    return solve_many(g, plan, k, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
 }
 
 int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, int64_t lds,
@@ -700,9 +1148,11 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
                fj_info* info) {
     if (int rc = check_graph_args(g)) return rc;
     if (int rc = check_opts(opts)) return rc;
-    if (k != 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
+    if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
     if (g->n == 0) return FJ_ERR_INVALID_ARG;
-    return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+    if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
+        return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+    return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
 }
 
 }  // extern "C"

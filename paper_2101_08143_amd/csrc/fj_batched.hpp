@@ -1,0 +1,512 @@
+// fj_batched.hpp -- k right-hand sides at once (HIP, gfx950).
+//
+// Vectors are node-major blocks: element (i, c) of X lives at X[i * KB + c],
+// KB = the number of columns rounded up to a power of two (2..64); padding
+// columns hold zeros and converge at once. The sparse pass gives each row a
+// group of KB lanes, lane c owning column c: the group loads up to KB column
+// indices and weights of the row with one coalesced load, broadcasts them
+// lane to lane, and every neighbour j becomes one contiguous KB-wide read of
+// X[j, :] (256 bytes for 64 FP32 columns). The CSR is thus read once per
+// iteration for all k solves, and the gather reads whole rows instead of
+// scattered elements.
+//
+// Every column runs its own CG (own alpha, beta, stopping test) on the shared
+// operator pass. A column's arithmetic is the same whatever else is in the
+// batch: its row sums run over the CSR in order on one lane, and its dot
+// products are reduced over a fixed row-to-workgroup assignment in a fixed
+// order. Results are therefore bitwise identical alone or batched, for the
+// same KB.
+#pragma once
+
+#include "fj_kernels.hpp"
+
+namespace fj {
+
+constexpr int KMAX = 64;       // columns per block
+constexpr int BPART = 16;      // partial sums per (workgroup, column)
+
+// Per-column squared relative tolerances, passed by value to the batched
+// start kernel so that no column's target depends on the others.
+struct ColumnTol {
+    double rtol2[KMAX];
+};
+
+__device__ __forceinline__ double shfl_d(double v, int src, int width) {
+    return __shfl(v, src, width);
+}
+
+// The rows of the workgroup's windows (blockIdx.x, +gridDim.x, ...). Calls
+// op.row(i, c, x_ic, sum_j w_ij (x_ic - x_jc), sum_j w_ij (x_ic - x_jc)^2) for
+// every row i and column c < KB, from lane c of the group that owns the row.
+// A long last row is split over all groups of the workgroup and combined in
+// LDS in group order. lred must hold 2 * WG doubles.
+template <typename T, typename V, typename Acc, int KB, typename Op>
+__device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
+                                             const T* __restrict__ X, Op& op, double* lred) {
+    constexpr int NG = WG / KB;
+    constexpr bool WEIGHTED = !std::is_same<V, Unit>::value;
+    const int lane = threadIdx.x % KB;
+    const int grp = threadIdx.x / KB;
+
+    auto row_sum = [&](int e_begin, int e_end, int e_step, double xi, double& lin, double& sq) {
+        for (int e0 = e_begin; e0 < e_end; e0 += e_step) {
+            const int e = e0 + lane;
+            int jl = 0;
+            double wl = 0.0;
+            if (e < e_end) {
+                jl = g.col[e];
+                wl = weight_at<V>(g.val, e);
+            }
+            const int cnt = min(KB, e_end - e0);
+            int t = 0;
+            for (; t + 4 <= cnt; t += 4) {  // four gathers in flight
+                int j[4];
+                double w[4], xj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    j[u] = __shfl(jl, t + u, KB);
+                    w[u] = WEIGHTED ? shfl_d(wl, t + u, KB) : 1.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xj[u] = static_cast<double>(X[static_cast<int64_t>(j[u]) * KB + lane]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double d = xi - xj[u];
+                    lin += w[u] * d;
+                    if constexpr (Acc::SQ) sq += w[u] * d * d;
+                }
+            }
+            for (; t < cnt; ++t) {
+                const int j = __shfl(jl, t, KB);
+                const double w = WEIGHTED ? shfl_d(wl, t, KB) : 1.0;
+                const double d = xi - static_cast<double>(X[static_cast<int64_t>(j) * KB + lane]);
+                lin += w * d;
+                if constexpr (Acc::SQ) sq += w * d * d;
+            }
+        }
+    };
+
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const WinDesc d = to_scalar(load_raw_desc(desc + k));
+        for (int a = grp; a < d.nrs; a += NG) {
+            const int i = d.r0 + a;
+            const double xi = static_cast<double>(X[static_cast<int64_t>(i) * KB + lane]);
+            double lin = 0.0, sq = 0.0;
+            row_sum(g.row_ptr[i], g.row_ptr[i + 1], KB, xi, lin, sq);
+            op.row(i, lane, xi, lin, sq);
+        }
+        if (d.long_last) {  // workgroup-uniform
+            const int i = d.r1 - 1;
+            const double xi = static_cast<double>(X[static_cast<int64_t>(i) * KB + lane]);
+            double lin = 0.0, sq = 0.0;
+            // group gr takes entry chunks elast + gr*KB, elast + (gr+NG)*KB, ...
+            for (int e0 = d.elast + grp * KB; e0 < d.eend; e0 += NG * KB) row_sum(e0, min(e0 + KB, d.eend), KB, xi, lin, sq);
+            lred[threadIdx.x] = lin;
+            lred[WG + threadIdx.x] = sq;
+            __syncthreads();
+            if (grp == 0) {
+                double L = 0.0, S = 0.0;
+                for (int gr = 0; gr < NG; ++gr) {
+                    L += lred[gr * KB + lane];
+                    S += lred[WG + gr * KB + lane];
+                }
+                op.row(i, lane, xi, L, S);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Per-column workgroup sums of N accumulators: lane c of every group holds
+// the workgroup's share for column c; groups are added in order and the
+// result goes to part[(blockIdx.x * KB + c) * BPART + v].
+template <int N, int KB>
+__device__ __forceinline__ void store_column_partials(const double (&v)[N], double* lred,
+                                                      double* __restrict__ part) {
+    constexpr int NG = WG / KB;
+    static_assert(N * WG <= 12 * WG, "LDS buffer too small");
+    for (int a = 0; a < N; ++a) lred[a * WG + threadIdx.x] = v[a];
+    __syncthreads();
+    if (threadIdx.x < KB) {
+        for (int a = 0; a < N; ++a) {
+            double t = 0.0;
+            for (int gr = 0; gr < NG; ++gr) t += lred[a * WG + gr * KB + threadIdx.x];
+            part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// Per-column totals of N partials over G workgroups, for a one-workgroup
+// finalize kernel: thread t sums column t % KB over workgroups t / KB,
+// t / KB + WG / KB, ...; stripes are then added in order. Column c's totals
+// end in tot[c * N + a] (LDS, KB * N doubles).
+template <int N, int KB>
+__device__ __forceinline__ void total_column_partials(int G, const double* __restrict__ part, double* lred,
+                                                      double* tot) {
+    constexpr int NS = WG / KB;
+    const int c = threadIdx.x % KB, sidx = threadIdx.x / KB;
+    double v[N];
+    for (int a = 0; a < N; ++a) v[a] = 0.0;
+    for (int b = sidx; b < G; b += NS)
+        for (int a = 0; a < N; ++a) v[a] += part[(static_cast<int64_t>(b) * KB + c) * BPART + a];
+    for (int a = 0; a < N; ++a) lred[a * WG + threadIdx.x] = v[a];
+    __syncthreads();
+    if (threadIdx.x < KB) {
+        for (int a = 0; a < N; ++a) {
+            double t = 0.0;
+            for (int s = 0; s < NS; ++s) t += lred[a * WG + s * KB + threadIdx.x];
+            tot[threadIdx.x * N + a] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ row operations
+
+template <typename T, int KB>
+struct OpSpmmCg {  // Q = (I + L) P and per-column p^T q, r^T M^{-1} q, q^T M^{-1} q
+    const T* __restrict__ R;
+    const float* __restrict__ minv;
+    T* __restrict__ Q;
+    double pq = 0.0, rmq = 0.0, qmq = 0.0;
+    __device__ void row(int i, int c, double pi, double lin, double) {
+        const int64_t at = static_cast<int64_t>(i) * KB + c;
+        const T qt = static_cast<T>(pi + lin);
+        Q[at] = qt;
+        const double q = static_cast<double>(qt);
+        const double mq = static_cast<double>(minv[i]) * q;
+        pq += pi * q;
+        rmq += static_cast<double>(R[at]) * mq;
+        qmq += q * mq;
+    }
+};
+
+template <int KB>
+struct OpSpmmEpilogue {  // per column: the sums of OpEpilogue
+    const double* __restrict__ S;
+    int64_t lds;
+    int k;
+    const Ctrl* __restrict__ ctrl;
+    double* __restrict__ R;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    __device__ void row(int i, int c, double zi, double t, double dsq) {
+        const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
+        const double ri = si - zi - t;
+        R[static_cast<int64_t>(i) * KB + c] = ri;
+        const double dm = zi - ctrl[c].mu;
+        const double dz = zi - si;
+        v[0] += t * t;
+        v[1] += dsq;
+        v[2] += dm * dm;
+        v[3] += zi * zi;
+        v[4] += zi;
+        v[5] += si * zi;
+        v[6] += ri * ri;
+        v[7] += zi * ri;
+        v[8] += dz * dz;
+    }
+};
+
+// ------------------------------------------------------------ kernels
+
+template <typename V, typename T, int KB>
+__global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restrict__ desc, int K,
+                                                const T* __restrict__ P, const T* __restrict__ R,
+                                                const float* __restrict__ minv, T* __restrict__ Q,
+                                                double* __restrict__ part) {
+    __shared__ double lred[12 * WG];
+    OpSpmmCg<T, KB> op{R, minv, Q};
+    spmm_windows<T, V, AccLin, KB>(g, desc, K, P, op, lred);
+    const double v[3] = {op.pq, op.rmq, op.qmq};
+    store_column_partials<3, KB>(v, lred, part);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(WG) k_fin_spmm(int G, const double* __restrict__ part, Ctrl* __restrict__ ctrl) {
+    __shared__ double lred[12 * WG];
+    __shared__ double tot[KB * 3];
+    total_column_partials<3, KB>(G, part, lred, tot);
+    if (threadIdx.x < KB) {
+        Ctrl& c = ctrl[threadIdx.x];
+        if (c.done == RUNNING) {
+            const double rz = c.rz, pq = tot[threadIdx.x * 3];
+            if (rz == 0.0) {
+                c.done = CONVERGED;
+            } else if (!(pq > 0.0) || !isfinite(pq)) {
+                c.done = BREAKDOWN;
+            } else {
+                const double alpha = rz / pq;
+                const double rz_next = rz - 2.0 * alpha * tot[threadIdx.x * 3 + 1] +
+                                       alpha * alpha * tot[threadIdx.x * 3 + 2];
+                c.alpha = alpha;
+                c.beta = rz_next / rz;
+            }
+        }
+    }
+}
+
+// Element-wise CG update of every running column; thread t always handles
+// column t % KB (the grid stride is a multiple of KB).
+template <typename T, int KB>
+__global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X, T* __restrict__ R,
+                                                       T* __restrict__ P, const T* __restrict__ Q,
+                                                       const float* __restrict__ minv,
+                                                       double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    __shared__ double lred[12 * WG];
+    const int c = threadIdx.x % KB;
+    const bool run = ctrl[c].done == RUNNING;
+    const double alpha = ctrl[c].alpha, beta = ctrl[c].beta;
+    double v[2] = {0.0, 0.0};
+    const int64_t total = static_cast<int64_t>(n) * KB;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
+    if (run) {
+        for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += stride) {
+            const int i = static_cast<int>(e / KB);
+            T x = X[e], r = R[e], p = P[e];
+            cg_update_elem(alpha, beta, x, r, p, Q[e], minv[i], v);
+            X[e] = x;
+            R[e] = r;
+            P[e] = p;
+        }
+    }
+    store_column_partials<2, KB>(v, lred, part);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(WG) k_fin_update_batched(int G, const double* __restrict__ part,
+                                                           Ctrl* __restrict__ ctrl) {
+    __shared__ double lred[12 * WG];
+    __shared__ double tot[KB * 2];
+    total_column_partials<2, KB>(G, part, lred, tot);
+    if (threadIdx.x < KB) {
+        Ctrl& c = ctrl[threadIdx.x];
+        if (c.done == RUNNING) {
+            const double rz = tot[threadIdx.x * 2], rr = tot[threadIdx.x * 2 + 1];
+            const int it = c.iters + 1;
+            c.iters = it;
+            c.rz = rz;
+            c.rr = rr;
+            c.hist[it % HIST] = rr;
+            if (!isfinite(rr)) c.done = BREAKDOWN;
+            else if (rr <= c.tol2) c.done = CONVERGED;
+            else if (it >= c.max_iter) c.done = ITER_CAP;
+        }
+    }
+}
+
+// Batched CG start. mode 0: X = 0, R = S (zero in padding columns) and the
+// statistics of each column of S; mode 1: restart from the current X with R
+// holding the true residual; mode 2: X = 0, R given. Only columns in `mask`
+// are touched. Partial slots per column: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad
+// count (columns < kcheck only), 5 max of -s, 6 max of s.
+template <typename T, int KB>
+__global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double* __restrict__ S, int64_t lds,
+                                                     T* __restrict__ X, T* __restrict__ R, T* __restrict__ P,
+                                                     const float* __restrict__ minv, int mode, uint64_t mask,
+                                                     int kcheck, double* __restrict__ part) {
+    __shared__ double lred[12 * WG];
+    const int c = threadIdx.x % KB;
+    const bool on = (mask >> c) & 1ull;
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY};  // 5: max of -s, 6: max of s
+    const int64_t total = static_cast<int64_t>(n) * KB;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
+    if (on) {
+        for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += stride) {
+            const int i = static_cast<int>(e / KB);
+            double ri;
+            if (mode == 0) {
+                const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
+                X[e] = T(0);
+                R[e] = static_cast<T>(si);
+                ri = static_cast<double>(R[e]);
+                v[2] += si * si;
+                v[3] += si;
+                if (c < kcheck && !(si >= 0.0 && si <= 1.0)) v[4] += 1.0;
+                v[5] = fmax(v[5], -si);
+                v[6] = fmax(v[6], si);
+            } else {
+                if (mode == 2) X[e] = T(0);
+                ri = static_cast<double>(R[e]);
+            }
+            const T zt = static_cast<T>(static_cast<double>(minv[i]) * ri);
+            if (P != nullptr) P[e] = zt;
+            v[0] += ri * static_cast<double>(zt);
+            v[1] += ri * ri;
+        }
+    }
+    // per-column max of slots 5, 6 over the groups, sums of the others
+    constexpr int NG = WG / KB;
+    for (int a = 0; a < 7; ++a) lred[a * WG + threadIdx.x] = v[a];
+    __syncthreads();
+    if (threadIdx.x < KB) {
+        for (int a = 0; a < 7; ++a) {
+            double t = a < 5 ? 0.0 : -INFINITY;
+            for (int gr = 0; gr < NG; ++gr) {
+                const double u = lred[a * WG + gr * KB + threadIdx.x];
+                t = a < 5 ? t + u : fmax(t, u);
+            }
+            part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a] = t;
+        }
+    }
+}
+
+template <int KB>
+__global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, const double* __restrict__ part,
+                                                         int mode, uint64_t mask, ColumnTol tol, int max_iter,
+                                                         int range_check, Ctrl* __restrict__ ctrl) {
+    __shared__ double lred[12 * WG];
+    __shared__ double tot[KB * 5];
+    __shared__ double mm[KB * 2];
+    total_column_partials<5, KB>(G, part, lred, tot);
+    {  // per-column max of slots 5 (-min s) and 6 (max s), striped like the sums
+        constexpr int NS = WG / KB;
+        const int c = threadIdx.x % KB, sidx = threadIdx.x / KB;
+        double a = -INFINITY, b = -INFINITY;
+        for (int blk = sidx; blk < G; blk += NS) {
+            a = fmax(a, part[(static_cast<int64_t>(blk) * KB + c) * BPART + 5]);
+            b = fmax(b, part[(static_cast<int64_t>(blk) * KB + c) * BPART + 6]);
+        }
+        lred[threadIdx.x] = a;
+        lred[WG + threadIdx.x] = b;
+        __syncthreads();
+        if (threadIdx.x < KB) {
+            double x = -INFINITY, y = -INFINITY;
+            for (int s2 = 0; s2 < NS; ++s2) {
+                x = fmax(x, lred[s2 * KB + threadIdx.x]);
+                y = fmax(y, lred[WG + s2 * KB + threadIdx.x]);
+            }
+            mm[threadIdx.x * 2] = x;
+            mm[threadIdx.x * 2 + 1] = y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < KB && !((mask >> threadIdx.x) & 1ull) && mode == 2)
+        ctrl[threadIdx.x].done = CONVERGED;  // an inner solve runs only the masked columns
+    if (threadIdx.x < KB && ((mask >> threadIdx.x) & 1ull)) {
+        const int c = threadIdx.x;
+        Ctrl& C = ctrl[c];
+        const double rz = tot[c * 5], rr = tot[c * 5 + 1];
+        if (mode == 0) {
+            C.smin = -mm[c * 2];
+            C.smax = mm[c * 2 + 1];
+            C.ss = tot[c * 5 + 2];
+            C.mu = tot[c * 5 + 3] / static_cast<double>(n);
+            C.bad = tot[c * 5 + 4] > 0.0 ? 2 : 0;
+            C.iters = 0;
+            C.max_iter = max_iter;
+        } else if (mode == 2) {
+            C.ss = rr;
+            C.iters = 0;
+            C.max_iter = max_iter;
+            C.bad = 0;
+        }
+        C.tol2 = tol.rtol2[c] * C.ss;
+        C.rz = rz;
+        C.rr = rr;
+        C.hist[C.iters % HIST] = rr;
+        if (c >= k) C.done = CONVERGED;  // padding column
+        else if (range_check && C.bad) C.done = BAD_INPUT;
+        else if (!isfinite(rr)) C.done = BREAKDOWN;
+        else if (rr <= C.tol2) C.done = CONVERGED;
+        else if (C.iters >= C.max_iter) C.done = ITER_CAP;
+        else C.done = RUNNING;
+    }
+}
+
+template <typename V, int KB>
+__global__ void __launch_bounds__(WG) k_epilogue_batched(Csr<V> g, const WinDesc* __restrict__ desc, int K, int k,
+                                                         const double* __restrict__ Z, const double* __restrict__ S,
+                                                         int64_t lds, double* __restrict__ R,
+                                                         double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    __shared__ double lred[12 * WG];
+    OpSpmmEpilogue<KB> op{S, lds, k, ctrl, R};
+    spmm_windows<double, V, AccLinSq, KB>(g, desc, K, Z, op, lred);
+    store_column_partials<9, KB>(op.v, lred, part);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(WG) k_fin_epilogue_batched(int G, int n_nodes, const double* __restrict__ part,
+                                                             Ctrl* __restrict__ ctrl) {
+    __shared__ double lred[12 * WG];
+    __shared__ double tot[KB * 9];
+    total_column_partials<9, KB>(G, part, lred, tot);
+    if (threadIdx.x < KB) {
+        const double* v = tot + threadIdx.x * 9;
+        Ctrl& C = ctrl[threadIdx.x];
+        const double n = static_cast<double>(n_nodes);
+        const double dev = v[4] - n * C.mu;
+        double idx[5];
+        idx[0] = v[0];
+        idx[1] = 0.5 * v[1];
+        idx[2] = fmax(v[2] - dev * dev / n, 0.0);
+        idx[3] = v[3];
+        idx[4] = v[5];
+        const double rho = sqrt(v[6]);
+        for (int c = 0; c < 5; ++c) C.res[c] = idx[c];
+        C.res[5] = rho;
+        C.res[6] = sqrt(C.ss);
+        C.res[7] = v[8];
+        C.res[8] = v[4];
+        C.res[9] = v[7];
+        const double rhos[4] = {rho, 0.5 * rho, rho, rho};  // see k_fin_epilogue
+        for (int c = 0; c < 4; ++c) {
+            const double rx = sqrt(idx[c]);
+            const double rh = rhos[c];
+            C.bound[c] = (rx > rh) ? rh * (2.0 * rx + rh) / ((rx - rh) * (rx - rh)) + 1e-13 : INFINITY;
+        }
+        const double a = (sqrt(idx[3]) + rho) * rho;
+        C.bound[4] = (idx[4] > a) ? a / (idx[4] - a) + 1e-13 : INFINITY;
+    }
+}
+
+// FJ_MIXED, batched: r32 = f32(r / ||r||) and z += ||r|| d per column (mode
+// as in k_mixed_cast); columns outside `mask` are left alone.
+template <int KB>
+__global__ void __launch_bounds__(WG) k_mixed_cast_batched(int n, const double* __restrict__ R64,
+                                                           float* __restrict__ R32, int mode, uint64_t mask,
+                                                           const Ctrl* __restrict__ ctrl) {
+    const int c = threadIdx.x % KB;
+    const double rho = mode == 0 ? sqrt(ctrl[c].ss) : ctrl[c].res[5];
+    const double inv = (((mask >> c) & 1ull) && rho > 0.0) ? 1.0 / rho : 0.0;
+    const int64_t total = static_cast<int64_t>(n) * KB;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += static_cast<int64_t>(gridDim.x) * WG)
+        R32[e] = static_cast<float>(R64[e] * inv);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(WG) k_mixed_refine_batched(int n, double* __restrict__ Z, const float* __restrict__ D,
+                                                             int mode, uint64_t mask, const Ctrl* __restrict__ ctrl) {
+    const int c = threadIdx.x % KB;
+    if (!((mask >> c) & 1ull)) return;
+    const double rho = mode == 0 ? sqrt(ctrl[c].ss) : ctrl[c].res[5];
+    const int64_t total = static_cast<int64_t>(n) * KB;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += static_cast<int64_t>(gridDim.x) * WG)
+        Z[e] += rho * static_cast<double>(D[e]);
+}
+
+// Gather columns of a node-major block into another (different leading
+// dimensions; padding columns of the destination are zeroed).
+__global__ void __launch_bounds__(WG) k_copy_block(int n, int k, int kd, const double* __restrict__ src,
+                                                   int64_t lds, double* __restrict__ dst, int64_t ldd) {
+    const int64_t total = static_cast<int64_t>(n) * kd;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += static_cast<int64_t>(gridDim.x) * WG) {
+        const int64_t i = e / kd;
+        const int c = static_cast<int>(e % kd);
+        dst[i * ldd + c] = c < k ? src[i * lds + c] : 0.0;
+    }
+}
+
+// Algorithm 1 literally (FJ_TWO_SOLVE): column 1 of the block is the centred
+// opinion vector s - mean(s) (Algorithm 1's second right-hand side), column 0 s.
+__global__ void __launch_bounds__(WG) k_two_solve_rhs(int n, const double* __restrict__ s, int64_t lds,
+                                                      const Ctrl* __restrict__ stats, double* __restrict__ dst) {
+    const double mu = stats->mu;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        const double si = s[static_cast<int64_t>(i) * lds];
+        dst[static_cast<int64_t>(i) * 2] = si;
+        dst[static_cast<int64_t>(i) * 2 + 1] = si - mu;
+    }
+}
+
+}  // namespace fj

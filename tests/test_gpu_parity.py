@@ -250,3 +250,112 @@ def test_full_size_workloads(torch_fj, name, precision):
     assert diff <= (zinfo[0].rel_residual + 1e-13) * np.linalg.norm(s)
     del G
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- k columns
+
+def _block(n, k, seed):
+    kinds = ["uniform", "exp", "pareto"]
+    return W.opinion_block(n, [kinds[c % 3] for c in range(k)], seed)
+
+
+@pytest.mark.parametrize("k", [2, 3, 16, 64, 70])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_indices_match_oracle(torch_fj, graphs, k, precision):
+    """k opinion vectors in one call (one CSR pass per iteration for all of
+    them): every column's five indices within 1e-6 of the oracle."""
+    torch, fj = torch_fj
+    g, G = graphs["cl50k_f32"]
+    S = _block(g.n, k, 100 + k)
+    say(f"batched indices k={k} {precision}")
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(eps=EPS, precision=prec),
+                                    check=False)
+    assert rc == fj.FJ_OK, [fj.info_dict(i) for i in infos if i.status != 0][:2]
+    for c in range(k) if k <= 16 else range(0, k, 7):
+        ref, _, _ = O.indices(g, S[:, c])
+        for j, name in enumerate(NAMES):
+            err = abs(vals[c][name] - ref[name]) / abs(ref[name])
+            assert err <= EPS, (c, name, err)
+            assert err <= infos[c].bound[j] + 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_solve_matches_oracle(torch_fj, graphs, precision):
+    torch, fj = torch_fj
+    g, G = graphs["cl100k_unit"]
+    S = _block(g.n, 5, 7)
+    say(f"batched solve {precision}")
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    Z, infos, rc = fj.fj_solve(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(rtol=1e-11, precision=prec))
+    Z = Z.cpu().numpy()
+    for c in range(5):
+        zref, _ = O.solve(g, S[:, c], rtol=1e-14)
+        assert infos[c].rel_residual <= 1e-11
+        assert np.linalg.norm(Z[:, c] - zref) <= (infos[c].rel_residual + 1e-13) * np.linalg.norm(S[:, c])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_column_alone_equals_column_in_mix(torch_fj, graphs, precision):
+    """A column's result does not depend on the other columns of its block:
+    alone (the rest zero) or among 63 others, bitwise."""
+    torch, fj = torch_fj
+    g, G = graphs["cl50k_f32"]
+    S = _block(g.n, 64, 55)
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    o = fj.make_opts(precision=prec)
+    say(f"alone vs mix {precision}")
+    mix, _, _ = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), o, check=False)
+    zmix = fj.fj_solve(G, torch.from_numpy(S).to("cuda:0"), o, check=False)[0].cpu().numpy()
+    for c in (0, 17, 63):
+        A = np.zeros_like(S)
+        A[:, c] = S[:, c]
+        alone, _, _ = fj.fj_indices(G, torch.from_numpy(A).to("cuda:0"), o, check=False)
+        assert alone[c] == mix[c], c
+        zal = fj.fj_solve(G, torch.from_numpy(A).to("cuda:0"), o, check=False)[0].cpu().numpy()
+        assert np.array_equal(zal[:, c], zmix[:, c])
+
+
+@pytest.mark.parametrize("name", ["ba3000", "cl50k_f32", "isolated9000"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_solve_literal_algorithm(torch_fj, graphs, name, precision):
+    """FJ_TWO_SOLVE: Algorithm 1 as printed (solves for s and for s - mean(s);
+    D and P from the second, C_I and C from the first, I_dc = D + C)."""
+    torch, fj = torch_fj
+    g, G = graphs[name]
+    s = W.opinions("exp", g.n, 31)
+    say(f"two-solve {name} {precision}")
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(s).to("cuda:0"),
+                                    fj.make_opts(eps=EPS, precision=prec, flags=fj.FJ_TWO_SOLVE), check=False)
+    assert rc == fj.FJ_OK, fj.info_dict(infos[0])
+    ref, _, _ = O.indices(g, s)
+    for j, k in enumerate(NAMES):
+        err = abs(vals[0][k] - ref[k]) / abs(ref[k])
+        assert err <= EPS, (k, err)
+        assert err <= infos[0].bound[j] + 1e-12
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_full_size_batched_k64(torch_fj, precision):
+    """The 1M-node Chung-Lu graph with k = 64 opinion vectors (21 uniform, 21
+    exponential, 22 Pareto, min-max scaled): all columns certified; sampled
+    columns checked against the oracle."""
+    torch, fj = torch_fj
+    g, _, _ = W.workload("cl1m")
+    S = W.opinion_block(g.n, ["uniform"] * 21 + ["exp"] * 21 + ["pareto"] * 22, 2004)
+    say(f"full k64 {precision}")
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(eps=EPS, precision=prec),
+                                    check=False)
+    assert rc == fj.FJ_OK
+    for c in (0, 20, 21, 41, 42, 63):
+        say(f"oracle column {c}")
+        ref, _, _ = O.indices(g, S[:, c])
+        for j, k in enumerate(NAMES):
+            err = abs(vals[c][k] - ref[k]) / abs(ref[k])
+            assert err <= EPS, (c, k, err)
+    del G
+    torch.cuda.empty_cache()
