@@ -40,6 +40,72 @@ def spmv_bytes(n: int, nnz: int, val_bytes: int) -> int:
     return nnz * (4 + val_bytes) + 4 * (n + 1) + 8 * n + 8 * n + 4 * n + 8 * n
 
 
+def spmm_bytes(n: int, nnz: int, val_bytes: int, kb: int, elem: int) -> int:
+    """Algorithmic bytes of one batched SpMM launch (k_spmm_cg) for kb columns of
+    `elem`-byte values: col and val once, row_ptr once, each row's block of P
+    read once (ideal gather), R read, Q written, the preconditioner once."""
+    return nnz * (4 + val_bytes) + 4 * (n + 1) + 3 * n * kb * elem + 4 * n
+
+
+def batched_forms(args, fj, W, torch, dev):
+    """The 1M-node Chung-Lu graph with k = 64 opinion vectors (21 uniform, 21
+    exponential, 22 Pareto, min-max scaled) in one call, FP64 and mixed,
+    against 64 sequential single-vector FP64 calls."""
+    g, _, spec = W.workload("cl1m")
+    S = W.opinion_block(g.n, ["uniform"] * 21 + ["exp"] * 21 + ["pareto"] * 22, 2004)
+    G = fj.Graph.from_csr(g, device=dev, validate=False)
+    Sd = torch.from_numpy(S).to(dev)
+    out = {}
+    for name, prec in (("batched64_fp64", fj.FJ_FP64), ("batched64_mixed", fj.FJ_MIXED)):
+        o = fj.make_opts(eps=args.eps, precision=prec)
+        po = fj.make_opts(eps=args.eps, precision=prec, flags=fj.FJ_PROFILE)
+        ws = G.workspace(64, o)
+        fj.fj_indices(G, Sd, o, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms, launches = 0.0, 0
+        for _ in range(args.batched_steps):
+            vals, infos, rc = fj.fj_indices(G, Sd, po, ws=ws)
+            ms += infos[0].ms_spmv
+            launches += infos[0].n_spmv
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.batched_steps
+        elem = 4 if prec == fj.FJ_MIXED else 8
+        b = spmm_bytes(g.n, g.nnz, 0, 64, elem)
+        avg = ms / max(launches, 1)
+        out[name] = {
+            "description": f"k=64 opinion vectors of the 1M-node Chung-Lu graph per call, "
+                           f"{'FP32 inner / FP64 refined' if prec == fj.FJ_MIXED else 'FP64'}",
+            "value": 64.0 / el,
+            "unit": "solves/s",
+            "ms_per_call": 1e3 * el,
+            "all_certified": bool(rc == fj.FJ_OK),
+            "iters_max": max(i.iters for i in infos),
+            "spmm_avg_launch_ms": avg,
+            "spmm_achieved_GBs": b / (avg * 1e-3) / 1e9 if avg > 0 else None,
+            "spmm_algorithmic_bytes_per_launch": b,
+        }
+        print(f"[bench] {name}: {1e3 * el:.1f} ms per call", file=sys.stderr, flush=True)
+    # the plain comparison: the same 64 vectors one at a time in FP64
+    o = fj.make_opts(eps=args.eps)
+    ws = G.workspace(1, o)
+    cols = [torch.from_numpy(S[:, c].copy()).to(dev) for c in range(64)]
+    fj.fj_indices(G, cols[0], o, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(64):
+        fj.fj_indices(G, cols[c], o, ws=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["sequential64_fp64"] = {"description": "the same 64 vectors, one fp64 call each",
+                                "value": 64.0 / el, "unit": "solves/s", "ms_total": 1e3 * el}
+    for name in ("batched64_fp64", "batched64_mixed"):
+        out[name]["speedup_vs_sequential_fp64"] = out[name]["value"] / out["sequential64_fp64"]["value"]
+    del G
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +114,8 @@ def main():
     ap.add_argument("--workload", default="cl4m", choices=sorted(WORKLOAD_META))
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=3,
+                    help="timed k=64 batched calls on the 1M-node graph (0 = skip that form)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -170,6 +238,9 @@ def main():
             },
         },
     }
+
+    if args.batched_steps > 0:
+        result["forms"].update(batched_forms(args, fj, W, torch, dev))
 
     if args.cpu_solves > 0:
         from oracle import sparse as O

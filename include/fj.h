@@ -166,6 +166,65 @@ int fj_indices(const fj_csr *g, const void *plan, int32_t k, const double *S, in
                const fj_opts *opts, void *ws, size_t ws_bytes, void *stream,
                fj_indices_t *out, fj_info *info);
 
+/* ---- serving ------------------------------------------------------------ */
+/*
+ * A continuous-batching server for index requests on resident graphs
+ * (Algorithm 1 for many opinion vectors arriving over time, FP64). Graphs and
+ * plans stay caller-owned on the device. Each graph with work gets a block of
+ * CG state for `block_columns` opinion vectors, carved from the caller's HBM
+ * arena; a graph whose block does not fit waits until another block is
+ * released. A request of k <= block_columns vectors is admitted when k
+ * columns of its graph's block are free, while the other columns keep
+ * iterating (continuous batching). Blocks replay HIP graphs of captured CG
+ * iterations on one stream per graph, so different graphs overlap on the
+ * device. Every column is certified to eps exactly as fj_indices would, and
+ * its result does not depend on the other requests in its block.
+ * The server is driven by one host thread calling fj_server_step.
+ */
+typedef struct fj_server fj_server;
+
+typedef struct fj_server_opts {
+    void *arena;                /* device memory for the blocks, 256-byte aligned (caller-owned) */
+    size_t arena_bytes;
+    int32_t block_columns;      /* 16 or 64 opinion vectors per graph block */
+    int32_t iters_per_replay;   /* CG iterations per captured HIP graph (e.g. 8) */
+    double eps;                 /* certified relative error of every index, in (0, 1/2) */
+    int32_t max_iter;           /* CG iterations per column over all passes; 0 = 2000 */
+    int32_t reserved;           /* must be 0 */
+} fj_server_opts;
+
+typedef struct fj_server_done {
+    uint64_t request_id;
+    int32_t graph_id;
+    int32_t status;             /* FJ_OK when every vector of the request is certified */
+    double latency_ms;          /* from fj_server_submit to the step that retired the request */
+} fj_server_done;
+
+/* Device bytes of one block for a graph of n nodes. */
+size_t fj_server_block_bytes(int32_t n, int32_t block_columns);
+
+int fj_server_create(const fj_server_opts *opts, fj_server **out);
+
+/* Waits for all device work of the server, then frees its host state and streams. */
+int fj_server_destroy(fj_server *srv);
+
+/* Register a prepared graph (fj_prepare) that stays resident; *graph_id receives its id. */
+int fj_server_add_graph(fj_server *srv, const fj_csr *g, const void *plan, int32_t *graph_id);
+
+/*
+ * Queue a request: k opinion vectors S (device, node-major, leading dimension
+ * lds >= k, caller-owned until the request completes). out and info are host
+ * arrays of k entries filled when the request completes (info may be NULL).
+ */
+int fj_server_submit(fj_server *srv, int32_t graph_id, int32_t k, const double *S, int64_t lds,
+                     fj_indices_t *out, fj_info *info, uint64_t *request_id);
+
+/* One non-blocking scheduling round; *busy_blocks = blocks with work in flight. */
+int fj_server_step(fj_server *srv, int32_t *busy_blocks);
+
+/* Completed requests since the last poll (up to max); *count receives how many. */
+int fj_server_poll(fj_server *srv, fj_server_done *done, int32_t max, int32_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -745,13 +745,13 @@ struct Batched {
         int rc = with_graph(c.g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
             if (int e = grid_for(k_epilogue_batched<Vc, KB>, c.pl.K, &grid_win)) return e;
-            k_epilogue_batched<Vc, KB><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, k, S.X, src, lds, S.R, S.part,
-                                                                  S.ctrl);
+            k_epilogue_batched<Vc, KB><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, k, ALL, S.X, src, lds, S.R,
+                                                                  S.part, S.ctrl);
             HIPCHK(hipGetLastError());
             return FJ_OK;
         });
         if (rc) return rc;
-        k_fin_epilogue_batched<KB><<<1, WG, 0, c.st>>>(grid_win, c.g->n, S.part, S.ctrl);
+        k_fin_epilogue_batched<KB><<<1, WG, 0, c.st>>>(grid_win, c.g->n, ALL, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
@@ -1027,6 +1027,8 @@ int solve_many(const fj_csr* g, const void* plan, int k, const double* S, int64_
     return worst;
 }
 
+#include "fj_server.hpp"
+
 }  // namespace
 
 // ==================================================================== C ABI
@@ -1153,6 +1155,117 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
     if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
         return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
     return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+}
+
+size_t fj_server_block_bytes(int32_t n, int32_t block_columns) {
+    if (n < 1 || (block_columns != 16 && block_columns != 64)) return 0;
+    return block_bytes(n, block_columns);
+}
+
+int fj_server_create(const fj_server_opts* opts, fj_server** out) {
+    if (!opts || !out || opts->reserved != 0) return FJ_ERR_INVALID_ARG;
+    if (opts->block_columns != 16 && opts->block_columns != 64) return FJ_ERR_INVALID_ARG;
+    if (opts->iters_per_replay < 1 || opts->iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
+    if (!(opts->eps > 0.0 && opts->eps < 0.5) || opts->max_iter < 0) return FJ_ERR_INVALID_ARG;
+    if (!opts->arena || !aligned(opts->arena) || opts->arena_bytes == 0) return FJ_ERR_WORKSPACE;
+    Server* s = new Server();
+    s->o = *opts;
+    s->arena = static_cast<char*>(opts->arena);
+    s->free_list[0] = opts->arena_bytes / ALIGN * ALIGN;
+    if (int rc = current_device(&s->device)) {
+        delete s;
+        return rc;
+    }
+    *out = reinterpret_cast<fj_server*>(s);
+    return FJ_OK;
+}
+
+int fj_server_destroy(fj_server* srv) {
+    if (!srv) return FJ_ERR_INVALID_ARG;
+    Server* s = reinterpret_cast<Server*>(srv);
+    int status = FJ_OK;
+    for (auto& G : s->graphs) {
+        if (G.blk)
+            if (int rc = release_block(*s, G)) status = rc;
+        if (G.st) {
+            const hipError_t e = hipStreamDestroy(G.st);
+            if (e != hipSuccess && status == FJ_OK) {
+                set_error("hipStreamDestroy", e);
+                status = FJ_ERR_HIP;
+            }
+        }
+    }
+    delete s;
+    return status;
+}
+
+int fj_server_add_graph(fj_server* srv, const fj_csr* g, const void* plan, int32_t* graph_id) {
+    if (!srv || !graph_id) return FJ_ERR_INVALID_ARG;
+    if (int rc = check_graph_args(g)) return rc;
+    if (g->n < 1) return FJ_ERR_INVALID_ARG;
+    if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
+    Server* s = reinterpret_cast<Server*>(srv);
+    ServerGraph G;
+    G.g = *g;
+    G.plan = plan;
+    G.pl = plan_layout(g);
+    HIPCHK(hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking));
+    s->graphs.push_back(std::move(G));
+    *graph_id = static_cast<int32_t>(s->graphs.size() - 1);
+    return FJ_OK;
+}
+
+int fj_server_submit(fj_server* srv, int32_t graph_id, int32_t k, const double* S, int64_t lds, fj_indices_t* out,
+                     fj_info* info, uint64_t* request_id) {
+    if (!srv || !S || !out || !request_id) return FJ_ERR_INVALID_ARG;
+    Server* s = reinterpret_cast<Server*>(srv);
+    if (graph_id < 0 || graph_id >= static_cast<int32_t>(s->graphs.size())) return FJ_ERR_INVALID_ARG;
+    if (k < 1 || k > s->o.block_columns || lds < k) return FJ_ERR_INVALID_ARG;
+    ServerGraph& G = s->graphs[graph_id];
+    if (block_bytes(G.g.n, s->o.block_columns) > s->o.arena_bytes) return FJ_ERR_WORKSPACE;  // could never run
+    ServerRequest r;
+    r.id = s->next_id++;
+    r.gid = graph_id;
+    r.k = k;
+    r.S = S;
+    r.lds = lds;
+    r.out = out;
+    r.info = info;
+    r.t_submit = std::chrono::steady_clock::now();
+    s->requests[r.id] = r;
+    G.queue.push_back(r.id);
+    *request_id = r.id;
+    return FJ_OK;
+}
+
+int fj_server_step(fj_server* srv, int32_t* busy_blocks) {
+    if (!srv) return FJ_ERR_INVALID_ARG;
+    Server* s = reinterpret_cast<Server*>(srv);
+    int busy = 0;
+    const int rc = s->o.block_columns == 64 ? server_step_kb<64>(*s, &busy) : server_step_kb<16>(*s, &busy);
+    if (busy_blocks) *busy_blocks = busy;
+    return rc;
+}
+
+int fj_server_poll(fj_server* srv, fj_server_done* done, int32_t max, int32_t* count) {
+    if (!srv || !count || (max > 0 && !done)) return FJ_ERR_INVALID_ARG;
+    Server* s = reinterpret_cast<Server*>(srv);
+    int32_t n = 0;
+    while (n < max && !s->completed.empty()) {
+        const uint64_t rid = s->completed.front();
+        s->completed.pop_front();
+        auto it = s->requests.find(rid);
+        if (it == s->requests.end()) continue;
+        const ServerRequest& r = it->second;
+        done[n].request_id = rid;
+        done[n].graph_id = r.gid;
+        done[n].status = r.status;
+        done[n].latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+        s->requests.erase(it);
+        ++n;
+    }
+    *count = n;
+    return FJ_OK;
 }
 
 }  // extern "C"

@@ -183,17 +183,18 @@ struct OpSpmmCg {  // Q = (I + L) P and per-column p^T q, r^T M^{-1} q, q^T M^{-
 };
 
 template <int KB>
-struct OpSpmmEpilogue {  // per column: the sums of OpEpilogue
+struct OpSpmmEpilogue {  // per column: the sums of OpEpilogue; R is written for columns in mask only
     const double* __restrict__ S;
     int64_t lds;
     int k;
+    uint64_t mask;
     const Ctrl* __restrict__ ctrl;
     double* __restrict__ R;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     __device__ void row(int i, int c, double zi, double t, double dsq) {
         const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
         const double ri = si - zi - t;
-        R[static_cast<int64_t>(i) * KB + c] = ri;
+        if ((mask >> c) & 1ull) R[static_cast<int64_t>(i) * KB + c] = ri;
         const double dm = zi - ctrl[c].mu;
         const double dz = zi - si;
         v[0] += t * t;
@@ -416,22 +417,23 @@ __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, co
 
 template <typename V, int KB>
 __global__ void __launch_bounds__(WG) k_epilogue_batched(Csr<V> g, const WinDesc* __restrict__ desc, int K, int k,
-                                                         const double* __restrict__ Z, const double* __restrict__ S,
-                                                         int64_t lds, double* __restrict__ R,
-                                                         double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+                                                         uint64_t mask, const double* __restrict__ Z,
+                                                         const double* __restrict__ S, int64_t lds,
+                                                         double* __restrict__ R, double* __restrict__ part,
+                                                         const Ctrl* __restrict__ ctrl) {
     __shared__ double lred[12 * WG];
-    OpSpmmEpilogue<KB> op{S, lds, k, ctrl, R};
+    OpSpmmEpilogue<KB> op{S, lds, k, mask, ctrl, R};
     spmm_windows<double, V, AccLinSq, KB>(g, desc, K, Z, op, lred);
     store_column_partials<9, KB>(op.v, lred, part);
 }
 
 template <int KB>
-__global__ void __launch_bounds__(WG) k_fin_epilogue_batched(int G, int n_nodes, const double* __restrict__ part,
-                                                             Ctrl* __restrict__ ctrl) {
+__global__ void __launch_bounds__(WG) k_fin_epilogue_batched(int G, int n_nodes, uint64_t mask,
+                                                             const double* __restrict__ part, Ctrl* __restrict__ ctrl) {
     __shared__ double lred[12 * WG];
     __shared__ double tot[KB * 9];
     total_column_partials<9, KB>(G, part, lred, tot);
-    if (threadIdx.x < KB) {
+    if (threadIdx.x < KB && ((mask >> threadIdx.x) & 1ull)) {
         const double* v = tot + threadIdx.x * 9;
         Ctrl& C = ctrl[threadIdx.x];
         const double n = static_cast<double>(n_nodes);
@@ -483,6 +485,41 @@ __global__ void __launch_bounds__(WG) k_mixed_refine_batched(int n, double* __re
     const int64_t total = static_cast<int64_t>(n) * KB;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += static_cast<int64_t>(gridDim.x) * WG)
         Z[e] += rho * static_cast<double>(D[e]);
+}
+
+// Zero `words` doubles (a kernel rather than a memset, so it can be captured).
+__global__ void __launch_bounds__(WG) k_fill_zero(double* __restrict__ p, int64_t words) {
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < words; e += static_cast<int64_t>(gridDim.x) * WG)
+        p[e] = 0.0;
+}
+
+// Set the done state of the columns in mask.
+__global__ void k_ctrl_set_done(Ctrl* __restrict__ ctrl, int count, uint64_t mask, int value) {
+    const int c = threadIdx.x;
+    if (c < count && ((mask >> c) & 1ull)) ctrl[c].done = value;
+}
+
+// Clear the control blocks of the columns in mask (the others keep running).
+__global__ void k_ctrl_reset_masked(Ctrl* __restrict__ ctrl, int count, uint64_t mask) {
+    constexpr int words = static_cast<int>(sizeof(Ctrl) / sizeof(uint32_t));
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < words * count; i += gridDim.x * blockDim.x) {
+        const int c = i / words;
+        if ((mask >> c) & 1ull) reinterpret_cast<uint32_t*>(ctrl)[i] = 0u;
+    }
+}
+
+// Scatter the k columns of a request into the slots slot[0..k) of a block.
+struct SlotMap {
+    int slot[KMAX];
+};
+__global__ void __launch_bounds__(WG) k_scatter_columns(int n, int k, const double* __restrict__ src, int64_t lds,
+                                                        SlotMap map, double* __restrict__ dst, int kb) {
+    const int64_t total = static_cast<int64_t>(n) * k;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += static_cast<int64_t>(gridDim.x) * WG) {
+        const int64_t i = e / k;
+        const int c = static_cast<int>(e % k);
+        dst[i * kb + map.slot[c]] = src[i * lds + c];
+    }
 }
 
 // Gather columns of a node-major block into another (different leading

@@ -40,7 +40,9 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
-           "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_indices")
+           "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_indices", "fj_server_block_bytes",
+           "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
+           "fj_server_step", "fj_server_poll")
 
 
 class fj_csr(ctypes.Structure):
@@ -62,6 +64,17 @@ class fj_info(ctypes.Structure):
                 ("outer_iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("bound", ctypes.c_double * 5), ("ms_spmv", ctypes.c_double),
                 ("n_spmv", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class fj_server_opts(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("block_columns", ctypes.c_int32),
+                ("iters_per_replay", ctypes.c_int32), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class fj_server_done(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("graph_id", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("latency_ms", ctypes.c_double)]
 
 
 class FJError(RuntimeError):
@@ -100,7 +113,16 @@ def lib():
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
                                  P(fj_info)]
-        for name in ("fj_prepare", "fj_apply", "fj_solve", "fj_indices"):
+        L.fj_server_block_bytes.argtypes = [i32, i32]
+        L.fj_server_block_bytes.restype = sz
+        L.fj_server_create.argtypes = [P(fj_server_opts), P(vp)]
+        L.fj_server_destroy.argtypes = [vp]
+        L.fj_server_add_graph.argtypes = [vp, P(fj_csr), vp, P(i32)]
+        L.fj_server_submit.argtypes = [vp, i32, i32, vp, i64, P(fj_indices_t), P(fj_info), P(ctypes.c_uint64)]
+        L.fj_server_step.argtypes = [vp, P(i32)]
+        L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
+        for name in ("fj_prepare", "fj_apply", "fj_solve", "fj_indices", "fj_server_create", "fj_server_destroy",
+                     "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -259,3 +281,93 @@ def info_dict(inf: fj_info) -> dict:
     return dict(status=inf.status, iters=inf.iters, passes=inf.passes, outer_iters=inf.outer_iters,
                 rel_residual=inf.rel_residual, bound=list(inf.bound), ms_spmv=inf.ms_spmv,
                 n_spmv=inf.n_spmv)
+
+
+class Server:
+    """Continuous-batching server (fj_server_* in include/fj.h). The arena is
+    one torch allocation; requests keep their opinion tensors alive here
+    until they complete."""
+
+    def __init__(self, arena_bytes, block_columns=16, iters_per_replay=8, eps=1e-6, max_iter=0, device="cuda"):
+        import torch
+        self.arena = _aligned_empty(torch, arena_bytes, device)
+        self.opts = fj_server_opts(arena=self.arena.data_ptr(), arena_bytes=int(arena_bytes),
+                                   block_columns=block_columns, iters_per_replay=iters_per_replay, eps=eps,
+                                   max_iter=max_iter, reserved=0)
+        self.handle = ctypes.c_void_p()
+        rc = lib().fj_server_create(ctypes.byref(self.opts), ctypes.byref(self.handle))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_server_create")
+        self.graphs = []
+        self.pending = {}
+
+    @staticmethod
+    def block_bytes(n, block_columns=16):
+        return lib().fj_server_block_bytes(int(n), int(block_columns))
+
+    def add_graph(self, graph: Graph) -> int:
+        gid = ctypes.c_int32()
+        rc = lib().fj_server_add_graph(self.handle, ctypes.byref(graph.csr), _ptr(graph.plan), ctypes.byref(gid))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_server_add_graph")
+        self.graphs.append(graph)
+        return gid.value
+
+    def submit(self, gid, S) -> int:
+        """S: device float64 tensor, n or n x k (k <= block_columns)."""
+        S2, k, lds = _check_block(self.graphs[gid], S, "S")
+        out = (fj_indices_t * k)()
+        info = (fj_info * k)()
+        rid = ctypes.c_uint64()
+        rc = lib().fj_server_submit(self.handle, gid, k, _ptr(S2), lds, out, info, ctypes.byref(rid))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_server_submit")
+        self.pending[rid.value] = (S2, out, info, k)
+        return rid.value
+
+    def step(self) -> int:
+        busy = ctypes.c_int32()
+        rc = lib().fj_server_step(self.handle, ctypes.byref(busy))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_server_step")
+        return busy.value
+
+    def poll(self, max_items=256):
+        """Completed requests: list of dicts with id, graph, status, latency_ms, values, infos."""
+        done = (fj_server_done * max_items)()
+        cnt = ctypes.c_int32()
+        rc = lib().fj_server_poll(self.handle, done, max_items, ctypes.byref(cnt))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_server_poll")
+        res = []
+        for d in done[:cnt.value]:
+            S2, out, info, k = self.pending.pop(d.request_id)
+            res.append(dict(id=d.request_id, graph=d.graph_id, status=d.status, latency_ms=d.latency_ms,
+                            values=[{nm: getattr(out[c], nm) for nm in INDEX_NAMES} for c in range(k)],
+                            infos=[info_dict(info[c]) for c in range(k)]))
+        return res
+
+    def drain(self, timeout_s=300.0):
+        """Step until every submitted request has completed; returns their results."""
+        import time
+        t0 = time.perf_counter()
+        results = []
+        while self.pending:
+            self.step()
+            results.extend(self.poll())
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"{len(self.pending)} requests still pending")
+        return results
+
+    def close(self):
+        if self.handle:
+            rc = lib().fj_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            if rc != FJ_OK:
+                raise FJError(rc, "fj_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+"""The continuous-batching server through the C ABI: results certified and
+matching the oracle, each request's result bitwise the same alone and in the
+mix, admission by HBM footprint, error paths."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sparse as O
+from paper_2101_08143_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_08143_amd import fj
+    graphs = [W.barabasi_albert(3000, 3, 11), W.chung_lu(50_000, 2.2, 30.0, 15, weighted=True),
+              W.chung_lu(100_000, 2.1, 20.0, 14), W.random_graph(400, 0.03, 13, weighted=True)]
+    G = []
+    for g in graphs:
+        say(f"prepare n={g.n}")
+        G.append(fj.Graph.from_csr(g, device="cuda:0"))
+    rng = np.random.default_rng(9)
+    reqs = []
+    for r in range(40):
+        gi = int(rng.integers(0, len(graphs)))
+        k = int(rng.integers(1, 17))
+        S = np.ascontiguousarray(rng.random((graphs[gi].n, k)))
+        reqs.append((gi, S))
+    return torch, fj, graphs, G, reqs
+
+
+def _run(fj, torch, G, reqs, arena_bytes, block_columns=16):
+    srv = fj.Server(arena_bytes, block_columns=block_columns, iters_per_replay=6)
+    gids = [srv.add_graph(g) for g in G]
+    ids = [srv.submit(gids[gi], torch.from_numpy(S).to("cuda:0")) for gi, S in reqs]
+    res = {r["id"]: r for r in srv.drain(timeout_s=240)}
+    srv.close()
+    return [res[i] for i in ids]
+
+
+def test_server_certified_and_matches_oracle(env):
+    torch, fj, graphs, G, reqs = env
+    say("server mixed run")
+    mixed = _run(fj, torch, G, reqs, 1 << 30)
+    assert all(r["status"] == fj.FJ_OK for r in mixed)
+    for (gi, S), r in list(zip(reqs, mixed))[:8]:
+        for c in range(0, S.shape[1], 5):
+            ref, _, _ = O.indices(graphs[gi], S[:, c])
+            for name in NAMES:
+                assert abs(r["values"][c][name] - ref[name]) <= 1e-6 * abs(ref[name])
+    env_cache["mixed"] = mixed
+
+
+env_cache = {}
+
+
+def test_server_result_same_alone_and_in_mix(env):
+    torch, fj, graphs, G, reqs = env
+    mixed = env_cache.get("mixed") or _run(fj, torch, G, reqs, 1 << 30)
+    for idx in (0, 7, 19, 33):
+        say(f"alone request {idx}")
+        alone = _run(fj, torch, G, [reqs[idx]], 1 << 30)[0]
+        assert alone["values"] == mixed[idx]["values"], idx
+
+
+def test_server_admission_by_footprint(env):
+    """An arena that holds only one block at a time: requests on other graphs
+    wait for the block to be released, and all still complete certified."""
+    torch, fj, graphs, G, reqs = env
+    biggest = max(g.n for g in graphs)
+    arena = fj.Server.block_bytes(biggest, 16) + 4096
+    say("small arena")
+    res = _run(fj, torch, G, reqs[:12], arena)
+    assert all(r["status"] == fj.FJ_OK for r in res)
+    ref = env_cache.get("mixed")
+    if ref:
+        for a, b in zip(res, ref[:12]):
+            assert a["values"] == b["values"]
+
+
+def test_server_errors(env):
+    torch, fj, graphs, G, reqs = env
+    srv = fj.Server(1 << 20, block_columns=16)
+    gid = srv.add_graph(G[2])
+    with pytest.raises(fj.FJError) as e:  # the 100k-node block cannot fit a 1 MiB arena
+        srv.submit(gid, torch.zeros((graphs[2].n, 2), dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == fj.FJ_ERR_WORKSPACE
+    gid0 = srv.add_graph(G[3])
+    with pytest.raises(fj.FJError) as e:
+        srv.submit(gid0, torch.zeros((graphs[3].n, 17), dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == fj.FJ_ERR_INVALID_ARG
+    srv.close()
+
+
+def test_server_graph_replays_equal_eager_batched_path(env):
+    """Server columns come from replayed HIP graphs interleaved with eager
+    admission and epilogue kernels; a 16-vector request must equal the eager
+    batched fj_indices on the same 16 vectors (same block width), bitwise."""
+    torch, fj, graphs, G, reqs = env
+    rng = np.random.default_rng(3)
+    for gi in (1, 2):
+        S = np.ascontiguousarray(rng.random((graphs[gi].n, 16)))
+        say(f"replay vs eager graph {gi}")
+        eager, _, rc = fj.fj_indices(G[gi], torch.from_numpy(S).to("cuda:0"))
+        assert rc == fj.FJ_OK
+        served = _run(fj, torch, G, [(gi, S), (0, reqs[0][1]), (gi, S)], 1 << 30)
+        assert served[0]["values"] == eager
+        assert served[2]["values"] == eager
