@@ -367,6 +367,35 @@ WORKLOADS = {
                       "s~Exp(1) min-max scaled"),
 }
 
+def serving_graph_params(count: int = 32, seed0: int = 1100):
+    """Graph g of the serving mix: Chung-Lu with n log-uniform in [1e4, 2e6],
+    exponent gamma ~ U[2.1, 2.8] and mean degree ~ U[5, 40], drawn from seed
+    seed0 + g; unit weights."""
+    out = []
+    for gi in range(count):
+        rng = np.random.default_rng(seed0 + gi)
+        n = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e6)))))
+        out.append(dict(n=n, gamma=float(rng.uniform(2.1, 2.8)), mean_deg=float(rng.uniform(5.0, 40.0)),
+                        seed=seed0 + gi))
+    return out
+
+
+def serving_graph(params) -> CSRGraph:
+    return chung_lu(params["n"], params["gamma"], params["mean_deg"], params["seed"],
+                    name=f"serve{params['seed']}")
+
+
+def serving_requests(count: int, n_graphs: int, seed: int = 3000, kmax: int = 16):
+    """(graph, k, first column) per request: graph uniform, k ~ UniformInt[1, kmax],
+    columns taken from a per-graph pool of 64 U[0,1] vectors starting at a
+    uniform offset."""
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, n_graphs, count)
+    k = rng.integers(1, kmax + 1, count)
+    c0 = rng.integers(0, 64 - k + 1)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(g, k, c0)]
+
+
 _cache: dict = {}
 
 
