@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed for cpu_baseline (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=3,
                     help="timed k=64 batched calls on the 1M-node graph (0 = skip that form)")
+    ap.add_argument("--dynamics-steps", type=int, default=3000,
+                    help="step cap of the FJ dynamics form (0 = skip it)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="measured requests per load level of the serving form (0 = skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -313,6 +315,27 @@ def main():
         },
     }
 
+    if args.dynamics_steps > 0:
+        # the model's own iteration (Eq. FJmodel) to a step change of 1e-9, for
+        # what the preconditioned solver buys over simulating the dynamics
+        z_dyn = torch.empty_like(sd)
+        ws = G.workspace(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, dinfo = fj.fj_dynamics(G, sd, args.dynamics_steps, tol=1e-9, z=z_dyn, ws=ws)
+        t_dyn = time.perf_counter() - t0
+        zs, _, _ = fj.fj_solve(G, sd, fj.make_opts(eps=args.eps, rtol=1e-12), ws=G.workspace(1))
+        result["forms"]["dynamics"] = {
+            "description": "synchronous FJ updates (Eq. FJmodel) from z = s until no z_i moves by more than "
+                           "1e-9 (or the step cap)",
+            "steps": dinfo["iters"], "step_cap": args.dynamics_steps, "last_change": dinfo["rel_residual"],
+            "converged": dinfo["status"] == 0, "ms_total": 1e3 * t_dyn,
+            "ms_per_step": 1e3 * t_dyn / max(dinfo["iters"], 1),
+            "max_abs_diff_vs_pcg_z": float((z_dyn - zs.view(-1)).abs().max()),
+            "pcg_ms_per_certified_solve": 1e3 * fp64["elapsed"] / args.steps,
+        }
+        print(f"[bench] dynamics: {dinfo['iters']} steps in {t_dyn:.3f}s", file=sys.stderr, flush=True)
+        del z_dyn, ws
     if args.batched_steps > 0:
         result["forms"].update(batched_forms(args, fj, W, torch, dev))
     if args.serve_requests > 0:

@@ -156,6 +156,21 @@ int fj_solve(const fj_csr *g, const void *plan, int32_t k, const double *S, int6
              void *stream, fj_info *info);
 
 /*
+ * The FJ opinion dynamics itself (Section 3.1, Eq. FJmodel): up to `steps`
+ * synchronous updates z_i <- (s_i + sum_j w_ij z_j) / (1 + sum_j w_ij) from
+ * z0 (NULL: start from s). Stops after the first step whose largest change
+ * max_i |z_i' - z_i| is <= tol (tol < 0: run all steps). s, z0, z: device
+ * double[n]; z receives the last iterate (z0 == z is allowed). ws: a
+ * workspace of at least fj_workspace_bytes(g, 1, FJ_FP64 opts) bytes.
+ * info (host, may be NULL): iters = steps taken, rel_residual = the last
+ * step's largest change, status. Returns FJ_OK when tol was met or tol < 0,
+ * FJ_ERR_NOT_CONVERGED when steps ran out first (z still written), and
+ * FJ_ERR_BREAKDOWN on a non-finite iterate. Synchronises before returning.
+ */
+int fj_dynamics(const fj_csr *g, const void *plan, const double *s, const double *z0, double *z,
+                int32_t steps, double tol, void *ws, size_t ws_bytes, void *stream, fj_info *info);
+
+/*
  * Algorithm 1 (Approxim): the five indices of Section 3.2 for each of k
  * opinion vectors, each certified to relative error <= opts->eps. S as in
  * fj_solve. out and info are host arrays of k entries (info may be NULL).

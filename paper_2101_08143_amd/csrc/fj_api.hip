@@ -1134,6 +1134,99 @@ int fj_apply(const fj_csr* g, const void* plan, const double* x, double* y, void
     });
 }
 
+int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,
+                int32_t steps, double tol, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
+    if (int rc = check_graph_args(g)) return rc;
+    if (!plan || !ws || !aligned(plan) || !aligned(ws)) return FJ_ERR_WORKSPACE;
+    if (steps < 0 || !(tol == tol)) return FJ_ERR_INVALID_ARG;
+    if (g->n > 0 && (!s || !z)) return FJ_ERR_INVALID_ARG;
+    const WsLayout wl = ws_layout(g, 1, FJ_FP64, 0);
+    if (ws_bytes < wl.total) return FJ_ERR_WORKSPACE;
+    if (info) *info = fj_info{};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = g->n;
+    if (!z0) z0 = s;
+    if (n == 0) return FJ_OK;
+    if (steps == 0) {
+        if (z0 != z) HIPCHK(hipMemcpyAsync(z, z0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return FJ_OK;
+    }
+    const PlanLayout pl = plan_layout(g);
+    const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(plan) + pl.desc);
+    char* W = static_cast<char*>(ws);
+    double* B = reinterpret_cast<double*>(W + wl.x);
+    double* part = reinterpret_cast<double*>(W + wl.part);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(W + wl.ctrl);
+    HostSlots* hs = nullptr;
+    if (int rc = host_slots(&hs)) return rc;
+    if (z0 == z) {  // the first step must not read and write the same vector
+        HIPCHK(hipMemcpyAsync(B, z0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        z0 = B;
+    }
+    k_ctrl_reset<<<1, WG, 0, st>>>(ctrl, 1);
+    HIPCHK(hipGetLastError());
+    k_fj_ctrl_init<<<1, 64, 0, st>>>(ctrl, tol < 0.0 ? -1.0 : tol, steps);
+    HIPCHK(hipGetLastError());
+    // step t reads src(t) and writes dst(t): dst(t) = z for even t, B for odd t
+    auto src = [&](int t) -> const double* { return t == 0 ? z0 : (t % 2 == 1 ? z : B); };
+    auto dst = [&](int t) -> double* { return t % 2 == 0 ? z : B; };
+    int queued = 0, slot_next = 0;
+    std::deque<int> pending;
+    Ctrl fin{};
+    int rc = with_graph(g, [&](auto G) -> int {
+        using Vc = typename decltype(G)::value_type;
+        int grid = 1;
+        if (int e = grid_for(k_fj_sweep<Vc>, pl.K, &grid)) return e;
+        auto enqueue = [&](int cnt) -> int {
+            for (int c = 0; c < cnt; ++c, ++queued) {
+                k_fj_sweep<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, src(queued), s, dst(queued), part, ctrl);
+                HIPCHK(hipGetLastError());
+                k_fin_fj<<<1, WG, 0, st>>>(grid, part, ctrl);
+                HIPCHK(hipGetLastError());
+            }
+            const int sl = slot_next++ % NSLOT;
+            HIPCHK(hipMemcpyAsync(hs->slot(sl), ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(hs->ev[sl], st));
+            pending.push_back(sl);
+            return FJ_OK;
+        };
+        constexpr int CHUNK = 32;
+        for (int k = 0; k < 2 && queued < steps; ++k)
+            if (int e = enqueue(std::min(CHUNK, steps - queued))) return e;
+        while (!pending.empty()) {
+            const int sl = pending.front();
+            pending.pop_front();
+            HIPCHK(hipEventSynchronize(hs->ev[sl]));
+            const Ctrl& cc = *hs->slot(sl);
+            if (cc.done != RUNNING) break;
+            if (queued < steps)
+                if (int e = enqueue(std::min(CHUNK, steps - queued))) return e;
+        }
+        return FJ_OK;
+    });
+    if (rc) return rc;
+    // later chunks are empty launches once the control block says done
+    HIPCHK(hipMemcpyAsync(hs->slot(NSLOT), ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(&fin, hs->slot(NSLOT), sizeof(Ctrl));
+    const int taken = fin.iters;
+    if (taken > 0 && dst(taken - 1) != z) {
+        HIPCHK(hipMemcpyAsync(z, B, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    int status = FJ_OK;
+    if (fin.done == BREAKDOWN) status = FJ_ERR_BREAKDOWN;
+    else if (fin.done != CONVERGED && tol >= 0.0) status = FJ_ERR_NOT_CONVERGED;
+    if (info) {
+        info->status = status;
+        info->iters = taken;
+        info->passes = 1;
+        info->rel_residual = fin.res[0];
+    }
+    return status;
+}
+
 int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int64_t lds, double* Z,
              int64_t ldz, const fj_opts* opts, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
     if (int rc = check_graph_args(g)) return rc;

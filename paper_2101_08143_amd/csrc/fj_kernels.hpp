@@ -155,9 +155,10 @@ __device__ __forceinline__ void total_partials(int G, const double* __restrict__
 // ------------------------------------------------------------ window pass
 
 // What a row accumulates over its neighbours j (d = x_i - x_j):
-struct AccLin   { static constexpr bool X = true,  SQ = false, DEG = false; };  // sum w d
-struct AccLinSq { static constexpr bool X = true,  SQ = true,  DEG = false; };  // sum w d, sum w d^2
-struct AccDeg   { static constexpr bool X = false, SQ = false, DEG = true;  };  // sum w
+struct AccLin   { static constexpr bool X = true,  SQ = false, DEG = false, RAW = false; };  // sum w d
+struct AccLinSq { static constexpr bool X = true,  SQ = true,  DEG = false, RAW = false; };  // sum w d, sum w d^2
+struct AccDeg   { static constexpr bool X = false, SQ = false, DEG = true,  RAW = false; };  // sum w
+struct AccRaw   { static constexpr bool X = true,  SQ = false, DEG = false, RAW = true;  };  // sum w x_j, sum w
 
 // Entry slot STAGE - 1 and row slot WIN are never read: a window stages at
 // most STAGE - 1 entries and WIN rows. Lanes with nothing to stage write
@@ -233,7 +234,8 @@ __device__ __forceinline__ void load_entries(const Csr<V>& g, const WinDesc& d, 
 
 // Reduce one window whose entries, row ends, own values and per-row inputs
 // are staged in LDS: calls op.row(i, x_i, sum_j w_ij (x_i - x_j),
-// sum_j w_ij (x_i - x_j)^2, in_i) exactly once for every row of the window,
+// sum_j w_ij (x_i - x_j)^2, in_i) (with AccRaw: op.row(i, x_i,
+// sum_j w_ij x_j, sum_j w_ij, in_i)) exactly once for every row of the window,
 // from a thread fixed by the data layout (so per-thread partial sums are
 // reproducible).
 //
@@ -275,6 +277,9 @@ __device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d,
             if constexpr (WEIGHTED) w = static_cast<double>(st.w[j]);
             if constexpr (Acc::DEG) {
                 lin += w;
+            } else if constexpr (Acc::RAW) {
+                lin += w * static_cast<double>(st.x[j]);
+                sq += w;
             } else {
                 const double diff = xa - static_cast<double>(st.x[j]);
                 lin += w * diff;
@@ -332,6 +337,15 @@ __device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d,
             if constexpr (Acc::DEG) {
 #pragma unroll
                 for (int u = 0; u < LONG_UNROLL; ++u) v[0] += ww[u];
+            } else if constexpr (Acc::RAW) {
+                double xv[LONG_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LONG_UNROLL; ++u) xv[u] = static_cast<double>(x[jj[u]]);
+#pragma unroll
+                for (int u = 0; u < LONG_UNROLL; ++u) {
+                    v[0] += ww[u] * xv[u];
+                    v[1] += ww[u];
+                }
             } else {
                 double xv[LONG_UNROLL];
 #pragma unroll
@@ -605,6 +619,78 @@ __global__ void __launch_bounds__(WG) k_apply(Csr<V> g, const WinDesc* __restric
     __shared__ double red[NWAVE * 2];
     OpApply op{y};
     my_windows<double, V, AccLin>(g, desc, K, x, op, st, red);
+}
+
+// One synchronous step of the FJ update rule (Section 3.1, Eq. FJmodel):
+// z'_i = (s_i + sum_j w_ij z_j) / (1 + sum_j w_ij), with the largest change
+// |z'_i - z_i| of the step.
+struct OpFj {
+    struct In {
+        double s;
+    };
+    const double* __restrict__ s;
+    double* __restrict__ znext;
+    double maxc = 0.0;
+    __device__ In load(int i) const { return {s[i]}; }
+    __device__ void row(int i, double zi, double wz, double wsum, const In& in) {
+        const double zn = (in.s + wz) / (1.0 + wsum);
+        znext[i] = zn;
+        maxc = fmax(maxc, fabs(zn - zi));
+    }
+};
+
+template <typename V>
+__global__ void __launch_bounds__(WG) k_fj_sweep(Csr<V> g, const WinDesc* __restrict__ desc, int K,
+                                                 const double* __restrict__ z, const double* __restrict__ s,
+                                                 double* __restrict__ znext, double* __restrict__ part,
+                                                 const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ Stage<double, V, OpFj::In> st;
+    __shared__ double red[NWAVE * 2];
+    OpFj op{s, znext};
+    my_windows<double, V, AccRaw>(g, desc, K, z, op, st, red);
+    double m = wave_max(op.maxc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) m = fmax(m, red[w]);
+        red[0] = m;
+    }
+    __syncthreads();
+    double v[1] = {red[0]};
+    store_partials<1>(v, part);
+}
+
+// Largest change of the step; stops when it is at most tol (held in tol2), or
+// at the step limit.
+__global__ void __launch_bounds__(WG) k_fin_fj(int G, const double* __restrict__ part, Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ double red[NWAVE];
+    double m = 0.0;
+    for (int b = threadIdx.x; b < G; b += WG) m = fmax(m, part[b * NPART]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) m = fmax(m, red[w]);
+        const int t = ctrl->iters;
+        ctrl->res[0] = m;
+        ctrl->hist[t % HIST] = m;
+        ctrl->iters = t + 1;
+        if (!isfinite(m)) ctrl->done = BREAKDOWN;
+        else if (m <= ctrl->tol2) ctrl->done = CONVERGED;
+        else if (t + 1 >= ctrl->max_iter) ctrl->done = ITER_CAP;
+    }
+}
+
+__global__ void k_fj_ctrl_init(Ctrl* __restrict__ ctrl, double tol, int max_steps) {
+    if (threadIdx.x == 0) {
+        ctrl->tol2 = tol;
+        ctrl->max_iter = max_steps;
+        ctrl->iters = 0;
+        ctrl->res[0] = 0.0;
+        ctrl->done = max_steps > 0 ? RUNNING : ITER_CAP;
+    }
 }
 
 // CG step, part 1: q = (I+L) p with the partial sums of p^T q, r^T M^{-1} q

@@ -40,7 +40,7 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
-           "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_indices", "fj_server_block_bytes",
+           "fj_workspace_bytes", "fj_apply", "fj_dynamics", "fj_solve", "fj_indices", "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll")
 
@@ -110,6 +110,7 @@ def lib():
         L.fj_workspace_bytes.argtypes = [P(fj_csr), i32, P(fj_opts)]
         L.fj_workspace_bytes.restype = sz
         L.fj_apply.argtypes = [P(fj_csr), vp, vp, vp, vp]
+        L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
                                  P(fj_info)]
@@ -121,7 +122,7 @@ def lib():
         L.fj_server_submit.argtypes = [vp, i32, i32, vp, i64, P(fj_indices_t), P(fj_info), P(ctypes.c_uint64)]
         L.fj_server_step.argtypes = [vp, P(i32)]
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
-        for name in ("fj_prepare", "fj_apply", "fj_solve", "fj_indices", "fj_server_create", "fj_server_destroy",
+        for name in ("fj_prepare", "fj_apply", "fj_dynamics", "fj_solve", "fj_indices", "fj_server_create", "fj_server_destroy",
                      "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -238,6 +239,27 @@ def _check_block(graph, S, name):
     if S.dim() != 2 or S.shape[0] != graph.n or S.stride(1) != 1:
         raise ValueError(f"{name} must be n x k with unit column stride")
     return S, S.shape[1], S.stride(0)
+
+
+def fj_dynamics(graph: Graph, s, steps: int, tol: float = -1.0, z0=None, z=None, ws=None, stream=None):
+    """Up to `steps` synchronous FJ updates (Eq. FJmodel) from z0 (default s);
+    stops early once a step changes no z_i by more than tol (tol < 0: never).
+    Returns (z, info dict); FJ_ERR_NOT_CONVERGED is reported in info, not raised."""
+    import torch
+    assert s.dtype == torch.float64 and s.is_contiguous() and s.numel() == graph.n
+    if z0 is not None:
+        assert z0.dtype == torch.float64 and z0.is_contiguous() and z0.numel() == graph.n
+    if z is None:
+        z = torch.empty_like(s)
+    if ws is None:
+        ws = graph.workspace(1)
+    inf = fj_info()
+    rc = lib().fj_dynamics(ctypes.byref(graph.csr), _ptr(graph.plan), _ptr(s),
+                           _ptr(z0) if z0 is not None else None, _ptr(z), int(steps), float(tol),
+                           _ptr(ws), ws.numel(), _stream_handle(torch, stream), ctypes.byref(inf))
+    if rc not in (FJ_OK, FJ_ERR_NOT_CONVERGED):
+        raise FJError(rc, "fj_dynamics")
+    return z, info_dict(inf)
 
 
 def fj_solve(graph: Graph, S, opts: Optional[fj_opts] = None, ws=None, Z=None, stream=None,

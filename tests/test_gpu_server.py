@@ -113,6 +113,6 @@ def test_server_graph_replays_equal_eager_batched_path(env):
         say(f"replay vs eager graph {gi}")
         eager, _, rc = fj.fj_indices(G[gi], torch.from_numpy(S).to("cuda:0"))
         assert rc == fj.FJ_OK
-        served = _run(fj, torch, G, [(gi, S), (0, reqs[0][1]), (gi, S)], 1 << 30)
+        served = _run(fj, torch, G, [(gi, S), reqs[0], reqs[1], (gi, S)], 1 << 30)
         assert served[0]["values"] == eager
-        assert served[2]["values"] == eager
+        assert served[3]["values"] == eager
