@@ -70,6 +70,11 @@ def batched_forms(args, fj, W, torch, dev):
             launches += infos[0].n_spmv
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / args.batched_steps
+        # the default shape (1 column per lane, full grid) for comparison
+        _, uinfos, _ = fj.fj_indices(G, Sd, fj.make_opts(eps=args.eps, precision=prec,
+                                                          flags=fj.FJ_PROFILE | fj.FJ_NO_TUNE), ws=ws)
+        untuned = uinfos[0].ms_spmv / max(uinfos[0].n_spmv, 1)
+        shape = fj.fj_spmm_choice(G, 64, prec)
         elem = 4 if prec == fj.FJ_MIXED else 8
         b = spmm_bytes(g.n, g.nnz, 0, 64, elem)
         avg = ms / max(launches, 1)
@@ -84,6 +89,8 @@ def batched_forms(args, fj, W, torch, dev):
             "spmm_avg_launch_ms": avg,
             "spmm_achieved_GBs": b / (avg * 1e-3) / 1e9 if avg > 0 else None,
             "spmm_algorithmic_bytes_per_launch": b,
+            "spmm_tuned_shape": {"columns_per_lane": shape[0], "grid": shape[1]} if shape else None,
+            "spmm_default_shape_avg_launch_ms": untuned,
         }
         print(f"[bench] {name}: {1e3 * el:.1f} ms per call", file=sys.stderr, flush=True)
     # the plain comparison: the same 64 vectors one at a time in FP64

@@ -80,6 +80,7 @@ typedef struct fj_csr {
 #define FJ_NO_RANGE_CHECK  2u  /* accept opinions outside [0,1] (the algebra holds for any real s) */
 #define FJ_VALIDATE_GRAPH  4u  /* fj_prepare checks the CSR contract (synchronises) */
 #define FJ_PROFILE         8u  /* time every SpMV launch with HIP events (fills fj_info.ms_*) */
+#define FJ_NO_TUNE        16u  /* batched solves: skip the SpMM autotuner, use 1 column per lane and the full grid */
 
 typedef struct fj_opts {
     double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */
@@ -154,6 +155,25 @@ int fj_apply(const fj_csr *g, const void *plan, const double *x, double *y, void
 int fj_solve(const fj_csr *g, const void *plan, int32_t k, const double *S, int64_t lds,
              double *Z, int64_t ldz, const fj_opts *opts, void *ws, size_t ws_bytes,
              void *stream, fj_info *info);
+
+/*
+ * The SpMM launch shape the autotuner chose for this graph (same pointers, n
+ * and nnz), block width kb (2, 4, ..., 64) and precision (FJ_FP64: FP64
+ * vectors; FJ_MIXED: the FP32 inner vectors) on the current device:
+ * *cpl columns per lane (a row is owned by kb / *cpl lanes) and *grid
+ * workgroups. The first batched solve of such a combination times every
+ * candidate shape once and keeps the fastest for the life of the process.
+ * Returns FJ_ERR_INVALID_ARG when nothing has been tuned for it yet.
+ */
+int fj_spmm_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t *cpl, int32_t *grid);
+
+/*
+ * Pin the SpMM launch shape for this graph, kb and precision on the current
+ * device instead of tuning it (for instance to reproduce another process's
+ * choice bit for bit): cpl in {1, 2, 4} dividing kb, grid in [1, 4096].
+ * Later batched solves and servers created afterwards use it.
+ */
+int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid);
 
 /*
  * The FJ opinion dynamics itself (Section 3.1, Eq. FJmodel): up to `steps`

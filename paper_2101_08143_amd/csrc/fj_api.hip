@@ -608,6 +608,126 @@ int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, d
     return status;
 }
 
+// ---------------------------------------------------------------- SpMM tuner
+
+// The batched SpMM has two launch parameters that trade lanes per row for
+// rows in flight: CPL columns per lane (a row is owned by KB / CPL lanes, so
+// a wave64 works on 64 * CPL / KB rows at once, each gather a CPL-wide vector
+// load) and the persistent grid (every workgroup that fits, or half as many).
+// The first batched solve of a (graph, KB, vector precision) on a device
+// times each candidate on its own vectors and keeps the fastest for the life
+// of the process; FJ_NO_TUNE pins CPL = 1 and the full grid. The row sums do
+// not depend on the choice; the order in which the per-column dot products
+// are added does (so two processes that tune differently may differ in the
+// last bits, while every call within a process sees the same choice).
+struct SpmmKey {
+    int dev, kb, tbytes, vt, n;
+    int64_t nnz;
+    const void *rp, *col, *val;
+    bool operator<(const SpmmKey& o) const {
+        return std::tie(dev, kb, tbytes, vt, n, nnz, rp, col, val) <
+               std::tie(o.dev, o.kb, o.tbytes, o.vt, o.n, o.nnz, o.rp, o.col, o.val);
+    }
+};
+struct SpmmChoice {
+    int cpl = 1, grid = 1;
+};
+std::mutex g_tune_mu;
+std::map<SpmmKey, SpmmChoice> g_tune;
+
+int spmm_key(const fj_csr* g, int kb, int tbytes, SpmmKey* k) {
+    int dev = 0;
+    if (int rc = current_device(&dev)) return rc;
+    *k = SpmmKey{dev, kb, tbytes, g->val_type, g->n, g->nnz, g->row_ptr, g->col_idx, g->val};
+    return FJ_OK;
+}
+
+template <typename Vc, typename T, int KB>
+struct Spmm {
+    static int full_grid(int cpl, int K, int* grid) {
+        if constexpr (KB % 4 == 0)
+            if (cpl == 4) return grid_for(k_spmm_cg<Vc, T, KB, 4>, K, grid);
+        if constexpr (KB % 2 == 0)
+            if (cpl == 2) return grid_for(k_spmm_cg<Vc, T, KB, 2>, K, grid);
+        return grid_for(k_spmm_cg<Vc, T, KB, 1>, K, grid);
+    }
+    static int launch(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
+                      const T* P, const T* R, const float* minv, T* Q, double* part) {
+        if constexpr (KB % 4 == 0)
+            if (ch.cpl == 4) {
+                k_spmm_cg<Vc, T, KB, 4><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
+                HIPCHK(hipGetLastError());
+                return FJ_OK;
+            }
+        if constexpr (KB % 2 == 0)
+            if (ch.cpl == 2) {
+                k_spmm_cg<Vc, T, KB, 2><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
+                HIPCHK(hipGetLastError());
+                return FJ_OK;
+            }
+        k_spmm_cg<Vc, T, KB, 1><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
+    }
+    // The launch shape for this graph: cached, or tuned now on the caller's
+    // vectors (Q and part are overwritten; the next SpMM recomputes them).
+    static int choose(const fj_csr* g, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
+                      const T* P, const T* R, const float* minv, T* Q, double* part, bool tune,
+                      SpmmChoice* out) {
+        if (!tune) {
+            out->cpl = 1;
+            return full_grid(1, K, &out->grid);
+        }
+        SpmmKey key{};
+        if (int rc = spmm_key(g, KB, static_cast<int>(sizeof(T)), &key)) return rc;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                *out = it->second;
+                return FJ_OK;
+            }
+        }
+        std::vector<SpmmChoice> cand;
+        for (int cpl : {1, 2, 4}) {
+            if (KB % cpl != 0) continue;
+            int full = 1;
+            if (int rc = full_grid(cpl, K, &full)) return rc;
+            cand.push_back({cpl, full});
+            if (full >= 2) cand.push_back({cpl, full / 2});
+        }
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        constexpr int REPS = 3;
+        float best = INFINITY;
+        SpmmChoice pick = cand.front();
+        int rc = FJ_OK;
+        for (const SpmmChoice& ch : cand) {
+            if ((rc = launch(ch, st, G, desc, K, P, R, minv, Q, part))) break;  // warm-up
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = FJ_ERR_HIP; break; }
+            for (int r = 0; r < REPS && rc == FJ_OK; ++r) rc = launch(ch, st, G, desc, K, P, R, minv, Q, part);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = FJ_ERR_HIP;
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                pick = ch;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        *out = g_tune.emplace(key, pick).first->second;
+        return FJ_OK;
+    }
+};
+
 // ---------------------------------------------------------------- k columns
 
 template <typename T>
@@ -621,7 +741,9 @@ struct BState {
 template <int KB>
 struct Batched {
     Ctx& c;
+    bool tune = true;
     int grid_vec = 1;
+    SpmmChoice ch64{1, 0}, ch32{1, 0};  // grid 0: not chosen yet
     static constexpr uint64_t ALL = KB >= 64 ? ~0ull : ((1ull << KB) - 1ull);
 
     int setup() {
@@ -653,13 +775,18 @@ struct Batched {
         int grid_win = 1;
         int rc = with_graph(c.g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
-            if (int e = grid_for(k_spmm_cg<Vc, T, KB>, c.pl.K, &grid_win)) return e;
+            SpmmChoice& ch = sizeof(T) == sizeof(double) ? ch64 : ch32;
+            if (ch.grid == 0)
+                if (int e = Spmm<Vc, T, KB>::choose(c.g, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part,
+                                                    tune, &ch))
+                    return e;
+            grid_win = ch.grid;
             if (c.profile) {
                 if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
                 HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
             }
-            k_spmm_cg<Vc, T, KB><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part);
-            HIPCHK(hipGetLastError());
+            if (int e = Spmm<Vc, T, KB>::launch(ch, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part))
+                return e;
             if (c.profile) {
                 HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
                 ++c.n_prof;
@@ -899,6 +1026,7 @@ template <int KB>
 int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t lds, int k, double* Z, int64_t ldz,
                 const fj_opts& o, bool want_indices, fj_indices_t* out, fj_info* info) {
     Batched<KB> B{c};
+    B.tune = (o.flags & FJ_NO_TUNE) == 0;
     if (int rc = B.setup()) return rc;
     const bool mixed = o.precision == FJ_MIXED;
     const bool two = (o.flags & FJ_TWO_SOLVE) && k == 1;
@@ -1132,6 +1260,32 @@ int fj_apply(const fj_csr* g, const void* plan, const double* x, double* y, void
         HIPCHK(hipGetLastError());
         return FJ_OK;
     });
+}
+
+int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl, int32_t* grid) {
+    if (int rc = check_graph_args(g)) return rc;
+    if (!cpl || !grid || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
+    if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
+    SpmmKey key{};
+    if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return FJ_ERR_INVALID_ARG;
+    *cpl = it->second.cpl;
+    *grid = it->second.grid;
+    return FJ_OK;
+}
+
+int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid) {
+    if (int rc = check_graph_args(g)) return rc;
+    if (kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
+    if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
+    if ((cpl != 1 && cpl != 2 && cpl != 4) || kb % cpl != 0 || grid < 1 || grid > GMAX) return FJ_ERR_INVALID_ARG;
+    SpmmKey key{};
+    if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = SpmmChoice{cpl, grid};
+    return FJ_OK;
 }
 
 int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,

@@ -35,21 +35,49 @@ __device__ __forceinline__ double shfl_d(double v, int src, int width) {
     return __shfl(v, src, width);
 }
 
-// The rows of the workgroup's windows (blockIdx.x, +gridDim.x, ...). Calls
-// op.row(i, c, x_ic, sum_j w_ij (x_ic - x_jc), sum_j w_ij (x_ic - x_jc)^2) for
-// every row i and column c < KB, from lane c of the group that owns the row.
-// A long last row is split over all groups of the workgroup and combined in
-// LDS in group order. lred must hold 2 * WG doubles.
-template <typename T, typename V, typename Acc, int KB, typename Op>
+// CPL consecutive columns of one node as doubles: one vector load per 16 bytes.
+template <typename T, int CPL>
+__device__ __forceinline__ void load_cols(const T* __restrict__ p, double (&out)[CPL]) {
+    if constexpr (std::is_same<T, double>::value && CPL >= 2) {
+#pragma unroll
+        for (int h = 0; h < CPL / 2; ++h) {
+            const double2 v = reinterpret_cast<const double2*>(p)[h];
+            out[2 * h] = v.x;
+            out[2 * h + 1] = v.y;
+        }
+    } else if constexpr (std::is_same<T, float>::value && CPL == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else if constexpr (std::is_same<T, float>::value && CPL == 2) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        out[0] = v.x; out[1] = v.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) out[q] = static_cast<double>(p[q]);
+    }
+}
+
+// The rows of the workgroup's windows (blockIdx.x, +gridDim.x, ...). A row is
+// owned by a group of GW = KB / CPL lanes; lane l of the group owns columns
+// l*CPL .. l*CPL + CPL - 1 and calls op.row(i, q, c, x_ic,
+// sum_j w_ij (x_ic - x_jc), sum_j w_ij (x_ic - x_jc)^2) for each of them
+// (q = c - l*CPL). Each column's row sum runs over the row's entries in CSR
+// order whatever CPL is. A long last row is split over all groups of the
+// workgroup and combined in LDS in group order. lred must hold
+// 2 * WG * CPL doubles.
+template <typename T, typename V, typename Acc, int KB, int CPL, typename Op>
 __device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
                                              const T* __restrict__ X, Op& op, double* lred) {
-    constexpr int NG = WG / KB;
+    static_assert(KB % CPL == 0, "CPL must divide KB");
+    constexpr int GW = KB / CPL;
+    constexpr int NG = WG / GW;
     constexpr bool WEIGHTED = !std::is_same<V, Unit>::value;
-    const int lane = threadIdx.x % KB;
-    const int grp = threadIdx.x / KB;
+    const int lane = threadIdx.x % GW;
+    const int grp = threadIdx.x / GW;
+    const int c0 = lane * CPL;
 
-    auto row_sum = [&](int e_begin, int e_end, int e_step, double xi, double& lin, double& sq) {
-        for (int e0 = e_begin; e0 < e_end; e0 += e_step) {
+    auto row_sum = [&](int e_begin, int e_end, const double (&xi)[CPL], double (&lin)[CPL], double (&sq)[CPL]) {
+        for (int e0 = e_begin; e0 < e_end; e0 += GW) {
             const int e = e0 + lane;
             int jl = 0;
             double wl = 0.0;
@@ -57,31 +85,39 @@ __device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __r
                 jl = g.col[e];
                 wl = weight_at<V>(g.val, e);
             }
-            const int cnt = min(KB, e_end - e0);
+            const int cnt = min(GW, e_end - e0);
             int t = 0;
             for (; t + 4 <= cnt; t += 4) {  // four gathers in flight
                 int j[4];
-                double w[4], xj[4];
+                double w[4], xj[4][CPL];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    j[u] = __shfl(jl, t + u, KB);
-                    w[u] = WEIGHTED ? shfl_d(wl, t + u, KB) : 1.0;
+                    j[u] = __shfl(jl, t + u, GW);
+                    w[u] = WEIGHTED ? shfl_d(wl, t + u, GW) : 1.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) xj[u] = static_cast<double>(X[static_cast<int64_t>(j[u]) * KB + lane]);
+                for (int u = 0; u < 4; ++u) load_cols<T, CPL>(X + static_cast<int64_t>(j[u]) * KB + c0, xj[u]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const double d = xi - xj[u];
-                    lin += w[u] * d;
-                    if constexpr (Acc::SQ) sq += w[u] * d * d;
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) {
+                        const double d = xi[q] - xj[u][q];
+                        lin[q] += w[u] * d;
+                        if constexpr (Acc::SQ) sq[q] += w[u] * d * d;
+                    }
                 }
             }
             for (; t < cnt; ++t) {
-                const int j = __shfl(jl, t, KB);
-                const double w = WEIGHTED ? shfl_d(wl, t, KB) : 1.0;
-                const double d = xi - static_cast<double>(X[static_cast<int64_t>(j) * KB + lane]);
-                lin += w * d;
-                if constexpr (Acc::SQ) sq += w * d * d;
+                const int j = __shfl(jl, t, GW);
+                const double w = WEIGHTED ? shfl_d(wl, t, GW) : 1.0;
+                double xj[CPL];
+                load_cols<T, CPL>(X + static_cast<int64_t>(j) * KB + c0, xj);
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    const double d = xi[q] - xj[q];
+                    lin[q] += w * d;
+                    if constexpr (Acc::SQ) sq[q] += w * d * d;
+                }
             }
         }
     };
@@ -90,47 +126,62 @@ __device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __r
         const WinDesc d = to_scalar(load_raw_desc(desc + k));
         for (int a = grp; a < d.nrs; a += NG) {
             const int i = d.r0 + a;
-            const double xi = static_cast<double>(X[static_cast<int64_t>(i) * KB + lane]);
-            double lin = 0.0, sq = 0.0;
-            row_sum(g.row_ptr[i], g.row_ptr[i + 1], KB, xi, lin, sq);
-            op.row(i, lane, xi, lin, sq);
+            double xi[CPL], lin[CPL], sq[CPL];
+            load_cols<T, CPL>(X + static_cast<int64_t>(i) * KB + c0, xi);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) lin[q] = sq[q] = 0.0;
+            row_sum(g.row_ptr[i], g.row_ptr[i + 1], xi, lin, sq);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) op.row(i, q, c0 + q, xi[q], lin[q], sq[q]);
         }
         if (d.long_last) {  // workgroup-uniform
             const int i = d.r1 - 1;
-            const double xi = static_cast<double>(X[static_cast<int64_t>(i) * KB + lane]);
-            double lin = 0.0, sq = 0.0;
-            // group gr takes entry chunks elast + gr*KB, elast + (gr+NG)*KB, ...
-            for (int e0 = d.elast + grp * KB; e0 < d.eend; e0 += NG * KB) row_sum(e0, min(e0 + KB, d.eend), KB, xi, lin, sq);
-            lred[threadIdx.x] = lin;
-            lred[WG + threadIdx.x] = sq;
+            double xi[CPL], lin[CPL], sq[CPL];
+            load_cols<T, CPL>(X + static_cast<int64_t>(i) * KB + c0, xi);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) lin[q] = sq[q] = 0.0;
+            // group gr takes entry chunks elast + gr*GW, elast + (gr+NG)*GW, ...
+            for (int e0 = d.elast + grp * GW; e0 < d.eend; e0 += NG * GW)
+                row_sum(e0, min(e0 + GW, d.eend), xi, lin, sq);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                lred[grp * KB + c0 + q] = lin[q];
+                lred[NG * KB + grp * KB + c0 + q] = sq[q];
+            }
             __syncthreads();
             if (grp == 0) {
-                double L = 0.0, S = 0.0;
-                for (int gr = 0; gr < NG; ++gr) {
-                    L += lred[gr * KB + lane];
-                    S += lred[WG + gr * KB + lane];
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    double L = 0.0, S = 0.0;
+                    for (int gr = 0; gr < NG; ++gr) {
+                        L += lred[gr * KB + c0 + q];
+                        S += lred[NG * KB + gr * KB + c0 + q];
+                    }
+                    op.row(i, q, c0 + q, xi[q], L, S);
                 }
-                op.row(i, lane, xi, L, S);
             }
             __syncthreads();
         }
     }
 }
 
-// Per-column workgroup sums of N accumulators: lane c of every group holds
-// the workgroup's share for column c; groups are added in order and the
-// result goes to part[(blockIdx.x * KB + c) * BPART + v].
-template <int N, int KB>
-__device__ __forceinline__ void store_column_partials(const double (&v)[N], double* lred,
+// Per-column workgroup sums of N accumulators: lane l of every group holds
+// the workgroup's share for columns l*CPL + q in v[a][q]; groups are added in
+// order and the result goes to part[(blockIdx.x * KB + c) * BPART + a].
+template <int N, int KB, int CPL>
+__device__ __forceinline__ void store_column_partials(const double (&v)[N][CPL], double* lred,
                                                       double* __restrict__ part) {
-    constexpr int NG = WG / KB;
-    static_assert(N * WG <= 12 * WG, "LDS buffer too small");
-    for (int a = 0; a < N; ++a) lred[a * WG + threadIdx.x] = v[a];
+    constexpr int GW = KB / CPL;
+    constexpr int NG = WG / GW;
+    static_assert(N * WG * CPL <= 12 * WG, "LDS buffer too small");
+    const int lane = threadIdx.x % GW, grp = threadIdx.x / GW;
+    for (int a = 0; a < N; ++a)
+        for (int q = 0; q < CPL; ++q) lred[a * NG * KB + grp * KB + lane * CPL + q] = v[a][q];
     __syncthreads();
     if (threadIdx.x < KB) {
         for (int a = 0; a < N; ++a) {
             double t = 0.0;
-            for (int gr = 0; gr < NG; ++gr) t += lred[a * WG + gr * KB + threadIdx.x];
+            for (int gr = 0; gr < NG; ++gr) t += lred[a * NG * KB + gr * KB + threadIdx.x];
             part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a] = t;
         }
     }
@@ -164,21 +215,21 @@ __device__ __forceinline__ void total_column_partials(int G, const double* __res
 
 // ------------------------------------------------------------ row operations
 
-template <typename T, int KB>
+template <typename T, int KB, int CPL>
 struct OpSpmmCg {  // Q = (I + L) P and per-column p^T q, r^T M^{-1} q, q^T M^{-1} q
     const T* __restrict__ R;
     const float* __restrict__ minv;
     T* __restrict__ Q;
-    double pq = 0.0, rmq = 0.0, qmq = 0.0;
-    __device__ void row(int i, int c, double pi, double lin, double) {
+    double v[3][CPL] = {};
+    __device__ void row(int i, int q, int c, double pi, double lin, double) {
         const int64_t at = static_cast<int64_t>(i) * KB + c;
         const T qt = static_cast<T>(pi + lin);
         Q[at] = qt;
-        const double q = static_cast<double>(qt);
-        const double mq = static_cast<double>(minv[i]) * q;
-        pq += pi * q;
-        rmq += static_cast<double>(R[at]) * mq;
-        qmq += q * mq;
+        const double qd = static_cast<double>(qt);
+        const double mq = static_cast<double>(minv[i]) * qd;
+        v[0][q] += pi * qd;
+        v[1][q] += static_cast<double>(R[at]) * mq;
+        v[2][q] += qd * mq;
     }
 };
 
@@ -190,37 +241,36 @@ struct OpSpmmEpilogue {  // per column: the sums of OpEpilogue; R is written for
     uint64_t mask;
     const Ctrl* __restrict__ ctrl;
     double* __restrict__ R;
-    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    __device__ void row(int i, int c, double zi, double t, double dsq) {
+    double v[9][1] = {};
+    __device__ void row(int i, int, int c, double zi, double t, double dsq) {
         const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
         const double ri = si - zi - t;
         if ((mask >> c) & 1ull) R[static_cast<int64_t>(i) * KB + c] = ri;
         const double dm = zi - ctrl[c].mu;
         const double dz = zi - si;
-        v[0] += t * t;
-        v[1] += dsq;
-        v[2] += dm * dm;
-        v[3] += zi * zi;
-        v[4] += zi;
-        v[5] += si * zi;
-        v[6] += ri * ri;
-        v[7] += zi * ri;
-        v[8] += dz * dz;
+        v[0][0] += t * t;
+        v[1][0] += dsq;
+        v[2][0] += dm * dm;
+        v[3][0] += zi * zi;
+        v[4][0] += zi;
+        v[5][0] += si * zi;
+        v[6][0] += ri * ri;
+        v[7][0] += zi * ri;
+        v[8][0] += dz * dz;
     }
 };
 
 // ------------------------------------------------------------ kernels
 
-template <typename V, typename T, int KB>
+template <typename V, typename T, int KB, int CPL>
 __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                 const T* __restrict__ P, const T* __restrict__ R,
                                                 const float* __restrict__ minv, T* __restrict__ Q,
                                                 double* __restrict__ part) {
     __shared__ double lred[12 * WG];
-    OpSpmmCg<T, KB> op{R, minv, Q};
-    spmm_windows<T, V, AccLin, KB>(g, desc, K, P, op, lred);
-    const double v[3] = {op.pq, op.rmq, op.qmq};
-    store_column_partials<3, KB>(v, lred, part);
+    OpSpmmCg<T, KB, CPL> op{R, minv, Q};
+    spmm_windows<T, V, AccLin, KB, CPL>(g, desc, K, P, op, lred);
+    store_column_partials<3, KB, CPL>(op.v, lred, part);
 }
 
 template <int KB>
@@ -271,7 +321,8 @@ __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X,
             P[e] = p;
         }
     }
-    store_column_partials<2, KB>(v, lred, part);
+    const double vv[2][1] = {{v[0]}, {v[1]}};
+    store_column_partials<2, KB, 1>(vv, lred, part);
 }
 
 template <int KB>
@@ -423,8 +474,8 @@ __global__ void __launch_bounds__(WG) k_epilogue_batched(Csr<V> g, const WinDesc
                                                          const Ctrl* __restrict__ ctrl) {
     __shared__ double lred[12 * WG];
     OpSpmmEpilogue<KB> op{S, lds, k, mask, ctrl, R};
-    spmm_windows<double, V, AccLinSq, KB>(g, desc, K, Z, op, lred);
-    store_column_partials<9, KB>(op.v, lred, part);
+    spmm_windows<double, V, AccLinSq, KB, 1>(g, desc, K, Z, op, lred);
+    store_column_partials<9, KB, 1>(op.v, lred, part);
 }
 
 template <int KB>

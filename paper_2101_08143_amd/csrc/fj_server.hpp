@@ -148,12 +148,22 @@ struct ServerOps {
         // capture `iters` CG iterations of the block
         int rc = with_graph(&G.g, [&](auto Gc) -> int {
             using Vc = typename decltype(Gc)::value_type;
-            if (int e = grid_for(k_spmm_cg<Vc, double, KB>, G.pl.K, &b->grid_win)) return e;
             const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(G.plan) + G.pl.desc);
             const float* minv = reinterpret_cast<const float*>(static_cast<const char*>(G.plan) + G.pl.minv);
+            // the same tuned launch shape as the eager batched path of this graph and width
+            SpmmChoice ch{};
+            if (int e = Spmm<Vc, double, KB>::choose(&G.g, G.st, Gc, desc, G.pl.K, b->P, b->R, minv, b->Q, b->part,
+                                                     true, &ch))
+                return e;
+            b->grid_win = ch.grid;
             HIPCHK(hipStreamBeginCapture(G.st, hipStreamCaptureModeThreadLocal));
             for (int t = 0; t < s.o.iters_per_replay; ++t) {
-                k_spmm_cg<Vc, double, KB><<<b->grid_win, WG, 0, G.st>>>(Gc, desc, G.pl.K, b->P, b->R, minv, b->Q, b->part);
+                if (int e = Spmm<Vc, double, KB>::launch(ch, G.st, Gc, desc, G.pl.K, b->P, b->R, minv, b->Q, b->part)) {
+                    hipGraph_t dropped = nullptr;
+                    (void)hipStreamEndCapture(G.st, &dropped);
+                    if (dropped) (void)hipGraphDestroy(dropped);
+                    return e;
+                }
                 k_fin_spmm<KB><<<1, WG, 0, G.st>>>(b->grid_win, b->part, b->ctrl);
                 k_update_batched<double, KB><<<b->grid_vec, WG, 0, G.st>>>(n, b->X, b->R, b->P, b->Q, minv, b->part,
                                                                           b->ctrl);

@@ -34,13 +34,14 @@ FJ_ERR_HIP = 8
 
 FJ_VAL_UNIT, FJ_VAL_F32, FJ_VAL_F64 = 0, 1, 2
 FJ_FP64, FJ_MIXED = 0, 1
-FJ_TWO_SOLVE, FJ_NO_RANGE_CHECK, FJ_VALIDATE_GRAPH, FJ_PROFILE = 1, 2, 4, 8
+FJ_TWO_SOLVE, FJ_NO_RANGE_CHECK, FJ_VALIDATE_GRAPH, FJ_PROFILE, FJ_NO_TUNE = 1, 2, 4, 8, 16
 
 INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
-           "fj_workspace_bytes", "fj_apply", "fj_dynamics", "fj_solve", "fj_indices", "fj_server_block_bytes",
+           "fj_workspace_bytes", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
+           "fj_indices", "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll")
 
@@ -110,6 +111,8 @@ def lib():
         L.fj_workspace_bytes.argtypes = [P(fj_csr), i32, P(fj_opts)]
         L.fj_workspace_bytes.restype = sz
         L.fj_apply.argtypes = [P(fj_csr), vp, vp, vp, vp]
+        L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32)]
+        L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32]
         L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
@@ -122,8 +125,8 @@ def lib():
         L.fj_server_submit.argtypes = [vp, i32, i32, vp, i64, P(fj_indices_t), P(fj_info), P(ctypes.c_uint64)]
         L.fj_server_step.argtypes = [vp, P(i32)]
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
-        for name in ("fj_prepare", "fj_apply", "fj_dynamics", "fj_solve", "fj_indices", "fj_server_create", "fj_server_destroy",
-                     "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll"):
+        for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
+                     "fj_indices", "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -239,6 +242,22 @@ def _check_block(graph, S, name):
     if S.dim() != 2 or S.shape[0] != graph.n or S.stride(1) != 1:
         raise ValueError(f"{name} must be n x k with unit column stride")
     return S, S.shape[1], S.stride(0)
+
+
+def fj_spmm_choice(graph: Graph, kb: int, precision: int = 0):
+    """(columns per lane, grid) the SpMM autotuner chose for this graph, block
+    width and precision, or None if nothing is tuned yet."""
+    cpl, grid = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = lib().fj_spmm_choice(ctypes.byref(graph.csr), int(kb), int(precision), ctypes.byref(cpl),
+                              ctypes.byref(grid))
+    return (cpl.value, grid.value) if rc == FJ_OK else None
+
+
+def fj_spmm_set_choice(graph: Graph, kb: int, cpl: int, grid: int, precision: int = 0):
+    """Pin the SpMM launch shape (columns per lane, grid) instead of tuning it."""
+    rc = lib().fj_spmm_set_choice(ctypes.byref(graph.csr), int(kb), int(precision), int(cpl), int(grid))
+    if rc != FJ_OK:
+        raise FJError(rc, "fj_spmm_set_choice")
 
 
 def fj_dynamics(graph: Graph, s, steps: int, tol: float = -1.0, z0=None, z=None, ws=None, stream=None):

@@ -280,6 +280,57 @@ def test_batched_indices_match_oracle(torch_fj, graphs, k, precision):
             assert err <= infos[c].bound[j] + 1e-12
 
 
+@pytest.mark.parametrize("name", ["cl50k_f32", "star6001", "gnp500_f64"])
+@pytest.mark.parametrize("k", [3, 16])
+@pytest.mark.parametrize("cpl", [1, 2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_every_spmm_shape_matches_oracle(torch_fj, name, k, cpl, precision):
+    """Each SpMM launch shape the autotuner can pick (columns per lane, full or
+    half grid), pinned in turn on a freshly prepared graph: certified indices
+    within 1e-6 of the oracle, and the row sums (hence the solve) agree between
+    shapes to the stopping tolerance."""
+    torch, fj = torch_fj
+    g = small_graphs()[name]
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=False)
+    kb = 4 if k == 3 else 16
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    S = _block(g.n, k, 300 + k)
+    say(f"spmm shape {name} k={k} cpl={cpl} {precision}")
+    grid = 64 if cpl == 2 else 512
+    fj.fj_spmm_set_choice(G, kb, cpl, grid, precision=prec)
+    assert fj.fj_spmm_choice(G, kb, prec) == (cpl, grid)
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(eps=EPS, precision=prec),
+                                    check=False)
+    assert rc == fj.FJ_OK
+    for c in range(k):
+        ref, _, _ = O.indices(g, S[:, c])
+        for j, nm in enumerate(NAMES):
+            err = abs(vals[c][nm] - ref[nm]) / abs(ref[nm])
+            assert err <= EPS and err <= infos[c].bound[j] + 1e-12, (c, nm, err)
+
+
+def test_batched_autotuner_records_a_shape(torch_fj):
+    """The first batched solve of a fresh (graph, width, precision) tunes and
+    caches a shape; FJ_NO_TUNE runs the default shape; both are certified."""
+    torch, fj = torch_fj
+    g = small_graphs()["cl100k_unit"]
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=False)
+    S = torch.from_numpy(_block(g.n, 16, 401)).to("cuda:0")
+    say("spmm autotuner")
+    assert fj.fj_spmm_choice(G, 16, fj.FJ_FP64) is None
+    v0, _, rc0 = fj.fj_indices(G, S, fj.make_opts(eps=EPS, flags=fj.FJ_NO_TUNE), check=False)
+    assert rc0 == fj.FJ_OK and fj.fj_spmm_choice(G, 16, fj.FJ_FP64) is None
+    v1, _, rc1 = fj.fj_indices(G, S, fj.make_opts(eps=EPS), check=False)
+    assert rc1 == fj.FJ_OK
+    cpl, grid = fj.fj_spmm_choice(G, 16, fj.FJ_FP64)
+    assert cpl in (1, 2, 4) and 1 <= grid <= 4096
+    v2, _, _ = fj.fj_indices(G, S, fj.make_opts(eps=EPS), check=False)
+    assert v2 == v1  # the cached choice is reused: bitwise repeatable
+    for c in range(16):
+        for nm in NAMES:
+            assert abs(v0[c][nm] - v1[c][nm]) <= 2 * EPS * abs(v0[c][nm])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_solve_matches_oracle(torch_fj, graphs, precision):
     torch, fj = torch_fj
