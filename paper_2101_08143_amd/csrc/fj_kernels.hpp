@@ -171,8 +171,7 @@ struct Stage {
     T xrow[WIN + 1];     // x_i of every row of the window
     int rend[WIN + 1];   // end of each row, relative to the window's first entry
     In rin[WIN + 1];     // the operation's per-row inputs
-    int crow[WG];        // row a thread's item range ends inside of (-1: none)
-    double clin[WG];     // that row's partial sums from the thread
+    double clin[WG];     // partial sums of the row a thread's item range ends inside of
     double csq[WG];
 };
 template <typename T, typename In>
@@ -181,7 +180,6 @@ struct Stage<T, Unit, In> {
     T xrow[WIN + 1];
     int rend[WIN + 1];
     In rin[WIN + 1];
-    int crow[WG];
     double clin[WG];
     double csq[WG];
 };
@@ -270,7 +268,7 @@ __device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d,
     int row_end = (a < nrs) ? st.rend[a] : 0;
     double xa = (Acc::X && a < nrs) ? static_cast<double>(st.xrow[a]) : 0.0;
     double lin = 0.0, sq = 0.0, first_lin = 0.0, first_sq = 0.0;
-    bool first_pending = false, open = false;
+    bool first_pending = false;
     for (int dd = d0; dd < d1; ++dd) {
         if (j < row_end) {  // entry j of row a
             double w = 1.0;
@@ -286,7 +284,6 @@ __device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d,
                 if constexpr (Acc::SQ) sq += w * diff * diff;
             }
             ++j;
-            open = true;
         } else {  // end of row a
             if (a == a0 && continued) {
                 first_pending = true;
@@ -297,7 +294,6 @@ __device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d,
             }
             lin = 0.0;
             sq = 0.0;
-            open = false;
             ++a;
             if (a < nrs) {
                 row_end = st.rend[a];
@@ -305,15 +301,34 @@ __device__ __forceinline__ void window_reduce(const Csr<V>& g, const WinDesc& d,
             }
         }
     }
-    st.crow[tid] = open ? a : -1;
     st.clin[tid] = lin;
     st.csq[tid] = sq;
     __syncthreads();
     if (first_pending) {
+        // Row a0 began in thread t0 (the one holding its first item) and every
+        // thread from t0 to tid - 1 left a partial sum of it. They are added
+        // from tid - 1 down to t0, eight independent LDS loads at a time.
+        const int item0 = a0 > 0 ? st.rend[a0 - 1] + a0 : 0;
+        const int t0 = item0 / ipt;
+        constexpr bool TWO = Acc::SQ || Acc::RAW;
         double L = first_lin, S = first_sq;
-        for (int t = tid - 1; t >= 0 && st.crow[t] == a0; --t) {
+        int t = tid - 1;
+        for (; t - 7 >= t0; t -= 8) {
+            double cl[8], cs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cl[u] = st.clin[t - u];
+                cs[u] = TWO ? st.csq[t - u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                L += cl[u];
+                S += cs[u];
+            }
+        }
+        for (; t >= t0; --t) {
             L += st.clin[t];
-            S += st.csq[t];
+            if constexpr (TWO) S += st.csq[t];
         }
         op.row(d.r0 + a0, st.xrow[a0], L, S, st.rin[a0]);
     }
