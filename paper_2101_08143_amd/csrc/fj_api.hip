@@ -764,7 +764,7 @@ struct Batched {
         k_init_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(n, k, src, lds, S.X, S.R, S.P, c.minv(), mode, mask, kcheck,
                                                         S.part);
         HIPCHK(hipGetLastError());
-        k_fin_init_batched<KB><<<1, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter,
+        k_fin_init_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter,
                                                    range_check ? 1 : 0, S.ctrl);
         HIPCHK(hipGetLastError());
         return FJ_OK;
@@ -794,11 +794,11 @@ struct Batched {
             return FJ_OK;
         });
         if (rc) return rc;
-        k_fin_spmm<KB><<<1, WG, 0, c.st>>>(grid_win, S.part, S.ctrl);
+        k_fin_spmm<KB><<<KB, WG, 0, c.st>>>(grid_win, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
         k_update_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(c.g->n, S.X, S.R, S.P, S.Q, c.minv(), S.part, S.ctrl);
         HIPCHK(hipGetLastError());
-        k_fin_update_batched<KB><<<1, WG, 0, c.st>>>(grid_vec, S.part, S.ctrl);
+        k_fin_update_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
@@ -878,7 +878,7 @@ struct Batched {
             return FJ_OK;
         });
         if (rc) return rc;
-        k_fin_epilogue_batched<KB><<<1, WG, 0, c.st>>>(grid_win, c.g->n, ALL, S.part, S.ctrl);
+        k_fin_epilogue_batched<KB><<<KB, WG, 0, c.st>>>(grid_win, c.g->n, ALL, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));

@@ -188,29 +188,22 @@ __device__ __forceinline__ void store_column_partials(const double (&v)[N][CPL],
     __syncthreads();
 }
 
-// Per-column totals of N partials over G workgroups, for a one-workgroup
-// finalize kernel: thread t sums column t % KB over workgroups t / KB,
-// t / KB + WG / KB, ...; stripes are then added in order. Column c's totals
-// end in tot[c * N + a] (LDS, KB * N doubles).
+// Totals of N partials of column c = blockIdx.x over G workgroups, for a
+// finalize kernel launched with one workgroup per column: thread t adds
+// workgroups t, t + WG, ... in order, then the workgroup adds the threads'
+// sums in a fixed order. Every thread receives the totals.
 template <int N, int KB>
-__device__ __forceinline__ void total_column_partials(int G, const double* __restrict__ part, double* lred,
-                                                      double* tot) {
-    constexpr int NS = WG / KB;
-    const int c = threadIdx.x % KB, sidx = threadIdx.x / KB;
-    double v[N];
+__device__ __forceinline__ void column_totals(int G, const double* __restrict__ part, double (&v)[N],
+                                              double* red) {
+    const int c = blockIdx.x;
+#pragma unroll
     for (int a = 0; a < N; ++a) v[a] = 0.0;
-    for (int b = sidx; b < G; b += NS)
-        for (int a = 0; a < N; ++a) v[a] += part[(static_cast<int64_t>(b) * KB + c) * BPART + a];
-    for (int a = 0; a < N; ++a) lred[a * WG + threadIdx.x] = v[a];
-    __syncthreads();
-    if (threadIdx.x < KB) {
-        for (int a = 0; a < N; ++a) {
-            double t = 0.0;
-            for (int s = 0; s < NS; ++s) t += lred[a * WG + s * KB + threadIdx.x];
-            tot[threadIdx.x * N + a] = t;
-        }
+    for (int b = threadIdx.x; b < G; b += WG) {
+        const double* p = part + (static_cast<int64_t>(b) * KB + c) * BPART;
+#pragma unroll
+        for (int a = 0; a < N; ++a) v[a] += p[a];
     }
-    __syncthreads();
+    block_sum<N>(v, red);
 }
 
 // ------------------------------------------------------------ row operations
@@ -275,24 +268,22 @@ __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restr
 
 template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_spmm(int G, const double* __restrict__ part, Ctrl* __restrict__ ctrl) {
-    __shared__ double lred[12 * WG];
-    __shared__ double tot[KB * 3];
-    total_column_partials<3, KB>(G, part, lred, tot);
-    if (threadIdx.x < KB) {
-        Ctrl& c = ctrl[threadIdx.x];
-        if (c.done == RUNNING) {
-            const double rz = c.rz, pq = tot[threadIdx.x * 3];
-            if (rz == 0.0) {
-                c.done = CONVERGED;
-            } else if (!(pq > 0.0) || !isfinite(pq)) {
-                c.done = BREAKDOWN;
-            } else {
-                const double alpha = rz / pq;
-                const double rz_next = rz - 2.0 * alpha * tot[threadIdx.x * 3 + 1] +
-                                       alpha * alpha * tot[threadIdx.x * 3 + 2];
-                c.alpha = alpha;
-                c.beta = rz_next / rz;
-            }
+    Ctrl& c = ctrl[blockIdx.x];  // one workgroup per column
+    if (c.done != RUNNING) return;
+    __shared__ double red[NWAVE * 3];
+    double tot[3];
+    column_totals<3, KB>(G, part, tot, red);
+    if (threadIdx.x == 0) {
+        const double rz = c.rz, pq = tot[0];
+        if (rz == 0.0) {
+            c.done = CONVERGED;
+        } else if (!(pq > 0.0) || !isfinite(pq)) {
+            c.done = BREAKDOWN;
+        } else {
+            const double alpha = rz / pq;
+            const double rz_next = rz - 2.0 * alpha * tot[1] + alpha * alpha * tot[2];
+            c.alpha = alpha;
+            c.beta = rz_next / rz;
         }
     }
 }
@@ -328,22 +319,21 @@ __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X,
 template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_update_batched(int G, const double* __restrict__ part,
                                                            Ctrl* __restrict__ ctrl) {
-    __shared__ double lred[12 * WG];
-    __shared__ double tot[KB * 2];
-    total_column_partials<2, KB>(G, part, lred, tot);
-    if (threadIdx.x < KB) {
-        Ctrl& c = ctrl[threadIdx.x];
-        if (c.done == RUNNING) {
-            const double rz = tot[threadIdx.x * 2], rr = tot[threadIdx.x * 2 + 1];
-            const int it = c.iters + 1;
-            c.iters = it;
-            c.rz = rz;
-            c.rr = rr;
-            c.hist[it % HIST] = rr;
-            if (!isfinite(rr)) c.done = BREAKDOWN;
-            else if (rr <= c.tol2) c.done = CONVERGED;
-            else if (it >= c.max_iter) c.done = ITER_CAP;
-        }
+    Ctrl& c = ctrl[blockIdx.x];  // one workgroup per column
+    if (c.done != RUNNING) return;
+    __shared__ double red[NWAVE * 2];
+    double tot[2];
+    column_totals<2, KB>(G, part, tot, red);
+    if (threadIdx.x == 0) {
+        const double rz = tot[0], rr = tot[1];
+        const int it = c.iters + 1;
+        c.iters = it;
+        c.rz = rz;
+        c.rr = rr;
+        c.hist[it % HIST] = rr;
+        if (!isfinite(rr)) c.done = BREAKDOWN;
+        else if (rr <= c.tol2) c.done = CONVERGED;
+        else if (it >= c.max_iter) c.done = ITER_CAP;
     }
 }
 
@@ -407,44 +397,41 @@ template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, const double* __restrict__ part,
                                                          int mode, uint64_t mask, ColumnTol tol, int max_iter,
                                                          int range_check, Ctrl* __restrict__ ctrl) {
-    __shared__ double lred[12 * WG];
-    __shared__ double tot[KB * 5];
-    __shared__ double mm[KB * 2];
-    total_column_partials<5, KB>(G, part, lred, tot);
-    {  // per-column max of slots 5 (-min s) and 6 (max s), striped like the sums
-        constexpr int NS = WG / KB;
-        const int c = threadIdx.x % KB, sidx = threadIdx.x / KB;
-        double a = -INFINITY, b = -INFINITY;
-        for (int blk = sidx; blk < G; blk += NS) {
-            a = fmax(a, part[(static_cast<int64_t>(blk) * KB + c) * BPART + 5]);
-            b = fmax(b, part[(static_cast<int64_t>(blk) * KB + c) * BPART + 6]);
-        }
-        lred[threadIdx.x] = a;
-        lred[WG + threadIdx.x] = b;
-        __syncthreads();
-        if (threadIdx.x < KB) {
-            double x = -INFINITY, y = -INFINITY;
-            for (int s2 = 0; s2 < NS; ++s2) {
-                x = fmax(x, lred[s2 * KB + threadIdx.x]);
-                y = fmax(y, lred[WG + s2 * KB + threadIdx.x]);
-            }
-            mm[threadIdx.x * 2] = x;
-            mm[threadIdx.x * 2 + 1] = y;
-        }
-        __syncthreads();
+    const int c = blockIdx.x;  // one workgroup per column
+    Ctrl& C = ctrl[c];
+    if (!((mask >> c) & 1ull)) {
+        if (mode == 2 && threadIdx.x == 0) C.done = CONVERGED;  // an inner solve runs only the masked columns
+        return;
     }
-    if (threadIdx.x < KB && !((mask >> threadIdx.x) & 1ull) && mode == 2)
-        ctrl[threadIdx.x].done = CONVERGED;  // an inner solve runs only the masked columns
-    if (threadIdx.x < KB && ((mask >> threadIdx.x) & 1ull)) {
-        const int c = threadIdx.x;
-        Ctrl& C = ctrl[c];
-        const double rz = tot[c * 5], rr = tot[c * 5 + 1];
+    __shared__ double red[NWAVE * 5];
+    double tot[5];
+    column_totals<5, KB>(G, part, tot, red);
+    // max of slots 5 (-min s) and 6 (max s) over the workgroups
+    double mx[2] = {-INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < G; b += WG) {
+        const double* p = part + (static_cast<int64_t>(b) * KB + c) * BPART;
+        mx[0] = fmax(mx[0], p[5]);
+        mx[1] = fmax(mx[1], p[6]);
+    }
+    mx[0] = wave_max(mx[0]);
+    mx[1] = wave_max(mx[1]);
+    if ((threadIdx.x & 63) == 0) {
+        red[(threadIdx.x >> 6) * 2] = mx[0];
+        red[(threadIdx.x >> 6) * 2 + 1] = mx[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) {
+            mx[0] = fmax(mx[0], red[w * 2]);
+            mx[1] = fmax(mx[1], red[w * 2 + 1]);
+        }
+        const double rz = tot[0], rr = tot[1];
         if (mode == 0) {
-            C.smin = -mm[c * 2];
-            C.smax = mm[c * 2 + 1];
-            C.ss = tot[c * 5 + 2];
-            C.mu = tot[c * 5 + 3] / static_cast<double>(n);
-            C.bad = tot[c * 5 + 4] > 0.0 ? 2 : 0;
+            C.smin = -mx[0];
+            C.smax = mx[1];
+            C.ss = tot[2];
+            C.mu = tot[3] / static_cast<double>(n);
+            C.bad = tot[4] > 0.0 ? 2 : 0;
             C.iters = 0;
             C.max_iter = max_iter;
         } else if (mode == 2) {
@@ -481,12 +468,12 @@ __global__ void __launch_bounds__(WG) k_epilogue_batched(Csr<V> g, const WinDesc
 template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_epilogue_batched(int G, int n_nodes, uint64_t mask,
                                                              const double* __restrict__ part, Ctrl* __restrict__ ctrl) {
-    __shared__ double lred[12 * WG];
-    __shared__ double tot[KB * 9];
-    total_column_partials<9, KB>(G, part, lred, tot);
-    if (threadIdx.x < KB && ((mask >> threadIdx.x) & 1ull)) {
-        const double* v = tot + threadIdx.x * 9;
-        Ctrl& C = ctrl[threadIdx.x];
+    if (!((mask >> blockIdx.x) & 1ull)) return;  // one workgroup per column
+    __shared__ double red[NWAVE * 9];
+    double v[9];
+    column_totals<9, KB>(G, part, v, red);
+    if (threadIdx.x == 0) {
+        Ctrl& C = ctrl[blockIdx.x];
         const double n = static_cast<double>(n_nodes);
         const double dev = v[4] - n * C.mu;
         double idx[5];

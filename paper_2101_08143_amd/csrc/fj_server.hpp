@@ -164,10 +164,10 @@ struct ServerOps {
                     if (dropped) (void)hipGraphDestroy(dropped);
                     return e;
                 }
-                k_fin_spmm<KB><<<1, WG, 0, G.st>>>(b->grid_win, b->part, b->ctrl);
+                k_fin_spmm<KB><<<KB, WG, 0, G.st>>>(b->grid_win, b->part, b->ctrl);
                 k_update_batched<double, KB><<<b->grid_vec, WG, 0, G.st>>>(n, b->X, b->R, b->P, b->Q, minv, b->part,
                                                                           b->ctrl);
-                k_fin_update_batched<KB><<<1, WG, 0, G.st>>>(b->grid_vec, b->part, b->ctrl);
+                k_fin_update_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, b->part, b->ctrl);
             }
             HIPCHK(hipStreamEndCapture(G.st, &b->graph));
             HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -212,7 +212,7 @@ struct ServerOps {
                                                                 KB, b->part);
         HIPCHK(hipGetLastError());
         const int max_iter = s.o.max_iter > 0 ? s.o.max_iter : 2000;
-        k_fin_init_batched<KB><<<1, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, mode, mask, tol, max_iter, 1, b->ctrl);
+        k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, mode, mask, tol, max_iter, 1, b->ctrl);
         HIPCHK(hipGetLastError());
         b->running |= mask;
         return FJ_OK;
@@ -227,7 +227,7 @@ struct ServerOps {
             k_epilogue_batched<Vc, KB><<<grid, WG, 0, G.st>>>(Gc, desc, G.pl.K, KB, b->finishing, b->X, b->S, KB, b->R,
                                                               b->part, b->ctrl);
             HIPCHK(hipGetLastError());
-            k_fin_epilogue_batched<KB><<<1, WG, 0, G.st>>>(grid, G.g.n, b->finishing, b->part, b->ctrl);
+            k_fin_epilogue_batched<KB><<<KB, WG, 0, G.st>>>(grid, G.g.n, b->finishing, b->part, b->ctrl);
             HIPCHK(hipGetLastError());
             return FJ_OK;
         });
