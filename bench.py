@@ -114,8 +114,9 @@ def batched_forms(args, fj, W, torch, dev):
 
 
 def serving_form(args, fj, W, torch, dev):
-    """Poisson request stream on 32 resident graphs through fj_server: the
-    saturation throughput, then p50/p99 latency at 0.5, 0.8 and 0.95 of it."""
+    """Poisson request stream on 32 resident graphs through fj_server, FP64 and
+    FJ_MIXED: the saturation throughput, then p50/p99 latency at 0.5, 0.8 and
+    0.95 of it. Returns {"serving": ..., "serving_mixed": ...}."""
     import numpy as np
     params = W.serving_graph_params()
     t0 = time.perf_counter()
@@ -128,61 +129,66 @@ def serving_form(args, fj, W, torch, dev):
     t_gen = time.perf_counter() - t0
     print(f"[bench] serving: 32 graphs ready in {t_gen:.1f}s", file=sys.stderr, flush=True)
     arena_bytes = 96 << 30
-    srv = fj.Server(arena_bytes, block_columns=16, iters_per_replay=8, eps=args.eps)
-    gids = [srv.add_graph(G) for G in graphs]
+    out = {}
+    for name, prec in (("serving", fj.FJ_FP64), ("serving_mixed", fj.FJ_MIXED)):
+        srv = fj.Server(arena_bytes, block_columns=16, iters_per_replay=8, eps=args.eps, precision=prec)
+        gids = [srv.add_graph(G) for G in graphs]
 
-    def run(reqs, arrivals):
-        """Submit request i at arrivals[i] seconds after the start; drive the
-        server until all complete. Returns per-request (latency_ms, k, status)."""
-        order = {}
-        start = time.perf_counter()
-        nxt = 0
-        out = []
-        while nxt < len(reqs) or srv.pending:
-            now = time.perf_counter() - start
-            while nxt < len(reqs) and arrivals[nxt] <= now:
-                gi, k, c0 = reqs[nxt]
-                rid = srv.submit(gids[gi], pools[gi][:, c0:c0 + k])
-                order[rid] = (nxt, k)
-                nxt += 1
-            srv.step()
-            for r in srv.poll():
-                i, k = order[r["id"]]
-                out.append((i, r["latency_ms"], k, r["status"]))
-        return out, time.perf_counter() - start
+        def run(reqs, arrivals):
+            """Submit request i at arrivals[i] seconds after the start; drive the
+            server until all complete. Returns per-request (latency_ms, k, status)."""
+            order = {}
+            start = time.perf_counter()
+            nxt = 0
+            res = []
+            while nxt < len(reqs) or srv.pending:
+                now = time.perf_counter() - start
+                while nxt < len(reqs) and arrivals[nxt] <= now:
+                    gi, k, c0 = reqs[nxt]
+                    rid = srv.submit(gids[gi], pools[gi][:, c0:c0 + k])
+                    order[rid] = (nxt, k)
+                    nxt += 1
+                srv.step()
+                for r in srv.poll():
+                    i, k = order[r["id"]]
+                    res.append((i, r["latency_ms"], k, r["status"]))
+            return res, time.perf_counter() - start
 
-    n_sat = max(args.serve_requests // 2, 32)
-    reqs = W.serving_requests(n_sat + 64, len(graphs), seed=3000)
-    run(reqs[:32], [0.0] * 32)  # warm-up (graph capture, first touches)
-    res, el = run(reqs[32:], [0.0] * (len(reqs) - 32))
-    solves = sum(k for _, _, k, _ in res)
-    sat_rps = len(res) / el
-    sat = {"requests_per_s": sat_rps, "solves_per_s": solves / el, "requests": len(res),
-           "all_certified": all(st == 0 for *_, st in res)}
-    print(f"[bench] serving saturation: {sat_rps:.1f} req/s, {solves / el:.1f} solves/s", file=sys.stderr, flush=True)
-    levels = {}
-    for f in (0.5, 0.8, 0.95):
-        rate = f * sat_rps
-        warm = max(args.serve_requests // 10, 10)
-        reqs = W.serving_requests(warm + args.serve_requests, len(graphs), seed=3001 + int(100 * f))
-        gaps = np.random.default_rng(4000 + int(100 * f)).exponential(1.0 / rate, len(reqs))
-        res, el = run(reqs, np.cumsum(gaps))
-        meas = sorted((i, lat, k, st) for i, lat, k, st in res if i >= warm)
-        lat = np.array([m[1] for m in meas])
-        solves = sum(m[2] for m in meas)
-        levels[f"{f:.2f}"] = {"offered_requests_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
-                              "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-                              "solves_per_s": solves / el, "measured_requests": len(meas),
-                              "all_certified": all(m[3] == 0 for m in meas)}
-        print(f"[bench] serving load {f}: p50 {levels[f'{f:.2f}']['p50_ms']:.1f} ms, "
-              f"p99 {levels[f'{f:.2f}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
-    srv.close()
+        n_sat = max(args.serve_requests // 2, 32)
+        reqs = W.serving_requests(n_sat + 64, len(graphs), seed=3000)
+        run(reqs[:32], [0.0] * 32)  # warm-up (graph capture, first touches)
+        res, el = run(reqs[32:], [0.0] * (len(reqs) - 32))
+        solves = sum(k for _, _, k, _ in res)
+        sat_rps = len(res) / el
+        sat = {"requests_per_s": sat_rps, "solves_per_s": solves / el, "requests": len(res),
+               "all_certified": all(st == 0 for *_, st in res)}
+        print(f"[bench] {name} saturation: {sat_rps:.1f} req/s, {solves / el:.1f} solves/s", file=sys.stderr,
+              flush=True)
+        levels = {}
+        for f in (0.5, 0.8, 0.95):
+            rate = f * sat_rps
+            warm = max(args.serve_requests // 10, 10)
+            reqs = W.serving_requests(warm + args.serve_requests, len(graphs), seed=3001 + int(100 * f))
+            gaps = np.random.default_rng(4000 + int(100 * f)).exponential(1.0 / rate, len(reqs))
+            res, el = run(reqs, np.cumsum(gaps))
+            meas = sorted((i, lat, k, st) for i, lat, k, st in res if i >= warm)
+            lat = np.array([m[1] for m in meas])
+            solves = sum(m[2] for m in meas)
+            levels[f"{f:.2f}"] = {"offered_requests_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                                  "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                                  "solves_per_s": solves / el, "measured_requests": len(meas),
+                                  "all_certified": all(m[3] == 0 for m in meas)}
+            print(f"[bench] {name} load {f}: p50 {levels[f'{f:.2f}']['p50_ms']:.1f} ms, "
+                  f"p99 {levels[f'{f:.2f}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        srv.close()
+        out[name] = {"description": "32 resident Chung-Lu graphs (n log-uniform in [1e4, 2e6], gamma U[2.1,2.8], "
+                                    "mean degree U[5,40]); requests of 1-16 U[0,1] vectors, graph uniform, Poisson "
+                                    "arrivals; 16-column blocks, 8 captured CG iterations per replay, "
+                                    + ("FP64" if prec == fj.FJ_FP64 else "FP32 inner CG with FP64 refinement"),
+                     "setup_s": t_gen, "saturation": sat, "load_levels": levels}
     del graphs, pools
     torch.cuda.empty_cache()
-    return {"description": "32 resident Chung-Lu graphs (n log-uniform in [1e4, 2e6], gamma U[2.1,2.8], "
-                           "mean degree U[5,40]); requests of 1-16 U[0,1] vectors, graph uniform, Poisson "
-                           "arrivals; 16-column blocks, 8 captured CG iterations per replay, FP64",
-            "setup_s": t_gen, "saturation": sat, "load_levels": levels}
+    return out
 
 
 def main():
@@ -346,7 +352,7 @@ def main():
     if args.batched_steps > 0:
         result["forms"].update(batched_forms(args, fj, W, torch, dev))
     if args.serve_requests > 0:
-        result["forms"]["serving"] = serving_form(args, fj, W, torch, dev)
+        result["forms"].update(serving_form(args, fj, W, torch, dev))
 
     if args.cpu_solves > 0:
         from oracle import sparse as O

@@ -204,12 +204,14 @@ int fj_indices(const fj_csr *g, const void *plan, int32_t k, const double *S, in
 /* ---- serving ------------------------------------------------------------ */
 /*
  * A continuous-batching server for index requests on resident graphs
- * (Algorithm 1 for many opinion vectors arriving over time, FP64). Graphs and
+ * (Algorithm 1 for many opinion vectors arriving over time). Graphs and
  * plans stay caller-owned on the device. Each graph with work gets a block of
  * CG state for `block_columns` opinion vectors, carved from the caller's HBM
- * arena; a graph whose block does not fit waits until another block is
- * released. A request of k <= block_columns vectors is admitted when k
- * columns of its graph's block are free, while the other columns keep
+ * arena; a block stays allocated while its graph is idle, and a graph whose
+ * block does not fit first releases idle blocks of other graphs (least
+ * recently used first), else waits until one becomes idle. The columns of a request (k <= block_columns vectors) enter free
+ * columns of its graph's block in arrival order as soon as columns free up,
+ * a request possibly in several pieces, while the other columns keep
  * iterating (continuous batching). Blocks replay HIP graphs of captured CG
  * iterations on one stream per graph, so different graphs overlap on the
  * device. Every column is certified to eps exactly as fj_indices would, and
@@ -225,7 +227,7 @@ typedef struct fj_server_opts {
     int32_t iters_per_replay;   /* CG iterations per captured HIP graph (e.g. 8) */
     double eps;                 /* certified relative error of every index, in (0, 1/2) */
     int32_t max_iter;           /* CG iterations per column over all passes; 0 = 2000 */
-    int32_t reserved;           /* must be 0 */
+    int32_t precision;          /* FJ_FP64, or FJ_MIXED (FP32 inner CG, FP64 refinement, as fj_indices) */
 } fj_server_opts;
 
 typedef struct fj_server_done {
@@ -235,8 +237,8 @@ typedef struct fj_server_done {
     double latency_ms;          /* from fj_server_submit to the step that retired the request */
 } fj_server_done;
 
-/* Device bytes of one block for a graph of n nodes. */
-size_t fj_server_block_bytes(int32_t n, int32_t block_columns);
+/* Device bytes of one block for a graph of n nodes (0 for invalid arguments). */
+size_t fj_server_block_bytes(int32_t n, int32_t block_columns, int32_t precision);
 
 int fj_server_create(const fj_server_opts *opts, fj_server **out);
 

@@ -765,7 +765,7 @@ struct Batched {
                                                         S.part);
         HIPCHK(hipGetLastError());
         k_fin_init_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter,
-                                                   range_check ? 1 : 0, S.ctrl);
+                                                   range_check ? 1 : 0, S.ctrl, 1);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
@@ -979,7 +979,7 @@ struct Batched {
         while (active && *outer < 8 && inner_total < max_iter) {
             ++*outer;
             const int mode = *outer == 1 ? 0 : 1;
-            k_mixed_cast_batched<KB><<<grid_vec, WG, 0, c.st>>>(n, S.R, I.R, mode, active, S.ctrl);
+            k_mixed_cast_batched<KB><<<grid_vec, WG, 0, c.st>>>(n, S.R, I.R, mode, active, S.ctrl, 1);
             HIPCHK(hipGetLastError());
             if (int rc = init(I, nullptr, 0, k, 0, 2, active, tau, max_iter - inner_total, false)) return rc;
             if (int rc = run(I, k, ci)) return rc;
@@ -1404,13 +1404,15 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
     return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
 }
 
-size_t fj_server_block_bytes(int32_t n, int32_t block_columns) {
+size_t fj_server_block_bytes(int32_t n, int32_t block_columns, int32_t precision) {
     if (n < 1 || (block_columns != 16 && block_columns != 64)) return 0;
-    return block_bytes(n, block_columns);
+    if (precision != FJ_FP64 && precision != FJ_MIXED) return 0;
+    return block_bytes(n, block_columns, precision == FJ_MIXED);
 }
 
 int fj_server_create(const fj_server_opts* opts, fj_server** out) {
-    if (!opts || !out || opts->reserved != 0) return FJ_ERR_INVALID_ARG;
+    if (!opts || !out) return FJ_ERR_INVALID_ARG;
+    if (opts->precision != FJ_FP64 && opts->precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
     if (opts->block_columns != 16 && opts->block_columns != 64) return FJ_ERR_INVALID_ARG;
     if (opts->iters_per_replay < 1 || opts->iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
     if (!(opts->eps > 0.0 && opts->eps < 0.5) || opts->max_iter < 0) return FJ_ERR_INVALID_ARG;
@@ -1469,7 +1471,8 @@ int fj_server_submit(fj_server* srv, int32_t graph_id, int32_t k, const double* 
     if (graph_id < 0 || graph_id >= static_cast<int32_t>(s->graphs.size())) return FJ_ERR_INVALID_ARG;
     if (k < 1 || k > s->o.block_columns || lds < k) return FJ_ERR_INVALID_ARG;
     ServerGraph& G = s->graphs[graph_id];
-    if (block_bytes(G.g.n, s->o.block_columns) > s->o.arena_bytes) return FJ_ERR_WORKSPACE;  // could never run
+    if (block_bytes(G.g.n, s->o.block_columns, s->o.precision == FJ_MIXED) > s->o.arena_bytes)
+        return FJ_ERR_WORKSPACE;  // could never run
     ServerRequest r;
     r.id = s->next_id++;
     r.gid = graph_id;
@@ -1478,6 +1481,7 @@ int fj_server_submit(fj_server* srv, int32_t graph_id, int32_t k, const double* 
     r.lds = lds;
     r.out = out;
     r.info = info;
+    r.remaining = k;
     r.t_submit = std::chrono::steady_clock::now();
     s->requests[r.id] = r;
     G.queue.push_back(r.id);

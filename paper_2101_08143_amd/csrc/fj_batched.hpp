@@ -396,11 +396,13 @@ __global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double*
 template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, const double* __restrict__ part,
                                                          int mode, uint64_t mask, ColumnTol tol, int max_iter,
-                                                         int range_check, Ctrl* __restrict__ ctrl) {
+                                                         int range_check, Ctrl* __restrict__ ctrl, int stop_others) {
     const int c = blockIdx.x;  // one workgroup per column
     Ctrl& C = ctrl[c];
     if (!((mask >> c) & 1ull)) {
-        if (mode == 2 && threadIdx.x == 0) C.done = CONVERGED;  // an inner solve runs only the masked columns
+        // an inner solve of the eager path runs only the masked columns; the
+        // server keeps the others running
+        if (mode == 2 && stop_others && threadIdx.x == 0) C.done = CONVERGED;
         return;
     }
     __shared__ double red[NWAVE * 5];
@@ -501,12 +503,14 @@ __global__ void __launch_bounds__(WG) k_fin_epilogue_batched(int G, int n_nodes,
 }
 
 // FJ_MIXED, batched: r32 = f32(r / ||r||) and z += ||r|| d per column (mode
-// as in k_mixed_cast); columns outside `mask` are left alone.
+// as in k_mixed_cast). Columns outside `mask` are left alone, except that the
+// cast zeroes their r32 when zero_others is set.
 template <int KB>
 __global__ void __launch_bounds__(WG) k_mixed_cast_batched(int n, const double* __restrict__ R64,
                                                            float* __restrict__ R32, int mode, uint64_t mask,
-                                                           const Ctrl* __restrict__ ctrl) {
+                                                           const Ctrl* __restrict__ ctrl, int zero_others) {
     const int c = threadIdx.x % KB;
+    if (!zero_others && !((mask >> c) & 1ull)) return;  // leave the other columns alone
     const double rho = mode == 0 ? sqrt(ctrl[c].ss) : ctrl[c].res[5];
     const double inv = (((mask >> c) & 1ull) && rho > 0.0) ? 1.0 / rho : 0.0;
     const int64_t total = static_cast<int64_t>(n) * KB;
@@ -535,6 +539,13 @@ __global__ void __launch_bounds__(WG) k_fill_zero(double* __restrict__ p, int64_
 __global__ void k_ctrl_set_done(Ctrl* __restrict__ ctrl, int count, uint64_t mask, int value) {
     const int c = threadIdx.x;
     if (c < count && ((mask >> c) & 1ull)) ctrl[c].done = value;
+}
+
+// res[5] = ||s|| for the columns in mask: the scale of the first inner solve
+// of FJ_MIXED, so that every later cast and correction reads res[5].
+__global__ void k_ctrl_rho_from_s(Ctrl* __restrict__ ctrl, int count, uint64_t mask) {
+    const int c = threadIdx.x;
+    if (c < count && ((mask >> c) & 1ull)) ctrl[c].res[5] = sqrt(ctrl[c].ss);
 }
 
 // Clear the control blocks of the columns in mask (the others keep running).

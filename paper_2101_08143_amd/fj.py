@@ -70,7 +70,7 @@ class fj_info(ctypes.Structure):
 class fj_server_opts(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("block_columns", ctypes.c_int32),
                 ("iters_per_replay", ctypes.c_int32), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32)]
 
 
 class fj_server_done(ctypes.Structure):
@@ -117,7 +117,7 @@ def lib():
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
                                  P(fj_info)]
-        L.fj_server_block_bytes.argtypes = [i32, i32]
+        L.fj_server_block_bytes.argtypes = [i32, i32, i32]
         L.fj_server_block_bytes.restype = sz
         L.fj_server_create.argtypes = [P(fj_server_opts), P(vp)]
         L.fj_server_destroy.argtypes = [vp]
@@ -329,12 +329,13 @@ class Server:
     one torch allocation; requests keep their opinion tensors alive here
     until they complete."""
 
-    def __init__(self, arena_bytes, block_columns=16, iters_per_replay=8, eps=1e-6, max_iter=0, device="cuda"):
+    def __init__(self, arena_bytes, block_columns=16, iters_per_replay=8, eps=1e-6, max_iter=0, device="cuda",
+                 precision=FJ_FP64):
         import torch
         self.arena = _aligned_empty(torch, arena_bytes, device)
         self.opts = fj_server_opts(arena=self.arena.data_ptr(), arena_bytes=int(arena_bytes),
                                    block_columns=block_columns, iters_per_replay=iters_per_replay, eps=eps,
-                                   max_iter=max_iter, reserved=0)
+                                   max_iter=max_iter, precision=precision)
         self.handle = ctypes.c_void_p()
         rc = lib().fj_server_create(ctypes.byref(self.opts), ctypes.byref(self.handle))
         if rc != FJ_OK:
@@ -343,8 +344,8 @@ class Server:
         self.pending = {}
 
     @staticmethod
-    def block_bytes(n, block_columns=16):
-        return lib().fj_server_block_bytes(int(n), int(block_columns))
+    def block_bytes(n, block_columns=16, precision=0):
+        return lib().fj_server_block_bytes(int(n), int(block_columns), int(precision))
 
     def add_graph(self, graph: Graph) -> int:
         gid = ctypes.c_int32()

@@ -39,8 +39,15 @@ def env():
     return torch, fj, graphs, G, reqs
 
 
-def _run(fj, torch, G, reqs, arena_bytes, block_columns=16):
-    srv = fj.Server(arena_bytes, block_columns=block_columns, iters_per_replay=6)
+PRECISIONS = ["fp64", "mixed"]
+
+
+def _prec(fj, precision):
+    return fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+
+
+def _run(fj, torch, G, reqs, arena_bytes, block_columns=16, precision="fp64"):
+    srv = fj.Server(arena_bytes, block_columns=block_columns, iters_per_replay=6, precision=_prec(fj, precision))
     gids = [srv.add_graph(g) for g in G]
     ids = [srv.submit(gids[gi], torch.from_numpy(S).to("cuda:0")) for gi, S in reqs]
     res = {r["id"]: r for r in srv.drain(timeout_s=240)}
@@ -48,41 +55,44 @@ def _run(fj, torch, G, reqs, arena_bytes, block_columns=16):
     return [res[i] for i in ids]
 
 
-def test_server_certified_and_matches_oracle(env):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_certified_and_matches_oracle(env, precision):
     torch, fj, graphs, G, reqs = env
-    say("server mixed run")
-    mixed = _run(fj, torch, G, reqs, 1 << 30)
+    say(f"server mixed run {precision}")
+    mixed = _run(fj, torch, G, reqs, 1 << 30, precision=precision)
     assert all(r["status"] == fj.FJ_OK for r in mixed)
     for (gi, S), r in list(zip(reqs, mixed))[:8]:
         for c in range(0, S.shape[1], 5):
             ref, _, _ = O.indices(graphs[gi], S[:, c])
             for name in NAMES:
                 assert abs(r["values"][c][name] - ref[name]) <= 1e-6 * abs(ref[name])
-    env_cache["mixed"] = mixed
+    env_cache[precision] = mixed
 
 
 env_cache = {}
 
 
-def test_server_result_same_alone_and_in_mix(env):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_result_same_alone_and_in_mix(env, precision):
     torch, fj, graphs, G, reqs = env
-    mixed = env_cache.get("mixed") or _run(fj, torch, G, reqs, 1 << 30)
+    mixed = env_cache.get(precision) or _run(fj, torch, G, reqs, 1 << 30, precision=precision)
     for idx in (0, 7, 19, 33):
-        say(f"alone request {idx}")
-        alone = _run(fj, torch, G, [reqs[idx]], 1 << 30)[0]
+        say(f"alone request {idx} {precision}")
+        alone = _run(fj, torch, G, [reqs[idx]], 1 << 30, precision=precision)[0]
         assert alone["values"] == mixed[idx]["values"], idx
 
 
-def test_server_admission_by_footprint(env):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_admission_by_footprint(env, precision):
     """An arena that holds only one block at a time: requests on other graphs
-    wait for the block to be released, and all still complete certified."""
+    wait until an idle block can be released, and all still complete certified."""
     torch, fj, graphs, G, reqs = env
     biggest = max(g.n for g in graphs)
-    arena = fj.Server.block_bytes(biggest, 16) + 4096
-    say("small arena")
-    res = _run(fj, torch, G, reqs[:12], arena)
+    arena = fj.Server.block_bytes(biggest, 16, _prec(fj, precision)) + 4096
+    say(f"small arena {precision}")
+    res = _run(fj, torch, G, reqs[:12], arena, precision=precision)
     assert all(r["status"] == fj.FJ_OK for r in res)
-    ref = env_cache.get("mixed")
+    ref = env_cache.get(precision)
     if ref:
         for a, b in zip(res, ref[:12]):
             assert a["values"] == b["values"]
@@ -100,19 +110,42 @@ def test_server_errors(env):
         srv.submit(gid0, torch.zeros((graphs[3].n, 17), dtype=torch.float64, device="cuda:0"))
     assert e.value.status == fj.FJ_ERR_INVALID_ARG
     srv.close()
+    with pytest.raises(fj.FJError) as e:
+        fj.Server(1 << 20, block_columns=16, precision=7)
+    assert e.value.status == fj.FJ_ERR_INVALID_ARG
+    assert fj.Server.block_bytes(1000, 16, 7) == 0
 
 
-def test_server_graph_replays_equal_eager_batched_path(env):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_rejects_opinions_out_of_range(env, precision):
+    """A request whose opinions leave [0, 1] comes back FJ_ERR_OPINION_RANGE;
+    the requests sharing its block are unaffected."""
+    torch, fj, graphs, G, reqs = env
+    say(f"server range check {precision}")
+    bad = np.array(reqs[2][1], copy=True)
+    bad[5, 0] = 1.5
+    res = _run(fj, torch, G, [reqs[2], (reqs[2][0], bad), reqs[3]], 1 << 30, precision=precision)
+    assert res[1]["status"] == fj.FJ_ERR_OPINION_RANGE
+    assert res[0]["status"] == fj.FJ_OK and res[2]["status"] == fj.FJ_OK
+    ref = env_cache.get(precision)
+    if ref:
+        assert res[0]["values"] == ref[2]["values"] and res[2]["values"] == ref[3]["values"]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_graph_replays_equal_eager_batched_path(env, precision):
     """Server columns come from replayed HIP graphs interleaved with eager
     admission and epilogue kernels; a 16-vector request must equal the eager
-    batched fj_indices on the same 16 vectors (same block width), bitwise."""
+    batched fj_indices on the same 16 vectors (same block width and
+    precision), bitwise, also when it enters the block in pieces."""
     torch, fj, graphs, G, reqs = env
     rng = np.random.default_rng(3)
     for gi in (1, 2):
         S = np.ascontiguousarray(rng.random((graphs[gi].n, 16)))
-        say(f"replay vs eager graph {gi}")
-        eager, _, rc = fj.fj_indices(G[gi], torch.from_numpy(S).to("cuda:0"))
+        say(f"replay vs eager graph {gi} {precision}")
+        eager, _, rc = fj.fj_indices(G[gi], torch.from_numpy(S).to("cuda:0"),
+                                     fj.make_opts(precision=_prec(fj, precision)))
         assert rc == fj.FJ_OK
-        served = _run(fj, torch, G, [(gi, S), reqs[0], reqs[1], (gi, S)], 1 << 30)
+        served = _run(fj, torch, G, [(gi, S), reqs[0], reqs[1], (gi, S)], 1 << 30, precision=precision)
         assert served[0]["values"] == eager
         assert served[3]["values"] == eager
