@@ -81,6 +81,7 @@ typedef struct fj_csr {
 #define FJ_VALIDATE_GRAPH  4u  /* fj_prepare checks the CSR contract (synchronises) */
 #define FJ_PROFILE         8u  /* time every SpMV launch with HIP events (fills fj_info.ms_*) */
 #define FJ_NO_TUNE        16u  /* batched solves: skip the SpMM autotuner, use 1 column per lane and the full grid */
+#define FJ_WARM_START     32u  /* fj_solve, k = 1: Z holds the starting guess on entry (e.g. an earlier solution) */
 
 typedef struct fj_opts {
     double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */

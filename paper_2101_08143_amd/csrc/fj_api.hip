@@ -459,8 +459,17 @@ void fill_outputs(const Ctrl& c, int status, int passes, int outer, fj_indices_t
 // FP64: PCG passes until certified (indices) or until the true relative
 // residual meets rtol (solve); each further pass restarts from the true
 // residual with a tighter target.
+// Warm start: z = z0 (device, stride ldz), then the true residual and the
+// certificate of z0 itself; CG runs only if z0 does not already meet the
+// target. Returns 1 in *done when z0 is accepted as it is.
+int warm_start(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const double* z0, int64_t ldz, Ctrl* cc) {
+    HIPCHK(hipMemcpy2DAsync(S.x, sizeof(double), z0, sizeof(double) * ldz, sizeof(double), c.g->n,
+                            hipMemcpyDeviceToDevice, c.st));
+    return epilogue(c, S, s, lds, cc);
+}
+
 int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const fj_opts& o, bool want_indices,
-               fj_indices_t* out, fj_info* info) {
+               fj_indices_t* out, fj_info* info, const double* z0 = nullptr, int64_t ldz = 0) {
     const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
     double rtol = o.rtol > 0.0 ? o.rtol : o.eps * 1e-2;
     const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
@@ -469,6 +478,25 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     int status = FJ_OK;
     double prev_rho = INFINITY;
     if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check)) return rc;
+    if (z0) {
+        if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
+        const double snorm = cc.res[6], rho = cc.res[5];
+        if (cc.done == BAD_INPUT) {
+            status = FJ_ERR_OPINION_RANGE;
+        } else if (want_indices ? certified(cc, o.eps) : (snorm == 0.0 || rho <= rtol * snorm)) {
+            status = FJ_OK;
+        } else {
+            status = -1;  // iterate from z0
+            prev_rho = rho;
+            if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check)) return rc;
+        }
+        if (status >= 0) {
+            cc.iters = 0;
+            fill_outputs(cc, status, 0, 0, out, info);
+            return status;
+        }
+        status = FJ_OK;
+    }
     for (;;) {
         ++passes;
         if (int rc = cg_run(c, S, passes == 1 ? 0 : cc.iters, max_iter, &cc)) return rc;
@@ -509,7 +537,7 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
 // residual tau; z += ||r|| d in FP64; FP64 epilogue (true residual, indices,
 // certificate). tau is chosen so that the next step should certify.
 int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, int64_t lds, const fj_opts& o,
-                bool want_indices, fj_indices_t* out, fj_info* info) {
+                bool want_indices, fj_indices_t* out, fj_info* info, const double* z0 = nullptr, int64_t ldz = 0) {
     const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
     const double target = o.rtol > 0.0 ? o.rtol : o.eps * 1e-2;  // solve: relative residual to reach
     const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
@@ -527,9 +555,20 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
     double rho = snorm;
     double tau = 1e-4;
     int inner_total = 0, outer = 0, status = FJ_ERR_NOT_CONVERGED;
+    if (z0) {  // start the refinement from z0 and its true residual
+        if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
+        rho = cc.res[5];
+        if (want_indices ? certified(cc, o.eps) : (snorm == 0.0 || rho <= target * snorm)) {
+            cc.iters = 0;
+            fill_outputs(cc, FJ_OK, 0, 0, out, info);
+            return FJ_OK;
+        }
+        const double goal = want_indices ? needed_rho(cc, o.eps) : target * snorm;
+        tau = std::min(1e-2, std::max(1e-5, 0.5 * goal / rho));
+    }
     while (outer < 8 && inner_total < max_iter) {
         ++outer;
-        const int mode = outer == 1 ? 0 : 1;
+        const int mode = (outer == 1 && !z0) ? 0 : 1;
         k_mixed_cast<<<c.grid_vec, WG, 0, c.st>>>(n, S.r, I.r, mode, S.ctrl);
         HIPCHK(hipGetLastError());
         if (int rc = cg_init(c, I, nullptr, 0, 2, tau, max_iter - inner_total, false)) return rc;
@@ -588,6 +627,7 @@ int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, d
     Ctrl* ctrls = reinterpret_cast<Ctrl*>(W + wl.ctrl);
     double* part = reinterpret_cast<double*>(W + wl.part);
     const bool mixed = o.precision == FJ_MIXED;  // FP64 side of FJ_MIXED keeps only x and r
+    const bool warm = Z && (o.flags & FJ_WARM_START);
     CgState<double> S64{reinterpret_cast<double*>(W + wl.x), reinterpret_cast<double*>(W + wl.r),
                         mixed ? nullptr : reinterpret_cast<double*>(W + wl.p),
                         mixed ? nullptr : reinterpret_cast<double*>(W + wl.q), &ctrls[0], part};
@@ -596,9 +636,9 @@ int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, d
         CgState<float> S32{reinterpret_cast<float*>(W + wl.x32), reinterpret_cast<float*>(W + wl.r32),
                            reinterpret_cast<float*>(W + wl.p32), reinterpret_cast<float*>(W + wl.q32), &ctrls[1],
                            part};
-        status = solve_mixed(c, S64, S32, S, lds, o, want_indices, out, info);
+        status = solve_mixed(c, S64, S32, S, lds, o, want_indices, out, info, warm ? Z : nullptr, ldz);
     } else {
-        status = solve_fp64(c, S64, S, lds, o, want_indices, out, info);
+        status = solve_fp64(c, S64, S, lds, o, want_indices, out, info, warm ? Z : nullptr, ldz);
     }
     if (Z && status != FJ_ERR_HIP && status != FJ_ERR_OPINION_RANGE) {
         HIPCHK(hipMemcpy2DAsync(Z, sizeof(double) * ldz, S64.x, sizeof(double), sizeof(double), g->n,
@@ -1386,6 +1426,10 @@ int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int6
     if (int rc = check_graph_args(g)) return rc;
     if (int rc = check_opts(opts)) return rc;
     if (k < 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
+    if ((opts->flags & FJ_WARM_START) && (k != 1 || (opts->flags & FJ_TWO_SOLVE))) {
+        std::snprintf(g_last_error, sizeof g_last_error, "FJ_WARM_START needs k = 1 without FJ_TWO_SOLVE");
+        return FJ_ERR_INVALID_ARG;
+    }
     if (g->n == 0) return FJ_OK;
     if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
         return solve_one(g, plan, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);

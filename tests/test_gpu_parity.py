@@ -332,6 +332,35 @@ def test_batched_autotuner_records_a_shape(torch_fj):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_start(torch_fj, graphs, precision):
+    """FJ_WARM_START: from the converged z no iteration runs and z is returned
+    as it was; from a perturbed z the solve converges to the oracle's z in
+    fewer iterations than from zero; k > 1 is refused."""
+    torch, fj = torch_fj
+    g, G = graphs["cl50k_f32"]
+    say(f"warm start {precision}")
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    s = np.random.default_rng(41).random(g.n)
+    sd = torch.from_numpy(s).to("cuda:0")
+    o = fj.make_opts(rtol=1e-10, precision=prec)
+    ow = fj.make_opts(rtol=1e-10, precision=prec, flags=fj.FJ_WARM_START)
+    z_cold, info_cold, rc = fj.fj_solve(G, sd, o)
+    assert rc == fj.FJ_OK
+    z0 = z_cold.clone()
+    z_w, info_w, rc = fj.fj_solve(G, sd, ow, Z=z0)
+    assert rc == fj.FJ_OK and info_w[0].iters == 0 and torch.equal(z_w, z_cold)
+    zp = z_cold + 1e-4 * torch.from_numpy(np.random.default_rng(42).standard_normal(g.n)).to("cuda:0")
+    z_p, info_p, rc = fj.fj_solve(G, sd, ow, Z=zp.clone())
+    assert rc == fj.FJ_OK and info_p[0].iters < info_cold[0].iters
+    zref, _ = O.solve(g, s, rtol=1e-14)
+    assert np.linalg.norm(z_p.cpu().numpy() - zref) <= 1.1e-10 * np.linalg.norm(s)
+    S2 = torch.from_numpy(_block(g.n, 2, 5)).to("cuda:0")
+    Z2 = torch.zeros_like(S2)
+    _, _, rc = fj.fj_solve(G, S2, ow, Z=Z2, check=False)
+    assert rc == fj.FJ_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_solve_matches_oracle(torch_fj, graphs, precision):
     torch, fj = torch_fj
     g, G = graphs["cl100k_unit"]
