@@ -48,6 +48,7 @@ extern "C" {
 #define FJ_ERR_BREAKDOWN      6  /* CG breakdown (p^T (I+L) p <= 0 or not finite) */
 #define FJ_ERR_UNCERTIFIABLE  7  /* an index is too close to 0 for a relative bound; bounds are written */
 #define FJ_ERR_HIP            8  /* a HIP runtime call failed */
+#define FJ_ERR_CANCELLED      9  /* the request was withdrawn with fj_server_cancel */
 
 /* ---- graph -------------------------------------------------------------- */
 #define FJ_VAL_UNIT 0  /* every edge has weight 1; val must be NULL */
@@ -262,6 +263,15 @@ int fj_server_step(fj_server *srv, int32_t *busy_blocks);
 
 /* Completed requests since the last poll (up to max); *count receives how many. */
 int fj_server_poll(fj_server *srv, fj_server_done *done, int32_t max, int32_t *count);
+
+/*
+ * Withdraw a request that has not completed: its waiting columns leave the
+ * queue, its columns in the block stop iterating and free their slots, and
+ * fj_server_poll then reports it with status FJ_ERR_CANCELLED (its outputs
+ * are undefined). FJ_ERR_INVALID_ARG for an unknown or already completed
+ * request.
+ */
+int fj_server_cancel(fj_server *srv, uint64_t request_id);
 
 #ifdef __cplusplus
 }

@@ -1221,6 +1221,7 @@ const char* fj_status_string(int status) {
         case FJ_ERR_BREAKDOWN: return "CG breakdown";
         case FJ_ERR_UNCERTIFIABLE: return "an index is too close to zero to certify a relative error";
         case FJ_ERR_HIP: return "HIP runtime error";
+        case FJ_ERR_CANCELLED: return "request cancelled";
         default: return "unknown status";
     }
 }
@@ -1560,6 +1561,45 @@ int fj_server_poll(fj_server* srv, fj_server_done* done, int32_t max, int32_t* c
         ++n;
     }
     *count = n;
+    return FJ_OK;
+}
+
+int fj_server_cancel(fj_server* srv, uint64_t request_id) {
+    if (!srv) return FJ_ERR_INVALID_ARG;
+    Server* s = reinterpret_cast<Server*>(srv);
+    auto it = s->requests.find(request_id);
+    if (it == s->requests.end() || it->second.remaining == 0) return FJ_ERR_INVALID_ARG;
+    ServerRequest& r = it->second;
+    ServerGraph& G = s->graphs[r.gid];
+    for (auto q = G.queue.begin(); q != G.queue.end(); ++q)
+        if (*q == request_id) {
+            G.queue.erase(q);
+            break;
+        }
+    if (ServerBlock* b = G.blk) {
+        uint64_t mask = 0;
+        for (int c = 0; c < s->o.block_columns; ++c)
+            if (b->slot_req[c] == static_cast<int64_t>(request_id)) {
+                mask |= 1ull << c;
+                b->slot_req[c] = -1;
+            }
+        if (mask) {  // stream-ordered after any replay or epilogue in flight
+            for (Ctrl* cb : {b->ctrl, b->ictrl}) {
+                if (!cb) continue;
+                k_ctrl_set_done<<<1, WG, 0, G.st>>>(cb, s->o.block_columns, mask, static_cast<int>(CONVERGED));
+                HIPCHK(hipGetLastError());
+            }
+            b->running &= ~mask;
+            b->finishing &= ~mask;
+            // the caller may free the request's opinion vectors once it is
+            // reported: let the scatter that read them finish first
+            HIPCHK(hipStreamSynchronize(G.st));
+        }
+    }
+    r.status = FJ_ERR_CANCELLED;
+    r.remaining = 0;
+    r.t_done = std::chrono::steady_clock::now();
+    s->completed.push_back(request_id);
     return FJ_OK;
 }
 

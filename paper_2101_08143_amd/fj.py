@@ -31,6 +31,7 @@ FJ_ERR_NOT_CONVERGED = 5
 FJ_ERR_BREAKDOWN = 6
 FJ_ERR_UNCERTIFIABLE = 7
 FJ_ERR_HIP = 8
+FJ_ERR_CANCELLED = 9
 
 FJ_VAL_UNIT, FJ_VAL_F32, FJ_VAL_F64 = 0, 1, 2
 FJ_FP64, FJ_MIXED = 0, 1
@@ -43,7 +44,7 @@ EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_byte
            "fj_workspace_bytes", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
            "fj_indices", "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
-           "fj_server_step", "fj_server_poll")
+           "fj_server_step", "fj_server_poll", "fj_server_cancel")
 
 
 class fj_csr(ctypes.Structure):
@@ -125,8 +126,10 @@ def lib():
         L.fj_server_submit.argtypes = [vp, i32, i32, vp, i64, P(fj_indices_t), P(fj_info), P(ctypes.c_uint64)]
         L.fj_server_step.argtypes = [vp, P(i32)]
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
+        L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
         for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
-                     "fj_indices", "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll"):
+                     "fj_indices", "fj_server_create", "fj_server_destroy", "fj_server_add_graph",
+                     "fj_server_submit", "fj_server_step", "fj_server_poll", "fj_server_cancel"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -388,6 +391,12 @@ class Server:
                             values=[{nm: getattr(out[c], nm) for nm in INDEX_NAMES} for c in range(k)],
                             infos=[info_dict(info[c]) for c in range(k)]))
         return res
+
+    def cancel(self, rid: int):
+        """Withdraw a request; poll() then reports it with FJ_ERR_CANCELLED."""
+        rc = lib().fj_server_cancel(self.handle, ctypes.c_uint64(rid))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_server_cancel")
 
     def drain(self, timeout_s=300.0):
         """Step until every submitted request has completed; returns their results."""

@@ -149,3 +149,27 @@ def test_server_graph_replays_equal_eager_batched_path(env, precision):
         served = _run(fj, torch, G, [(gi, S), reqs[0], reqs[1], (gi, S)], 1 << 30, precision=precision)
         assert served[0]["values"] == eager
         assert served[3]["values"] == eager
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_cancel(env, precision):
+    """Cancelling a queued request and one already iterating: both come back
+    FJ_ERR_CANCELLED, the freed columns take later requests, and the other
+    requests still give their results bitwise."""
+    torch, fj, graphs, G, reqs = env
+    say(f"server cancel {precision}")
+    srv = fj.Server(1 << 30, block_columns=16, iters_per_replay=6, precision=_prec(fj, precision))
+    gids = [srv.add_graph(g) for g in G]
+    picks = [r for r in reqs if r[0] == 1][:4]
+    ids = [srv.submit(gids[gi], torch.from_numpy(S).to("cuda:0")) for gi, S in picks]
+    srv.step()  # admits what fits and starts iterating
+    srv.cancel(ids[0])
+    srv.cancel(ids[-1])
+    with pytest.raises(fj.FJError):
+        srv.cancel(12345678)
+    res = {r["id"]: r for r in srv.drain(timeout_s=240)}
+    assert res[ids[0]]["status"] == fj.FJ_ERR_CANCELLED and res[ids[-1]]["status"] == fj.FJ_ERR_CANCELLED
+    alone = _run(fj, torch, G, picks[1:3], 1 << 30, precision=precision)
+    for rid, ref in zip(ids[1:3], alone):
+        assert res[rid]["status"] == fj.FJ_OK and res[rid]["values"] == ref["values"]
+    srv.close()
