@@ -159,6 +159,16 @@ int fj_solve(const fj_csr *g, const void *plan, int32_t k, const double *S, int6
              void *stream, fj_info *info);
 
 /*
+ * Algorithm 1's a-priori solver accuracy for an n-node graph with weights in
+ * [w_min, w_max], centred opinions of norm sbar_norm and error parameter
+ * eps: delta = eps w_min ||sbar|| / (3 w_max n^3 (n w_max + 1) sqrt(n)).
+ * Reported beside the a-posteriori certificate that the library uses
+ * instead (delta lies far below FP64 resolution at these sizes). Host only;
+ * returns NaN for arguments outside the algorithm's domain.
+ */
+double fj_apriori_delta(int64_t n, double w_min, double w_max, double sbar_norm, double eps);
+
+/*
  * The SpMM launch shape the autotuner chose for this graph (same pointers, n
  * and nnz), block width kb (2, 4, ..., 64) and precision (FJ_FP64: FP64
  * vectors; FJ_MIXED: the FP32 inner vectors) on the current device:

@@ -1303,6 +1303,13 @@ int fj_apply(const fj_csr* g, const void* plan, const double* x, double* y, void
     });
 }
 
+double fj_apriori_delta(int64_t n, double w_min, double w_max, double sbar_norm, double eps) {
+    if (n < 1 || !(w_min > 0.0) || !(w_max >= w_min) || !(sbar_norm >= 0.0) || !(eps > 0.0 && eps < 0.5))
+        return NAN;
+    const double nd = static_cast<double>(n);
+    return eps * w_min * sbar_norm / (3.0 * w_max * nd * nd * nd * (nd * w_max + 1.0) * std::sqrt(nd));
+}
+
 int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl, int32_t* grid) {
     if (int rc = check_graph_args(g)) return rc;
     if (!cpl || !grid || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;

@@ -41,7 +41,7 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
-           "fj_workspace_bytes", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
+           "fj_workspace_bytes", "fj_apply", "fj_apriori_delta", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
            "fj_indices", "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll", "fj_server_cancel")
@@ -112,6 +112,8 @@ def lib():
         L.fj_workspace_bytes.argtypes = [P(fj_csr), i32, P(fj_opts)]
         L.fj_workspace_bytes.restype = sz
         L.fj_apply.argtypes = [P(fj_csr), vp, vp, vp, vp]
+        L.fj_apriori_delta.argtypes = [i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.fj_apriori_delta.restype = ctypes.c_double
         L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32)]
         L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32]
         L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
@@ -245,6 +247,11 @@ def _check_block(graph, S, name):
     if S.dim() != 2 or S.shape[0] != graph.n or S.stride(1) != 1:
         raise ValueError(f"{name} must be n x k with unit column stride")
     return S, S.shape[1], S.stride(0)
+
+
+def fj_apriori_delta(n: int, w_min: float, w_max: float, sbar_norm: float, eps: float) -> float:
+    """Algorithm 1's a-priori solver accuracy delta (for reports)."""
+    return lib().fj_apriori_delta(int(n), float(w_min), float(w_max), float(sbar_norm), float(eps))
 
 
 def fj_spmm_choice(graph: Graph, kb: int, precision: int = 0):

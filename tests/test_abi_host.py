@@ -3,6 +3,7 @@ function include/fj.h declares, rejects bad arguments before touching the
 device, and the row-window partition the kernels assume holds on the
 generated workloads."""
 import ctypes
+import math
 import os
 import re
 
@@ -133,3 +134,16 @@ def test_window_partition_invariants(name):
         ns = (elast if long_last else eend) - rp[r0]
         assert 0 <= ns < WIN + LONGROW
     assert covered == g.n
+
+
+def test_apriori_delta(lib):
+    """Algorithm 1's delta (its first line) for a 10^4-node unit-weight graph
+    and U[0,1] opinions: about 1e-23, far below FP64 resolution, which is why
+    the library certifies a posteriori instead."""
+    n, sbar = 10_000, (10_000 / 12) ** 0.5
+    d = fj.fj_apriori_delta(n, 1.0, 1.0, sbar, 1e-6)
+    assert d == pytest.approx(1e-6 * sbar / (3 * n**3 * (n + 1) * n**0.5), rel=1e-12)
+    assert 5e-24 < d < 2e-23 and d < 2.0**-52
+    assert fj.fj_apriori_delta(4_000_000, 0.5, 2.0, 100.0, 1e-6) < 1e-34
+    assert math.isnan(fj.fj_apriori_delta(0, 1.0, 1.0, 1.0, 1e-6))
+    assert math.isnan(fj.fj_apriori_delta(10, 1.0, 1.0, 1.0, 0.5))
