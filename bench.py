@@ -119,7 +119,8 @@ def batched_forms(args, fj, W, torch, dev):
             "spmm_avg_launch_ms": avg,
             "spmm_achieved_GBs": b / (avg * 1e-3) / 1e9 if avg > 0 else None,
             "spmm_algorithmic_bytes_per_launch": b,
-            "spmm_tuned_shape": {"columns_per_lane": shape[0], "grid": shape[1]} if shape else None,
+            "spmm_tuned_shape": {"columns_per_lane": shape[0], "grid": shape[1], "split_rows": bool(shape[2])}
+            if shape else None,
             "spmm_default_shape_avg_launch_ms": untuned,
         }
         print(f"[bench] {name}: {1e3 * el:.1f} ms per call", file=sys.stderr, flush=True)

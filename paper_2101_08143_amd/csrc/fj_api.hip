@@ -671,6 +671,7 @@ struct SpmmKey {
 };
 struct SpmmChoice {
     int cpl = 1, grid = 1;
+    bool split = true;  // merge-path item split over lane groups, or one group per row
 };
 std::mutex g_tune_mu;
 std::map<SpmmKey, SpmmChoice> g_tune;
@@ -684,30 +685,33 @@ int spmm_key(const fj_csr* g, int kb, int tbytes, SpmmKey* k) {
 
 template <typename Vc, typename T, int KB>
 struct Spmm {
-    static int full_grid(int cpl, int K, int* grid) {
+    template <int CPL>
+    static int grid_of(bool split, int K, int* grid) {
+        return split ? grid_for(k_spmm_cg<Vc, T, KB, CPL, true>, K, grid)
+                     : grid_for(k_spmm_cg<Vc, T, KB, CPL, false>, K, grid);
+    }
+    static int full_grid(int cpl, bool split, int K, int* grid) {
         if constexpr (KB % 4 == 0)
-            if (cpl == 4) return grid_for(k_spmm_cg<Vc, T, KB, 4>, K, grid);
+            if (cpl == 4) return grid_of<4>(split, K, grid);
         if constexpr (KB % 2 == 0)
-            if (cpl == 2) return grid_for(k_spmm_cg<Vc, T, KB, 2>, K, grid);
-        return grid_for(k_spmm_cg<Vc, T, KB, 1>, K, grid);
+            if (cpl == 2) return grid_of<2>(split, K, grid);
+        return grid_of<1>(split, K, grid);
+    }
+    template <int CPL>
+    static int go(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
+                  const T* P, const T* R, const float* minv, T* Q, double* part) {
+        if (ch.split) k_spmm_cg<Vc, T, KB, CPL, true><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
+        else k_spmm_cg<Vc, T, KB, CPL, false><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
     }
     static int launch(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
                       const T* P, const T* R, const float* minv, T* Q, double* part) {
         if constexpr (KB % 4 == 0)
-            if (ch.cpl == 4) {
-                k_spmm_cg<Vc, T, KB, 4><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
-                HIPCHK(hipGetLastError());
-                return FJ_OK;
-            }
+            if (ch.cpl == 4) return go<4>(ch, st, G, desc, K, P, R, minv, Q, part);
         if constexpr (KB % 2 == 0)
-            if (ch.cpl == 2) {
-                k_spmm_cg<Vc, T, KB, 2><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
-                HIPCHK(hipGetLastError());
-                return FJ_OK;
-            }
-        k_spmm_cg<Vc, T, KB, 1><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
-        HIPCHK(hipGetLastError());
-        return FJ_OK;
+            if (ch.cpl == 2) return go<2>(ch, st, G, desc, K, P, R, minv, Q, part);
+        return go<1>(ch, st, G, desc, K, P, R, minv, Q, part);
     }
     // The launch shape for this graph: cached, or tuned now on the caller's
     // vectors (Q and part are overwritten; the next SpMM recomputes them).
@@ -716,7 +720,8 @@ struct Spmm {
                       SpmmChoice* out) {
         if (!tune) {
             out->cpl = 1;
-            return full_grid(1, K, &out->grid);
+            out->split = true;
+            return full_grid(1, true, K, &out->grid);
         }
         SpmmKey key{};
         if (int rc = spmm_key(g, KB, static_cast<int>(sizeof(T)), &key)) return rc;
@@ -729,12 +734,15 @@ struct Spmm {
             }
         }
         std::vector<SpmmChoice> cand;
-        for (int cpl : {1, 2, 4}) {
-            if (KB % cpl != 0) continue;
-            int full = 1;
-            if (int rc = full_grid(cpl, K, &full)) return rc;
-            cand.push_back({cpl, full});
-            if (full >= 2) cand.push_back({cpl, full / 2});
+        for (bool split : {true, false}) {
+            for (int cpl : {1, 2, 4}) {
+                if (KB % cpl != 0) continue;
+                if (!split && KB / cpl < 8) continue;  // a row per group of < 8 lanes serialises long rows
+                int full = 1;
+                if (int rc = full_grid(cpl, split, K, &full)) return rc;
+                cand.push_back({cpl, full, split});
+                if (full >= 2) cand.push_back({cpl, full / 2, split});
+            }
         }
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -1310,9 +1318,10 @@ double fj_apriori_delta(int64_t n, double w_min, double w_max, double sbar_norm,
     return eps * w_min * sbar_norm / (3.0 * w_max * nd * nd * nd * (nd * w_max + 1.0) * std::sqrt(nd));
 }
 
-int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl, int32_t* grid) {
+int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl, int32_t* grid,
+                   int32_t* split) {
     if (int rc = check_graph_args(g)) return rc;
-    if (!cpl || !grid || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
+    if (!cpl || !grid || !split || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
     if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
     SpmmKey key{};
     if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
@@ -1321,18 +1330,20 @@ int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl,
     if (it == g_tune.end()) return FJ_ERR_INVALID_ARG;
     *cpl = it->second.cpl;
     *grid = it->second.grid;
+    *split = it->second.split ? 1 : 0;
     return FJ_OK;
 }
 
-int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid) {
+int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid, int32_t split) {
     if (int rc = check_graph_args(g)) return rc;
     if (kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
     if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
     if ((cpl != 1 && cpl != 2 && cpl != 4) || kb % cpl != 0 || grid < 1 || grid > GMAX) return FJ_ERR_INVALID_ARG;
+    if (split != 0 && split != 1) return FJ_ERR_INVALID_ARG;
     SpmmKey key{};
     if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[key] = SpmmChoice{cpl, grid};
+    g_tune[key] = SpmmChoice{cpl, grid, split == 1};
     return FJ_OK;
 }
 

@@ -57,8 +57,208 @@ __device__ __forceinline__ void load_cols(const T* __restrict__ p, double (&out)
     }
 }
 
-// The rows of the workgroup's windows (blockIdx.x, +gridDim.x, ...). A row is
-// owned by a group of GW = KB / CPL lanes; lane l of the group owns columns
+// LDS of the batched window pass: the window's column indices, weights and
+// row ends (staged with coalesced loads), and per group the sums of the row
+// its item range ends inside of (also reused to combine a long last row).
+template <typename V, int KB, int CPL>
+struct SpmmStage {
+    static constexpr int NG = WG / (KB / CPL);
+    int col[STAGE];
+    typename WeightReg<V>::type w[std::is_same<V, Unit>::value ? 1 : STAGE];
+    int rend[WIN + 1];
+    double plin[NG * KB];
+    double psq[NG * KB];
+};
+
+// The windows k0, k0 + G, ... of the workgroup (k0 = blockIdx.x). A group of
+// GW = KB / CPL lanes works like one thread of the single-vector pass: lane l
+// owns columns l*CPL .. l*CPL + CPL - 1, and group g walks the items
+// (entries and row ends, in CSR order) [g*ipg, (g+1)*ipg) of the window, so
+// every group gets the same share of the window whatever the row lengths.
+// Each entry costs one CPL-wide gather per lane (the group reads the
+// neighbour's KB values as one contiguous run). op.row(i, q, c, x_ic,
+// sum_j w_ij (x_ic - x_jc), sum_j w_ij (x_ic - x_jc)^2) is called once per row
+// and column, by the group holding the row's end; a row begun in earlier
+// groups first adds their partial sums, in group order. Each column's row
+// sum thus follows a fixed order set by the data alone. A long last row is
+// split over all groups and combined in group order.
+template <typename T, typename V, typename Acc, int KB, int CPL, typename Op>
+__device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
+                                             const T* __restrict__ X, Op& op, SpmmStage<V, KB, CPL>& st) {
+    static_assert(KB % CPL == 0, "CPL must divide KB");
+    constexpr int GW = KB / CPL;
+    constexpr int NG = WG / GW;
+    constexpr bool WEIGHTED = !std::is_same<V, Unit>::value;
+    const int tid = threadIdx.x;
+    const int lane = tid % GW;
+    const int grp = tid / GW;
+    const int c0 = lane * CPL;
+
+    for (int k = blockIdx.x; k < K; k += gridDim.x) {
+        const WinDesc d = to_scalar(load_raw_desc(desc + k));
+        const int nrs = d.nrs, ns = d.ns;
+        for (int e = tid; e < ns; e += WG) {
+            st.col[e] = stream_load(&g.col[d.e0 + e]);
+            if constexpr (WEIGHTED) st.w[e] = stream_load(&g.val[d.e0 + e]);
+        }
+        for (int a = tid; a < nrs; a += WG) st.rend[a] = g.row_ptr[d.r0 + a + 1] - d.e0;
+        __syncthreads();
+        const int total = nrs + ns;
+        const int ipg = (total + NG - 1) / NG;
+        const int i0 = min(grp * ipg, total);
+        const int i1 = min(i0 + ipg, total);
+        int lo = 0, hi = nrs;
+        while (lo < hi) {  // a0 = number of row ends before item i0 (row a's end is item rend[a] + a)
+            const int mid = (lo + hi) >> 1;
+            if (st.rend[mid] + mid < i0) lo = mid + 1;
+            else hi = mid;
+        }
+        const int a0 = lo;
+        int a = a0;
+        int j = i0 - a0;
+        const bool continued = (i0 < i1) && (j > (a0 > 0 ? st.rend[a0 - 1] : 0));
+        int row_end = a < nrs ? st.rend[a] : 0;
+        double xi[CPL], lin[CPL], sq[CPL], flin[CPL], fsq[CPL];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) lin[q] = sq[q] = flin[q] = fsq[q] = 0.0;
+        if (a < nrs) load_cols<T, CPL>(X + static_cast<int64_t>(d.r0 + a) * KB + c0, xi);
+        bool first_pending = false;
+        int dd = i0;
+        while (dd < i1) {
+            if (j < row_end) {  // a run of entries of row a
+                const int run = min(row_end - j, i1 - dd);
+                int u = 0;
+                for (; u + 4 <= run; u += 4) {  // four gathers in flight
+                    int jj[4];
+                    double w[4], xj[4][CPL];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        jj[v] = st.col[j + u + v];
+                        w[v] = WEIGHTED ? static_cast<double>(st.w[j + u + v]) : 1.0;
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) load_cols<T, CPL>(X + static_cast<int64_t>(jj[v]) * KB + c0, xj[v]);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                        for (int q = 0; q < CPL; ++q) {
+                            const double df = xi[q] - xj[v][q];
+                            lin[q] += w[v] * df;
+                            if constexpr (Acc::SQ) sq[q] += w[v] * df * df;
+                        }
+                    }
+                }
+                for (; u < run; ++u) {
+                    const int jc = st.col[j + u];
+                    const double w = WEIGHTED ? static_cast<double>(st.w[j + u]) : 1.0;
+                    double xj[CPL];
+                    load_cols<T, CPL>(X + static_cast<int64_t>(jc) * KB + c0, xj);
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) {
+                        const double df = xi[q] - xj[q];
+                        lin[q] += w * df;
+                        if constexpr (Acc::SQ) sq[q] += w * df * df;
+                    }
+                }
+                j += run;
+                dd += run;
+            } else {  // end of row a
+                if (a == a0 && continued) {
+                    first_pending = true;
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) {
+                        flin[q] = lin[q];
+                        fsq[q] = sq[q];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) op.row(d.r0 + a, q, c0 + q, xi[q], lin[q], sq[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) lin[q] = sq[q] = 0.0;
+                ++a;
+                ++dd;
+                if (a < nrs) {
+                    row_end = st.rend[a];
+                    load_cols<T, CPL>(X + static_cast<int64_t>(d.r0 + a) * KB + c0, xi);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {  // the row still open at the end of the range
+            st.plin[grp * KB + c0 + q] = lin[q];
+            if constexpr (Acc::SQ) st.psq[grp * KB + c0 + q] = sq[q];
+        }
+        __syncthreads();
+        if (first_pending) {  // groups t0 .. grp-1 hold the rest of row a0
+            const int t0 = (a0 > 0 ? st.rend[a0 - 1] + a0 : 0) / ipg;
+            double xr[CPL];
+            load_cols<T, CPL>(X + static_cast<int64_t>(d.r0 + a0) * KB + c0, xr);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                double L = flin[q], S = fsq[q];
+                for (int t = grp - 1; t >= t0; --t) {
+                    L += st.plin[t * KB + c0 + q];
+                    if constexpr (Acc::SQ) S += st.psq[t * KB + c0 + q];
+                }
+                op.row(d.r0 + a0, q, c0 + q, xr[q], L, S);
+            }
+        }
+        if (d.long_last) {  // workgroup-uniform
+            __syncthreads();  // plin / psq are reused below
+            const int i = d.r1 - 1;
+            double xl[CPL], L[CPL], Sq[CPL];
+            load_cols<T, CPL>(X + static_cast<int64_t>(i) * KB + c0, xl);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) L[q] = Sq[q] = 0.0;
+            // group gr takes entry chunks elast + gr*GW, elast + (gr+NG)*GW, ...; lane l loads entry l of a chunk
+            for (int e0 = d.elast + grp * GW; e0 < d.eend; e0 += NG * GW) {
+                const int e = e0 + lane;
+                int jl = 0;
+                double wl = 0.0;
+                if (e < d.eend) {
+                    jl = g.col[e];
+                    wl = weight_at<V>(g.val, e);
+                }
+                const int cnt = min(GW, d.eend - e0);
+                for (int t = 0; t < cnt; ++t) {
+                    const int jc = __shfl(jl, t, GW);
+                    const double w = WEIGHTED ? shfl_d(wl, t, GW) : 1.0;
+                    double xj[CPL];
+                    load_cols<T, CPL>(X + static_cast<int64_t>(jc) * KB + c0, xj);
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) {
+                        const double df = xl[q] - xj[q];
+                        L[q] += w * df;
+                        if constexpr (Acc::SQ) Sq[q] += w * df * df;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                st.plin[grp * KB + c0 + q] = L[q];
+                st.psq[grp * KB + c0 + q] = Sq[q];
+            }
+            __syncthreads();
+            if (grp == 0) {
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    double LL = 0.0, SS = 0.0;
+                    for (int gr = 0; gr < NG; ++gr) {
+                        LL += st.plin[gr * KB + c0 + q];
+                        SS += st.psq[gr * KB + c0 + q];
+                    }
+                    op.row(i, q, c0 + q, xl[q], LL, SS);
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next window
+    }
+}
+
+// Row-per-group variant of the window pass (an autotuner candidate for wide
+// blocks): the rows of the workgroup's windows (blockIdx.x, +gridDim.x, ...).
+// A row is owned by a group of GW = KB / CPL lanes; lane l of the group owns columns
 // l*CPL .. l*CPL + CPL - 1 and calls op.row(i, q, c, x_ic,
 // sum_j w_ij (x_ic - x_jc), sum_j w_ij (x_ic - x_jc)^2) for each of them
 // (q = c - l*CPL). Each column's row sum runs over the row's entries in CSR
@@ -66,7 +266,7 @@ __device__ __forceinline__ void load_cols(const T* __restrict__ p, double (&out)
 // workgroup and combined in LDS in group order. lred must hold
 // 2 * WG * CPL doubles.
 template <typename T, typename V, typename Acc, int KB, int CPL, typename Op>
-__device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
+__device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
                                              const T* __restrict__ X, Op& op, double* lred) {
     static_assert(KB % CPL == 0, "CPL must divide KB");
     constexpr int GW = KB / CPL;
@@ -255,15 +455,25 @@ struct OpSpmmEpilogue {  // per column: the sums of OpEpilogue; R is written for
 
 // ------------------------------------------------------------ kernels
 
-template <typename V, typename T, int KB, int CPL>
+// SPLIT: merge-path item split over lane groups (spmm_windows); otherwise one
+// group per row (spmm_rows).
+template <typename V, typename T, int KB, int CPL, bool SPLIT>
 __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                 const T* __restrict__ P, const T* __restrict__ R,
                                                 const float* __restrict__ minv, T* __restrict__ Q,
                                                 double* __restrict__ part) {
-    __shared__ double lred[12 * WG];
     OpSpmmCg<T, KB, CPL> op{R, minv, Q};
-    spmm_windows<T, V, AccLin, KB, CPL>(g, desc, K, P, op, lred);
-    store_column_partials<3, KB, CPL>(op.v, lred, part);
+    if constexpr (SPLIT) {
+        __shared__ SpmmStage<V, KB, CPL> st;
+        static_assert(sizeof(st) >= 3 * WG * CPL * sizeof(double), "stage too small to reuse for the partials");
+        spmm_windows<T, V, AccLin, KB, CPL>(g, desc, K, P, op, st);
+        // the window pass ended with a barrier: its LDS now holds the partial sums
+        store_column_partials<3, KB, CPL>(op.v, reinterpret_cast<double*>(&st), part);
+    } else {
+        __shared__ double lred[12 * WG];
+        spmm_rows<T, V, AccLin, KB, CPL>(g, desc, K, P, op, lred);
+        store_column_partials<3, KB, CPL>(op.v, lred, part);
+    }
 }
 
 template <int KB>
@@ -461,9 +671,10 @@ __global__ void __launch_bounds__(WG) k_epilogue_batched(Csr<V> g, const WinDesc
                                                          const double* __restrict__ S, int64_t lds,
                                                          double* __restrict__ R, double* __restrict__ part,
                                                          const Ctrl* __restrict__ ctrl) {
-    __shared__ double lred[12 * WG];
+    __shared__ SpmmStage<V, KB, 1> st;
+    __shared__ double lred[9 * WG];
     OpSpmmEpilogue<KB> op{S, lds, k, mask, ctrl, R};
-    spmm_windows<double, V, AccLinSq, KB, 1>(g, desc, K, Z, op, lred);
+    spmm_windows<double, V, AccLinSq, KB, 1>(g, desc, K, Z, op, st);
     store_column_partials<9, KB, 1>(op.v, lred, part);
 }
 

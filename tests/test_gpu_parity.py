@@ -283,22 +283,23 @@ def test_batched_indices_match_oracle(torch_fj, graphs, k, precision):
 @pytest.mark.parametrize("name", ["cl50k_f32", "star6001", "gnp500_f64"])
 @pytest.mark.parametrize("k", [3, 16])
 @pytest.mark.parametrize("cpl", [1, 2, 4])
+@pytest.mark.parametrize("split", [1, 0])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batched_every_spmm_shape_matches_oracle(torch_fj, name, k, cpl, precision):
+def test_batched_every_spmm_shape_matches_oracle(torch_fj, name, k, cpl, split, precision):
     """Each SpMM launch shape the autotuner can pick (columns per lane, full or
-    half grid), pinned in turn on a freshly prepared graph: certified indices
-    within 1e-6 of the oracle, and the row sums (hence the solve) agree between
-    shapes to the stopping tolerance."""
+    a small grid, items split over lane groups or one group per row), pinned in
+    turn on a freshly prepared graph: certified indices within 1e-6 of the
+    oracle."""
     torch, fj = torch_fj
     g = small_graphs()[name]
     G = fj.Graph.from_csr(g, device="cuda:0", validate=False)
     kb = 4 if k == 3 else 16
     prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
     S = _block(g.n, k, 300 + k)
-    say(f"spmm shape {name} k={k} cpl={cpl} {precision}")
+    say(f"spmm shape {name} k={k} cpl={cpl} split={split} {precision}")
     grid = 64 if cpl == 2 else 512
-    fj.fj_spmm_set_choice(G, kb, cpl, grid, precision=prec)
-    assert fj.fj_spmm_choice(G, kb, prec) == (cpl, grid)
+    fj.fj_spmm_set_choice(G, kb, cpl, grid, precision=prec, split=split)
+    assert fj.fj_spmm_choice(G, kb, prec) == (cpl, grid, split)
     vals, infos, rc = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(eps=EPS, precision=prec),
                                     check=False)
     assert rc == fj.FJ_OK
@@ -322,8 +323,8 @@ def test_batched_autotuner_records_a_shape(torch_fj):
     assert rc0 == fj.FJ_OK and fj.fj_spmm_choice(G, 16, fj.FJ_FP64) is None
     v1, _, rc1 = fj.fj_indices(G, S, fj.make_opts(eps=EPS), check=False)
     assert rc1 == fj.FJ_OK
-    cpl, grid = fj.fj_spmm_choice(G, 16, fj.FJ_FP64)
-    assert cpl in (1, 2, 4) and 1 <= grid <= 4096
+    cpl, grid, split = fj.fj_spmm_choice(G, 16, fj.FJ_FP64)
+    assert cpl in (1, 2, 4) and 1 <= grid <= 4096 and split in (0, 1)
     v2, _, _ = fj.fj_indices(G, S, fj.make_opts(eps=EPS), check=False)
     assert v2 == v1  # the cached choice is reused: bitwise repeatable
     for c in range(16):
