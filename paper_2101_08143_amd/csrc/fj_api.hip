@@ -478,6 +478,13 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     int status = FJ_OK;
     double prev_rho = INFINITY;
     if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check)) return rc;
+    if (!z0 && !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N) {  // start from mean(s) 1
+        k_cg_shift<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, c.minv(), S.ctrl, S.part);
+        HIPCHK(hipGetLastError());
+        k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
+                                       S.ctrl);
+        HIPCHK(hipGetLastError());
+    }
     if (z0) {
         if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
         const double snorm = cc.res[6], rho = cc.res[5];

@@ -895,6 +895,44 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
     }
 }
 
+// Single-vector FP64 solves of graphs from this many nodes on start from
+// mean(s) 1 (below, the two extra launches cost more than the iteration they
+// save; the batched and mixed-precision drivers measured no gain from it).
+constexpr int MEAN_START_MIN_N = 65536;
+
+// Start CG from the constant vector mean(s) 1 instead of 0. Since
+// (I + L) 1 = 1 (L 1 = 0, Section 2.1), its residual is exactly the centred
+// s - mean(s) 1, and the remaining error z - mean(s) 1 is the centred
+// solution that Algorithm 1 solves for separately (Section 2.2: Omega 1 = 1),
+// whose energy is far smaller than that of z. Runs after k_cg_init mode 0
+// (r = s, mu known); k_fin_init mode 1 then takes rz and rr.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_cg_shift(int n, T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
+                                                 const float* __restrict__ minv, const Ctrl* __restrict__ ctrl,
+                                                 double* __restrict__ part) {
+    __shared__ double red[NWAVE * 2];
+    const double mu = ctrl->mu;
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        x[i] = static_cast<T>(mu);
+        const T rt = static_cast<T>(static_cast<double>(r[i]) - mu);
+        r[i] = rt;
+        const double ri = static_cast<double>(rt);
+        const T zt = static_cast<T>(static_cast<double>(minv[i]) * ri);
+        p[i] = zt;
+        v[0] += ri * static_cast<double>(zt);
+        v[1] += ri * ri;
+    }
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+        double* out = part + blockIdx.x * NPART;
+        out[0] = v[0];
+        out[1] = v[1];
+        out[5] = INFINITY;
+        out[6] = -INFINITY;
+    }
+}
+
 __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __restrict__ part, int mode,
                                                  double rtol2, int max_iter, int range_check,
                                                  Ctrl* __restrict__ ctrl) {

@@ -332,6 +332,33 @@ def test_batched_autotuner_records_a_shape(torch_fj):
             assert abs(v0[c][nm] - v1[c][nm]) <= 2 * EPS * abs(v0[c][nm])
 
 
+@pytest.mark.parametrize("k", [1, 16])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_and_mean_start_both_match_oracle(torch_fj, graphs, k, precision):
+    """Single-vector FP64 solves of graphs of >= 65536 nodes start CG from
+    mean(s) 1 by default (its residual is the centred s, since (I + L) 1 = 1);
+    FJ_ZERO_START starts from 0 (the other drivers always do). Both certify and
+    match the oracle; the mean start needs no more iterations."""
+    torch, fj = torch_fj
+    g, G = graphs["cl100k_unit"]
+    say(f"zero vs mean start k={k} {precision}")
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    S = _block(g.n, k, 500 + k)
+    Sd = torch.from_numpy(S if k > 1 else S[:, 0].copy()).to("cuda:0")
+    res = {}
+    for flags in (0, fj.FJ_ZERO_START):
+        vals, infos, rc = fj.fj_indices(G, Sd, fj.make_opts(eps=EPS, precision=prec, flags=flags), check=False)
+        assert rc == fj.FJ_OK
+        res[flags] = (vals, infos)
+    for c in range(0, k, 5):
+        ref, _, _ = O.indices(g, S[:, c])
+        for flags, (vals, infos) in res.items():
+            for nm in NAMES:
+                assert abs(vals[c][nm] - ref[nm]) <= EPS * abs(ref[nm]), (flags, c, nm)
+    if precision == "fp64" and k == 1:
+        assert res[0][1][0].iters <= res[fj.FJ_ZERO_START][1][0].iters
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_warm_start(torch_fj, graphs, precision):
     """FJ_WARM_START: from the converged z no iteration runs and z is returned
