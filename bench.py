@@ -305,8 +305,22 @@ def main():
     val_bytes = 0 if g.val is None else g.val.dtype.itemsize
     b_launch = spmv_bytes(g.n, g.nnz, val_bytes)
     avg_ms = fp64["ms_spmv"] / max(fp64["n_spmv"], 1)
+    work_ms = fp64["ms_spmv"] / max(fp64["iters"], 1)  # launches past convergence return at once
     bytes_per_launch = b_launch * fp64["iters"] / max(fp64["n_spmv"], 1)  # launches after convergence do no work
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    # the bare CSR-order gather over the same matrix: the floor for the SpMV
+    xg = torch.rand(g.n, dtype=torch.float64, device=dev)
+    yg = fj.fj_gather_bound(G, xg)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        fj.fj_gather_bound(G, xg, yg)
+    e1.record()
+    torch.cuda.synchronize()
+    gather_ms = e0.elapsed_time(e1) / 10
+    del xg, yg
 
     vals, info = fp64["vals"], fp64["info"]
     result = {
@@ -336,6 +350,11 @@ def main():
             "launches": fp64["n_spmv"],
             "working_launches": fp64["iters"],
             "algorithmic_bytes_per_working_launch": b_launch,
+            "working_launch_ms": work_ms,
+            "gather_ceiling_ms": gather_ms,
+            "frac_of_gather_ceiling": gather_ms / work_ms if work_ms > 0 else None,
+            "gather_ceiling_note": "fj_gather_bound: the same col/val streams and one random x_j gather per "
+                                   "entry, nothing else; random gathers, not HBM bytes, bound this kernel",
         },
         "detail": {
             "iters_per_solve": info.iters,

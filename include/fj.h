@@ -194,6 +194,17 @@ int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t c
                        int32_t split);
 
 /*
+ * Measurement aid (not part of any solve): the bare gather of an SpMV over
+ * this CSR in storage order, y[t] = sum_{e = 8t}^{8t+7} w_e x[col_e], with
+ * eight gathers in flight per thread and no row bookkeeping. Its duration is
+ * the floor for any pass that reads the CSR once and gathers x per entry in
+ * this order (the gather rate, not HBM bandwidth, bounds such passes on
+ * power-law graphs). x: device double[n]; y: device double[(nnz + 7) / 8].
+ * Asynchronous on `stream`.
+ */
+int fj_gather_bound(const fj_csr *g, const double *x, double *y, void *stream);
+
+/*
  * The FJ opinion dynamics itself (Section 3.1, Eq. FJmodel): up to `steps`
  * synchronous updates z_i <- (s_i + sum_j w_ij z_j) / (1 + sum_j w_ij) from
  * z0 (NULL: start from s). Stops after the first step whose largest change

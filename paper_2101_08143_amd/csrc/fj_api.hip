@@ -1354,6 +1354,21 @@ int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t c
     return FJ_OK;
 }
 
+int fj_gather_bound(const fj_csr* g, const double* x, double* y, void* stream) {
+    if (int rc = check_graph_args(g)) return rc;
+    if (g->nnz == 0) return FJ_OK;
+    if (!x || !y) return FJ_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return with_graph(g, [&](auto G) -> int {
+        using Vc = typename decltype(G)::value_type;
+        int grid = 1;
+        if (int rc = grid_for(k_gather_bound<Vc>, (g->nnz / 8 + WG) / WG, &grid)) return rc;
+        k_gather_bound<Vc><<<grid, WG, 0, st>>>(G, x, y);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
+    });
+}
+
 int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,
                 int32_t steps, double tol, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
     if (int rc = check_graph_args(g)) return rc;

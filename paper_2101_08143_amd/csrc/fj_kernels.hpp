@@ -636,6 +636,36 @@ __global__ void __launch_bounds__(WG) k_apply(Csr<V> g, const WinDesc* __restric
     my_windows<double, V, AccLin>(g, desc, K, x, op, st, red);
 }
 
+// Measurement aid, not part of the solve: the bare gather of an SpMV in CSR
+// order. Thread t reads entries 8t .. 8t+7 (col and val, streamed) and
+// writes y[t] = sum w_e x_col(e), ignoring row boundaries, with eight gathers
+// in flight. Its time is the floor for any pass that reads the CSR once and
+// gathers x_j per entry in this order.
+template <typename V>
+__global__ void __launch_bounds__(WG) k_gather_bound(Csr<V> g, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t groups = (static_cast<int64_t>(g.nnz) + 7) / 8;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; t < groups;
+         t += static_cast<int64_t>(gridDim.x) * WG) {
+        int j[8];
+        double w[8], v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = t * 8 + u;
+            const int64_t ec = e < g.nnz ? e : g.nnz - 1;
+            j[u] = stream_load(&g.col[ec]);
+            double wv = 1.0;
+            if constexpr (!std::is_same<V, Unit>::value) wv = static_cast<double>(stream_load(&g.val[ec]));
+            w[u] = e < g.nnz ? wv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = x[j[u]];
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += w[u] * v[u];
+        y[t] = acc;
+    }
+}
+
 // One synchronous step of the FJ update rule (Section 3.1, Eq. FJmodel):
 // z'_i = (s_i + sum_j w_ij z_j) / (1 + sum_j w_ij), with the largest change
 // |z'_i - z_i| of the step.

@@ -42,8 +42,8 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
-           "fj_workspace_bytes", "fj_apply", "fj_apriori_delta", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
-           "fj_indices", "fj_server_block_bytes",
+           "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
+           "fj_spmm_set_choice", "fj_gather_bound", "fj_dynamics", "fj_indices", "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll", "fj_server_cancel")
 
@@ -117,6 +117,7 @@ def lib():
         L.fj_apriori_delta.restype = ctypes.c_double
         L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32)]
         L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32, i32]
+        L.fj_gather_bound.argtypes = [P(fj_csr), vp, vp, vp]
         L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
@@ -130,9 +131,10 @@ def lib():
         L.fj_server_step.argtypes = [vp, P(i32)]
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
-        for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_dynamics", "fj_solve",
-                     "fj_indices", "fj_server_create", "fj_server_destroy", "fj_server_add_graph",
-                     "fj_server_submit", "fj_server_step", "fj_server_poll", "fj_server_cancel"):
+        for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
+                     "fj_dynamics", "fj_solve", "fj_indices", "fj_server_create", "fj_server_destroy",
+                     "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll",
+                     "fj_server_cancel"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -270,6 +272,18 @@ def fj_spmm_set_choice(graph: Graph, kb: int, cpl: int, grid: int, precision: in
                                   int(split))
     if rc != FJ_OK:
         raise FJError(rc, "fj_spmm_set_choice")
+
+
+def fj_gather_bound(graph: Graph, x, y=None, stream=None):
+    """Measurement aid: the bare CSR-order gather (see include/fj.h). Returns y."""
+    import torch
+    assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == graph.n
+    if y is None:
+        y = torch.empty((graph.csr.nnz + 7) // 8, dtype=torch.float64, device=x.device)
+    rc = lib().fj_gather_bound(ctypes.byref(graph.csr), _ptr(x), _ptr(y), _stream_handle(torch, stream))
+    if rc != FJ_OK:
+        raise FJError(rc, "fj_gather_bound")
+    return y
 
 
 def fj_dynamics(graph: Graph, s, steps: int, tol: float = -1.0, z0=None, z=None, ws=None, stream=None):

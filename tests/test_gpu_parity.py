@@ -75,6 +75,20 @@ def test_apply_matches_oracle(torch_fj, graphs, name):
     assert np.all(np.abs(y - ref) <= _tolerance_apply(g, x))
 
 
+@pytest.mark.parametrize("name", ["cl50k_f32", "gnp500_f64", "star6001", "isolated9000"])
+def test_gather_bound_probe(torch_fj, graphs, name):
+    """The measurement aid fj_gather_bound computes y[t] = sum of w_e x[col_e]
+    over entries 8t .. 8t+7 (a padded tail counts zero)."""
+    torch, fj = torch_fj
+    g, G = graphs[name]
+    say(f"gather bound {name}")
+    x = np.random.default_rng(7).random(g.n)
+    y = fj.fj_gather_bound(G, torch.from_numpy(x).to("cuda:0")).cpu().numpy()
+    pad = (-g.nnz) % 8
+    prod = np.concatenate([g.weights_f64() * x[g.col], np.zeros(pad)]).reshape(-1, 8)
+    assert np.allclose(y, prod.sum(axis=1), rtol=1e-13, atol=1e-13)
+
+
 @pytest.mark.parametrize("name", [n for n in small_graphs() if n not in ("path5",)])
 @pytest.mark.parametrize("kind", ["uniform", "exp"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
