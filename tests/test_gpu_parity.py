@@ -75,6 +75,48 @@ def test_apply_matches_oracle(torch_fj, graphs, name):
     assert np.all(np.abs(y - ref) <= _tolerance_apply(g, x))
 
 
+def _random_case(seed):
+    """A graph of random family, size, weights and opinion law (seeded)."""
+    rng = np.random.default_rng(seed)
+    fam = seed % 5
+    if fam == 0:
+        g = W.random_graph(int(rng.integers(20, 3000)), float(rng.uniform(0.002, 0.05)), seed,
+                           weighted=bool(rng.integers(0, 2)), val_dtype=np.float32 if rng.integers(0, 2) else np.float64)
+    elif fam == 1:
+        g = W.barabasi_albert(int(rng.integers(50, 20000)), int(rng.integers(1, 6)), seed)
+    elif fam == 2:
+        g = W.chung_lu(int(rng.integers(1000, 60000)), float(rng.uniform(2.05, 3.0)), float(rng.uniform(2, 40)), seed,
+                       weighted=bool(rng.integers(0, 2)))
+    elif fam == 3:
+        g = W.cycle_graph(int(rng.integers(3, 50000)), float(rng.uniform(0.1, 5.0)))
+    else:
+        g = W.torus_graph(int(rng.integers(3, 200)), int(rng.integers(3, 200)))
+    kind = ["uniform", "exp", "pareto"][seed % 3]
+    return g, W.opinions(kind, g.n, seed + 1)
+
+
+@pytest.mark.parametrize("seed", list(range(40)))
+def test_random_graphs_match_oracle(torch_fj, seed):
+    """Forty seeded graphs of mixed families (G(n,p), Barabasi-Albert,
+    Chung-Lu, weighted cycles, tori), sizes, weight types and opinion laws:
+    FP64 indices within 1e-6 of the oracle and inside their own bounds; the
+    mixed path certified too."""
+    torch, fj = torch_fj
+    g, s = _random_case(seed)
+    say(f"random graph seed={seed} n={g.n} nnz={g.nnz}")
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    ref, _, _ = O.indices(g, s)
+    sd = torch.from_numpy(s).to("cuda:0")
+    for prec in (fj.FJ_FP64, fj.FJ_MIXED):
+        vals, infos, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, precision=prec), check=False)
+        if rc == fj.FJ_ERR_UNCERTIFIABLE:  # an index too close to 0 (e.g. disagreement on a tiny graph)
+            continue
+        assert rc == fj.FJ_OK, (prec, fj.info_dict(infos[0]))
+        for j, nm in enumerate(NAMES):
+            err = abs(vals[0][nm] - ref[nm]) / abs(ref[nm])
+            assert err <= EPS and err <= infos[0].bound[j] + 1e-12, (prec, nm, err)
+
+
 @pytest.mark.parametrize("name", ["cl50k_f32", "gnp500_f64", "star6001", "isolated9000"])
 def test_gather_bound_probe(torch_fj, graphs, name):
     """The measurement aid fj_gather_bound computes y[t] = sum of w_e x[col_e]
