@@ -260,6 +260,7 @@ struct CgState {
     T *x, *r, *p, *q;
     Ctrl* ctrl;
     double* part;
+    const double* s_est = nullptr;  // FP64 only: s (contiguous) for the on-device index estimates
 };
 
 // What every launch of a solve needs.
@@ -291,7 +292,7 @@ struct Ctx {
 
 template <typename T>
 int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, double rtol, int max_iter,
-            bool range_check) {
+            bool range_check, double eps_stop = 0.0) {
     const int n = c.g->n;
     if (mode != 1) {
         k_ctrl_reset<<<1, WG, 0, c.st>>>(S.ctrl, 1);
@@ -300,7 +301,7 @@ int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, doubl
     k_cg_init<T><<<c.grid_vec, WG, 0, c.st>>>(n, s, lds, S.x, S.r, S.p, c.minv(), mode, S.part);
     HIPCHK(hipGetLastError());
     k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, mode, rtol * rtol, max_iter, range_check ? 1 : 0,
-                                   S.ctrl);
+                                   S.ctrl, eps_stop);
     HIPCHK(hipGetLastError());
     return FJ_OK;
 }
@@ -326,10 +327,23 @@ int cg_iteration(Ctx& c, CgState<T>& S) {
     if (rc) return rc;
     k_fin_spmv<<<1, WG, 0, c.st>>>(grid_win, S.part, S.ctrl);
     HIPCHK(hipGetLastError());
-    k_cg_update<T><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, S.q, c.minv(), S.part, S.ctrl);
-    HIPCHK(hipGetLastError());
-    k_fin_update<<<1, WG, 0, c.st>>>(c.grid_vec, S.part, S.ctrl);
-    HIPCHK(hipGetLastError());
+    bool est = false;
+    if constexpr (std::is_same<T, double>::value) est = S.s_est != nullptr;
+    if (est) {
+        if constexpr (std::is_same<T, double>::value) {
+            k_cg_update<T, true><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, S.q, c.minv(), S.s_est, S.part,
+                                                             S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_fin_update<true><<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, S.ctrl);
+            HIPCHK(hipGetLastError());
+        }
+    } else {
+        k_cg_update<T, false><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, S.q, c.minv(), nullptr, S.part,
+                                                          S.ctrl);
+        HIPCHK(hipGetLastError());
+        k_fin_update<false><<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+    }
     return FJ_OK;
 }
 
@@ -477,12 +491,18 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     int passes = 0;
     int status = FJ_OK;
     double prev_rho = INFINITY;
-    if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check)) return rc;
+    // Default target: also stop as soon as the on-device estimates of all five
+    // indices at the current x meet 0.8 eps (the epilogue then certifies; the
+    // estimates differ from the certified values only at the order of rho).
+    const bool packable = lds == 1 && reinterpret_cast<uintptr_t>(s) % 16 == 0;  // read in 16-byte packs
+    const double eps_stop = (want_indices && o.rtol == 0.0 && packable && !z0) ? 0.8 * o.eps : 0.0;
+    S.s_est = eps_stop > 0.0 ? s : nullptr;
+    if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check, eps_stop)) return rc;
     if (!z0 && !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N) {  // start from mean(s) 1
         k_cg_shift<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, c.minv(), S.ctrl, S.part);
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
-                                       S.ctrl);
+                                       S.ctrl, eps_stop);
         HIPCHK(hipGetLastError());
     }
     if (z0) {
@@ -531,6 +551,7 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
         double next = rtol * 0.1;
         if (want_indices && snorm > 0.0) next = std::min(next, 0.5 * needed_rho(cc, o.eps) / snorm);
         rtol = std::max(next, 1e-16);
+        S.s_est = nullptr;  // a restart runs to its residual target
         if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check)) return rc;
     }
     fill_outputs(cc, status, passes, 0, out, info);
@@ -620,7 +641,7 @@ int make_ctx(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k
     c->st = static_cast<hipStream_t>(stream);
     c->profile = (o->flags & FJ_PROFILE) != 0;
     if (int rc = host_slots(&c->hs)) return rc;
-    return grid_for(k_cg_update<double>, (static_cast<int64_t>(g->n) + 2 * WG - 1) / (2 * WG), &c->grid_vec);
+    return grid_for(k_cg_update<double, true>, (static_cast<int64_t>(g->n) + 2 * WG - 1) / (2 * WG), &c->grid_vec);
 }
 
 // Single right-hand side, either precision. Z (may be null) receives z.
@@ -1104,7 +1125,7 @@ int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t ld
         k_cg_init<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S, lds, S64.X, S64.R, nullptr, c.minv(), 0, part);
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, part, 0, 1.0, max_iter,
-                                       (o.flags & FJ_NO_RANGE_CHECK) ? 0 : 1, ctrls);
+                                       (o.flags & FJ_NO_RANGE_CHECK) ? 0 : 1, ctrls, 0.0);
         HIPCHK(hipGetLastError());
         Ctrl st0{};
         HIPCHK(hipMemcpyAsync(&st0, ctrls, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));

@@ -55,6 +55,7 @@ struct Ctrl {
     double smin, smax;    // range of s
     double res[16];       // epilogue: indices, residual and diagnostics (see k_epilogue)
     double bound[5];      // certified relative error bound of each index
+    double eps_stop;      // > 0: also stop once the estimated bounds of all five indices are below it
     double hist[HIST];    // rr after iteration t is in hist[t % HIST]
     int32_t done;         // 0 running, 1 converged, 2 iteration cap, 3 breakdown, 4 bad input
     int32_t iters;        // CG iterations so far (all passes)
@@ -825,46 +826,109 @@ __device__ __forceinline__ void cg_update_pack(int t, double alpha, double beta,
     reinterpret_cast<P*>(p)[t] = pv;
 }
 
-template <typename T>
+// EST (single vector, FP64, s contiguous): also the sums that estimate the
+// five indices at the new x (Section 3.2 via Proposition 1: C = x^T x,
+// sum x for P, I_dc = s^T x, C_I ~ ||s - x||^2 since s - z = L z), for the
+// early stop in k_fin_update.
+template <bool EST>
+__device__ __forceinline__ void est_pack(int t, const double* __restrict__ x, const double* __restrict__ s,
+                                         double (&e)[4]) {
+    if constexpr (EST) {
+        const double2 xv = reinterpret_cast<const double2*>(x)[t];
+        const double2 sv = reinterpret_cast<const double2*>(s)[t];
+        e[0] += xv.x * xv.x + xv.y * xv.y;
+        e[1] += xv.x + xv.y;
+        e[2] += sv.x * xv.x + sv.y * xv.y;
+        const double d0 = sv.x - xv.x, d1 = sv.y - xv.y;
+        e[3] += d0 * d0 + d1 * d1;
+    }
+}
+
+template <typename T, bool EST>
 __global__ void __launch_bounds__(WG) k_cg_update(int n, T* __restrict__ x, T* __restrict__ r,
                                                   T* __restrict__ p, const T* __restrict__ q,
-                                                  const float* __restrict__ minv,
+                                                  const float* __restrict__ minv, const double* __restrict__ s,
                                                   double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    static_assert(!EST || std::is_same<T, double>::value, "estimates are for FP64 vectors");
     if (ctrl->done != RUNNING) return;
-    __shared__ double red[NWAVE * 2];
+    __shared__ double red[NWAVE * 6];
     constexpr int N = Pack<T>::N;
     const double alpha = ctrl->alpha, beta = ctrl->beta;
     double v[2] = {0.0, 0.0};
+    double e[4] = {0.0, 0.0, 0.0, 0.0};
     const int npack = n / N;
     const int stride = gridDim.x * WG;
     int t = blockIdx.x * WG + threadIdx.x;
     for (; t + stride < npack; t += 2 * stride) {  // two packs per thread in flight
         cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
         cg_update_pack(t + stride, alpha, beta, x, r, p, q, minv, v);
+        if constexpr (EST) {
+            est_pack<EST>(t, reinterpret_cast<const double*>(x), s, e);
+            est_pack<EST>(t + stride, reinterpret_cast<const double*>(x), s, e);
+        }
     }
-    if (t < npack) cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
+    if (t < npack) {
+        cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
+        if constexpr (EST) est_pack<EST>(t, reinterpret_cast<const double*>(x), s, e);
+    }
     if (blockIdx.x == 0 && threadIdx.x < n - npack * N) {
         const int i = npack * N + threadIdx.x;
         cg_update_elem(alpha, beta, x[i], r[i], p[i], q[i], minv[i], v);
+        if constexpr (EST) {
+            const double xi = static_cast<double>(x[i]), si = s[i];
+            e[0] += xi * xi;
+            e[1] += xi;
+            e[2] += si * xi;
+            e[3] += (si - xi) * (si - xi);
+        }
     }
-    block_sum<2>(v, red);
-    store_partials<2>(v, part);
+    if constexpr (EST) {
+        double w[6] = {v[0], v[1], e[0], e[1], e[2], e[3]};
+        block_sum<6>(w, red);
+        store_partials<6>(w, part);
+    } else {
+        block_sum<2>(v, red);
+        store_partials<2>(v, part);
+    }
 }
 
-__global__ void __launch_bounds__(WG) k_fin_update(int G, const double* __restrict__ part,
+// The relative error bound of an index from its value and the residual norm
+// it sees (see k_fin_epilogue); infinite when no relative bound exists.
+__device__ __forceinline__ double quad_bound(double X, double rh) {
+    const double rx = sqrt(fmax(X, 0.0));
+    return rx > rh ? rh * (2.0 * rx + rh) / ((rx - rh) * (rx - rh)) : INFINITY;
+}
+
+template <bool EST>
+__global__ void __launch_bounds__(WG) k_fin_update(int G, int n, const double* __restrict__ part,
                                                    Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ double red[NWAVE * 2];
-    double v[2];
-    total_partials<2>(G, part, v, red);
+    constexpr int NV = EST ? 6 : 2;
+    __shared__ double red[NWAVE * NV];
+    double v[NV];
+    total_partials<NV>(G, part, v, red);
     if (threadIdx.x == 0) {
         const int it = ctrl->iters + 1;
         ctrl->iters = it;
         ctrl->rz = v[0];
         ctrl->rr = v[1];
         ctrl->hist[it % HIST] = v[1];
+        bool early = false;
+        if constexpr (EST) {
+            // estimated indices at the new x with the recursive residual norm;
+            // the FP64 epilogue still certifies the result afterwards
+            if (ctrl->eps_stop > 0.0 && v[1] >= 0.0) {
+                const double rho = sqrt(v[1]);
+                const double C = v[2], mean = v[3] / static_cast<double>(n), Idc = v[4];
+                const double P = C - static_cast<double>(n) * mean * mean, D = Idc - C, CI = v[5];
+                const double a = (sqrt(fmax(C, 0.0)) + rho) * rho;
+                const double bdc = Idc > a ? a / (Idc - a) : INFINITY;
+                early = fmax(fmax(quad_bound(CI, rho), quad_bound(D, 0.5 * rho)),
+                             fmax(fmax(quad_bound(P, rho), quad_bound(C, rho)), bdc)) <= ctrl->eps_stop;
+            }
+        }
         if (!isfinite(v[1])) ctrl->done = BREAKDOWN;
-        else if (v[1] <= ctrl->tol2) ctrl->done = CONVERGED;
+        else if (v[1] <= ctrl->tol2 || early) ctrl->done = CONVERGED;
         else if (it >= ctrl->max_iter) ctrl->done = ITER_CAP;
     }
 }
@@ -965,7 +1029,7 @@ __global__ void __launch_bounds__(WG) k_cg_shift(int n, T* __restrict__ x, T* __
 
 __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __restrict__ part, int mode,
                                                  double rtol2, int max_iter, int range_check,
-                                                 Ctrl* __restrict__ ctrl) {
+                                                 Ctrl* __restrict__ ctrl, double eps_stop) {
     __shared__ double red[NWAVE * 5];
     __shared__ double mm[2 * NWAVE];
     double v[5];
@@ -1003,6 +1067,7 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
             ctrl->bad = 0;
         }
         ctrl->tol2 = rtol2 * ctrl->ss;
+        ctrl->eps_stop = eps_stop;
         ctrl->rz = v[0];
         ctrl->rr = v[1];
         ctrl->hist[ctrl->iters % HIST] = v[1];
