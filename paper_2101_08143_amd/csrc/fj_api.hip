@@ -811,6 +811,9 @@ struct BState {
     T *X, *R, *P, *Q;
     Ctrl* ctrl;  // KB control blocks
     double* part;
+    const double* s_est = nullptr;  // FP64 only: the opinions (stride s_lds, s_k columns) for index estimates
+    int64_t s_lds = 0;
+    int s_k = 0;
 };
 
 // The batched driver for KB columns (see fj_batched.hpp).
@@ -824,12 +827,12 @@ struct Batched {
 
     int setup() {
         const int64_t units = (static_cast<int64_t>(c.g->n) * KB + WG - 1) / WG;
-        return grid_for(k_update_batched<double, KB>, units, &grid_vec);
+        return grid_for(k_update_batched<double, KB, true>, units, &grid_vec);
     }
 
     template <typename T>
     int init(BState<T>& S, const double* src, int64_t lds, int k, int kcheck, int mode, uint64_t mask,
-             const double* rtol, int max_iter, bool range_check) {
+             const double* rtol, int max_iter, bool range_check, double eps_stop = 0.0) {
         ColumnTol tol{};
         for (int col = 0; col < KB; ++col) tol.rtol2[col] = rtol[col] * rtol[col];
         const int n = c.g->n;
@@ -841,7 +844,7 @@ struct Batched {
                                                         S.part);
         HIPCHK(hipGetLastError());
         k_fin_init_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter,
-                                                   range_check ? 1 : 0, S.ctrl, 1);
+                                                   range_check ? 1 : 0, S.ctrl, 1, eps_stop);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
@@ -872,10 +875,23 @@ struct Batched {
         if (rc) return rc;
         k_fin_spmm<KB><<<KB, WG, 0, c.st>>>(grid_win, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
-        k_update_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(c.g->n, S.X, S.R, S.P, S.Q, c.minv(), S.part, S.ctrl);
-        HIPCHK(hipGetLastError());
-        k_fin_update_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, S.part, S.ctrl);
-        HIPCHK(hipGetLastError());
+        bool est = false;
+        if constexpr (std::is_same<T, double>::value) est = S.s_est != nullptr;
+        if (est) {
+            if constexpr (std::is_same<T, double>::value) {
+                k_update_batched<T, KB, true><<<grid_vec, WG, 0, c.st>>>(c.g->n, S.X, S.R, S.P, S.Q, c.minv(), S.s_est,
+                                                                       S.s_lds, S.s_k, S.part, S.ctrl);
+                HIPCHK(hipGetLastError());
+                k_fin_update_batched<KB, true><<<KB, WG, 0, c.st>>>(grid_vec, c.g->n, S.part, S.ctrl);
+                HIPCHK(hipGetLastError());
+            }
+        } else {
+            k_update_batched<T, KB, false><<<grid_vec, WG, 0, c.st>>>(c.g->n, S.X, S.R, S.P, S.Q, c.minv(), nullptr,
+                                                                    0, 0, S.part, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_fin_update_batched<KB, false><<<KB, WG, 0, c.st>>>(grid_vec, c.g->n, S.part, S.ctrl);
+            HIPCHK(hipGetLastError());
+        }
         return FJ_OK;
     }
 
@@ -1008,7 +1024,15 @@ struct Batched {
             prev_rho[col] = INFINITY;
             if (col < k) status[col] = FJ_ERR_NOT_CONVERGED;
         }
-        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, rtol, max_iter, range_check)) return rc;
+        // default target with indices: also stop a column once the estimates of
+        // its five indices meet 0.8 eps (see k_fin_update_batched)
+        const double eps_stop = (want_indices && o.rtol == 0.0 && !(o.flags & FJ_TWO_SOLVE)) ? 0.8 * o.eps : 0.0;
+        if (eps_stop > 0.0) {
+            S.s_est = src;
+            S.s_lds = lds;
+            S.s_k = k;
+        }
+        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, rtol, max_iter, range_check, eps_stop)) return rc;
         *passes = 0;
         for (;;) {
             ++*passes;
@@ -1019,6 +1043,7 @@ struct Batched {
             const uint64_t again = triage(cs, k, o, want_indices, which, rtol, prev_rho, status, *passes >= MAX_PASSES);
             if (!again) break;
             for (int col = 0; col < k; ++col) prev_rho[col] = cs[col].res[5];
+            S.s_est = nullptr;  // a restart runs to its residual target
             if (int rc = init(S, src, lds, k, kcheck, 1, again, rtol, max_iter, range_check)) return rc;
         }
         return FJ_OK;

@@ -500,49 +500,87 @@ __global__ void __launch_bounds__(WG) k_fin_spmm(int G, const double* __restrict
 
 // Element-wise CG update of every running column; thread t always handles
 // column t % KB (the grid stride is a multiple of KB).
-template <typename T, int KB>
+// EST (FP64): also, per column, the sums that estimate the five indices at the
+// new x (see k_cg_update): x^T x, sum x, s^T x, ||s - x||^2, with s read from
+// S (column c of node i at S[i * lds + c], zero for c >= k). Only columns
+// whose residual is already within a factor 100 of their target pay for
+// the extra read (est_window); the others cannot stop early yet.
+__device__ __forceinline__ bool est_window(const Ctrl& c) { return c.eps_stop > 0.0 && c.rr <= 1e4 * c.tol2; }
+
+template <typename T, int KB, bool EST>
 __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X, T* __restrict__ R,
                                                        T* __restrict__ P, const T* __restrict__ Q,
                                                        const float* __restrict__ minv,
+                                                       const double* __restrict__ S, int64_t lds, int k,
                                                        double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    static_assert(!EST || std::is_same<T, double>::value, "estimates are for FP64 vectors");
     __shared__ double lred[12 * WG];
     const int c = threadIdx.x % KB;
     const bool run = ctrl[c].done == RUNNING;
+    const bool est = EST && est_window(ctrl[c]);
     const double alpha = ctrl[c].alpha, beta = ctrl[c].beta;
     double v[2] = {0.0, 0.0};
+    double e[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t total = static_cast<int64_t>(n) * KB;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
     if (run) {
-        for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total; e += stride) {
-            const int i = static_cast<int>(e / KB);
-            T x = X[e], r = R[e], p = P[e];
-            cg_update_elem(alpha, beta, x, r, p, Q[e], minv[i], v);
-            X[e] = x;
-            R[e] = r;
-            P[e] = p;
+        for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e0 < total; e0 += stride) {
+            const int i = static_cast<int>(e0 / KB);
+            T x = X[e0], r = R[e0], p = P[e0];
+            cg_update_elem(alpha, beta, x, r, p, Q[e0], minv[i], v);
+            X[e0] = x;
+            R[e0] = r;
+            P[e0] = p;
+            if (EST && est) {
+                const double xi = static_cast<double>(x);
+                const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
+                e[0] += xi * xi;
+                e[1] += xi;
+                e[2] += si * xi;
+                e[3] += (si - xi) * (si - xi);
+            }
         }
     }
-    const double vv[2][1] = {{v[0]}, {v[1]}};
-    store_column_partials<2, KB, 1>(vv, lred, part);
+    if constexpr (EST) {
+        const double vv[6][1] = {{v[0]}, {v[1]}, {e[0]}, {e[1]}, {e[2]}, {e[3]}};
+        store_column_partials<6, KB, 1>(vv, lred, part);
+    } else {
+        const double vv[2][1] = {{v[0]}, {v[1]}};
+        store_column_partials<2, KB, 1>(vv, lred, part);
+    }
 }
 
-template <int KB>
-__global__ void __launch_bounds__(WG) k_fin_update_batched(int G, const double* __restrict__ part,
+template <int KB, bool EST>
+__global__ void __launch_bounds__(WG) k_fin_update_batched(int G, int n, const double* __restrict__ part,
                                                            Ctrl* __restrict__ ctrl) {
     Ctrl& c = ctrl[blockIdx.x];  // one workgroup per column
     if (c.done != RUNNING) return;
-    __shared__ double red[NWAVE * 2];
-    double tot[2];
-    column_totals<2, KB>(G, part, tot, red);
+    constexpr int NV = EST ? 6 : 2;
+    __shared__ double red[NWAVE * NV];
+    double tot[NV];
+    column_totals<NV, KB>(G, part, tot, red);
     if (threadIdx.x == 0) {
+        const bool est_on = EST && est_window(c);  // decided on the residual the update saw
         const double rz = tot[0], rr = tot[1];
         const int it = c.iters + 1;
         c.iters = it;
         c.rz = rz;
         c.rr = rr;
         c.hist[it % HIST] = rr;
+        bool early = false;
+        if constexpr (EST) {  // as k_fin_update, for the columns the update summed
+            if (est_on && rr >= 0.0) {
+                const double rho = sqrt(rr);
+                const double C = tot[2], mean = tot[3] / static_cast<double>(n), Idc = tot[4];
+                const double P = C - static_cast<double>(n) * mean * mean, D = Idc - C, CI = tot[5];
+                const double a = (sqrt(fmax(C, 0.0)) + rho) * rho;
+                const double bdc = Idc > a ? a / (Idc - a) : INFINITY;
+                early = fmax(fmax(quad_bound(CI, rho), quad_bound(D, 0.5 * rho)),
+                             fmax(fmax(quad_bound(P, rho), quad_bound(C, rho)), bdc)) <= c.eps_stop;
+            }
+        }
         if (!isfinite(rr)) c.done = BREAKDOWN;
-        else if (rr <= c.tol2) c.done = CONVERGED;
+        else if (rr <= c.tol2 || early) c.done = CONVERGED;
         else if (it >= c.max_iter) c.done = ITER_CAP;
     }
 }
@@ -606,7 +644,8 @@ __global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double*
 template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, const double* __restrict__ part,
                                                          int mode, uint64_t mask, ColumnTol tol, int max_iter,
-                                                         int range_check, Ctrl* __restrict__ ctrl, int stop_others) {
+                                                         int range_check, Ctrl* __restrict__ ctrl, int stop_others,
+                                                         double eps_stop) {
     const int c = blockIdx.x;  // one workgroup per column
     Ctrl& C = ctrl[c];
     if (!((mask >> c) & 1ull)) {
@@ -653,6 +692,7 @@ __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, co
             C.bad = 0;
         }
         C.tol2 = tol.rtol2[c] * C.ss;
+        C.eps_stop = eps_stop;
         C.rz = rz;
         C.rr = rr;
         C.hist[C.iters % HIST] = rr;

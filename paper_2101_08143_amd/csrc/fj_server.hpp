@@ -166,7 +166,7 @@ struct ServerOps {
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&b->host), sizeof(Ctrl) * KB * 2, hipHostMallocDefault));
         HIPCHK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
         const int64_t units = (static_cast<int64_t>(n) * KB + WG - 1) / WG;
-        if (int rc = grid_for(k_update_batched<double, KB>, units, &b->grid_vec)) return rc;
+        if (int rc = grid_for(k_update_batched<double, KB, true>, units, &b->grid_vec)) return rc;
         // zero the vectors (kernels, not memsets), every column idle
         k_fill_zero<<<b->grid_vec, WG, 0, G.st>>>(b->X, static_cast<int64_t>(vec_bytes / sizeof(double)));
         HIPCHK(hipGetLastError());
@@ -203,8 +203,15 @@ struct ServerOps {
                     return e;
                 }
                 k_fin_spmm<KB><<<KB, WG, 0, G.st>>>(b->grid_win, b->part, cg);
-                k_update_batched<T, KB><<<b->grid_vec, WG, 0, G.st>>>(n, X, R, P, Q, minv, b->part, cg);
-                k_fin_update_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, b->part, cg);
+                if constexpr (std::is_same<T, double>::value) {  // with the index estimates of the eager path
+                    k_update_batched<T, KB, true><<<b->grid_vec, WG, 0, G.st>>>(n, X, R, P, Q, minv, b->S, KB, KB,
+                                                                               b->part, cg);
+                    k_fin_update_batched<KB, true><<<KB, WG, 0, G.st>>>(b->grid_vec, n, b->part, cg);
+                } else {
+                    k_update_batched<T, KB, false><<<b->grid_vec, WG, 0, G.st>>>(n, X, R, P, Q, minv, nullptr, 0, 0,
+                                                                                b->part, cg);
+                    k_fin_update_batched<KB, false><<<KB, WG, 0, G.st>>>(b->grid_vec, n, b->part, cg);
+                }
             }
             HIPCHK(hipStreamEndCapture(G.st, &b->graph));
             HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -260,8 +267,9 @@ struct ServerOps {
             k_init_batched<double, KB><<<b->grid_vec, WG, 0, G.st>>>(n, KB, b->S, KB, b->X, b->R, b->P, minv, mode,
                                                                     mask, KB, b->part);
             HIPCHK(hipGetLastError());
+            // the first pass may stop on the index estimates, as the eager path does
             k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, mode, mask, tol, max_iter, 1,
-                                                        b->ctrl, 0);
+                                                        b->ctrl, 0, mode == 0 ? 0.8 * s.o.eps : 0.0);
             HIPCHK(hipGetLastError());
             b->running |= mask;
             return FJ_OK;
@@ -272,7 +280,7 @@ struct ServerOps {
                                                                     mask, KB, b->part);
             HIPCHK(hipGetLastError());
             k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, 0, mask, tol, max_iter, 1, b->ctrl,
-                                                        0);
+                                                        0, 0.0);
             HIPCHK(hipGetLastError());
             k_ctrl_rho_from_s<<<1, WG, 0, G.st>>>(b->ctrl, KB, mask);
             HIPCHK(hipGetLastError());
@@ -284,7 +292,7 @@ struct ServerOps {
                                                                mask, 0, b->part);
         HIPCHK(hipGetLastError());
         k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, 2, mask, tol, max_iter, 0, b->ictrl,
-                                                    0);
+                                                    0, 0.0);
         HIPCHK(hipGetLastError());
         b->running |= mask;
         return FJ_OK;
