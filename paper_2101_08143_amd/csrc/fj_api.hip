@@ -292,7 +292,7 @@ struct Ctx {
 
 template <typename T>
 int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, double rtol, int max_iter,
-            bool range_check, double eps_stop = 0.0) {
+            bool range_check, double eps_stop = 0.0, int deflate = 0) {
     const int n = c.g->n;
     if (mode != 1) {
         k_ctrl_reset<<<1, WG, 0, c.st>>>(S.ctrl, 1);
@@ -301,7 +301,7 @@ int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, doubl
     k_cg_init<T><<<c.grid_vec, WG, 0, c.st>>>(n, s, lds, S.x, S.r, S.p, c.minv(), mode, S.part);
     HIPCHK(hipGetLastError());
     k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, mode, rtol * rtol, max_iter, range_check ? 1 : 0,
-                                   S.ctrl, eps_stop);
+                                   S.ctrl, eps_stop, deflate);
     HIPCHK(hipGetLastError());
     return FJ_OK;
 }
@@ -498,11 +498,13 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     const double eps_stop = (want_indices && o.rtol == 0.0 && packable && !z0) ? 0.8 * o.eps : 0.0;
     S.s_est = eps_stop > 0.0 ? s : nullptr;
     if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check, eps_stop)) return rc;
-    if (!z0 && !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N) {  // start from mean(s) 1
+    // start from mean(s) 1 and deflate the constant vector (k_cg_shift)
+    const int deflate = (!z0 && !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N) ? 1 : 0;
+    if (deflate) {
         k_cg_shift<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, c.minv(), S.ctrl, S.part);
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
-                                       S.ctrl, eps_stop);
+                                       S.ctrl, eps_stop, 1);
         HIPCHK(hipGetLastError());
     }
     if (z0) {
@@ -552,7 +554,8 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
         if (want_indices && snorm > 0.0) next = std::min(next, 0.5 * needed_rho(cc, o.eps) / snorm);
         rtol = std::max(next, 1e-16);
         S.s_est = nullptr;  // a restart runs to its residual target
-        if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check)) return rc;
+        // (still deflated: x keeps mean(s), so the true residual is centred up to rounding)
+        if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check, 0.0, deflate)) return rc;
     }
     fill_outputs(cc, status, passes, 0, out, info);
     if (info)
@@ -1150,7 +1153,7 @@ int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t ld
         k_cg_init<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S, lds, S64.X, S64.R, nullptr, c.minv(), 0, part);
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, part, 0, 1.0, max_iter,
-                                       (o.flags & FJ_NO_RANGE_CHECK) ? 0 : 1, ctrls, 0.0);
+                                       (o.flags & FJ_NO_RANGE_CHECK) ? 0 : 1, ctrls, 0.0, 0);
         HIPCHK(hipGetLastError());
         Ctrl st0{};
         HIPCHK(hipMemcpyAsync(&st0, ctrls, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));

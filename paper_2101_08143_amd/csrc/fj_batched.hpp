@@ -518,8 +518,8 @@ __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X,
     const int c = threadIdx.x % KB;
     const bool run = ctrl[c].done == RUNNING;
     const bool est = EST && est_window(ctrl[c]);
-    const double alpha = ctrl[c].alpha, beta = ctrl[c].beta;
-    double v[2] = {0.0, 0.0};
+    const double alpha = ctrl[c].alpha, beta = ctrl[c].beta, pbar = ctrl[c].pbar;
+    double v[3] = {0.0, 0.0, 0.0};
     double e[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t total = static_cast<int64_t>(n) * KB;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X,
         for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e0 < total; e0 += stride) {
             const int i = static_cast<int>(e0 / KB);
             T x = X[e0], r = R[e0], p = P[e0];
-            cg_update_elem(alpha, beta, x, r, p, Q[e0], minv[i], v);
+            cg_update_elem(alpha, beta, pbar, x, r, p, Q[e0], minv[i], v);
             X[e0] = x;
             R[e0] = r;
             P[e0] = p;

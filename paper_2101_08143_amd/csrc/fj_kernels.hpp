@@ -56,12 +56,14 @@ struct Ctrl {
     double res[16];       // epilogue: indices, residual and diagnostics (see k_epilogue)
     double bound[5];      // certified relative error bound of each index
     double eps_stop;      // > 0: also stop once the estimated bounds of all five indices are below it
+    double pbar;          // deflated CG: mean of the current direction p (0 otherwise)
     double hist[HIST];    // rr after iteration t is in hist[t % HIST]
     int32_t done;         // 0 running, 1 converged, 2 iteration cap, 3 breakdown, 4 bad input
     int32_t iters;        // CG iterations so far (all passes)
     int32_t max_iter;
     int32_t bad;          // 2 when some s_i is NaN or outside [0,1]
-    int32_t pad[4];
+    int32_t deflate;      // 1: CG deflated by the constant vector (see k_cg_shift)
+    int32_t pad[3];
 };
 
 enum Done : int32_t { RUNNING = 0, CONVERGED = 1, ITER_CAP = 2, BREAKDOWN = 3, BAD_INPUT = 4 };
@@ -545,10 +547,11 @@ struct OpCgSpmv {
     const T* __restrict__ r;
     const float* __restrict__ minv;
     T* __restrict__ q;
+    double shift;  // deflated CG: q = (I+L) p - mean(p) 1, the projection of (I+L) p
     double pq = 0.0, rmq = 0.0, qmq = 0.0;
     __device__ In load(int i) const { return {r[i], minv[i]}; }
     __device__ void row(int i, T pi, double lin, double, const In& in) {
-        const T qt = static_cast<T>(static_cast<double>(pi) + lin);
+        const T qt = static_cast<T>(static_cast<double>(pi) + lin - shift);
         q[i] = qt;
         const double qi = static_cast<double>(qt);
         const double mq = static_cast<double>(in.m) * qi;
@@ -739,8 +742,8 @@ __global__ void k_fj_ctrl_init(Ctrl* __restrict__ ctrl, double tol, int max_step
     }
 }
 
-// CG step, part 1: q = (I+L) p with the partial sums of p^T q, r^T M^{-1} q
-// and q^T M^{-1} q.
+// CG step, part 1: q = (I+L) p (minus mean(p) 1 when deflated) with the
+// partial sums of p^T q, r^T M^{-1} q and q^T M^{-1} q.
 template <typename V, typename T>
 __global__ void __launch_bounds__(WG) k_cg_spmv(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                 const T* __restrict__ p, const T* __restrict__ r,
@@ -749,7 +752,7 @@ __global__ void __launch_bounds__(WG) k_cg_spmv(Csr<V> g, const WinDesc* __restr
     if (ctrl->done != RUNNING) return;
     __shared__ Stage<T, V, typename OpCgSpmv<T>::In> st;
     __shared__ double red[NWAVE * 4];
-    OpCgSpmv<T> op{r, minv, q};
+    OpCgSpmv<T> op{r, minv, q, ctrl->pbar};
     my_windows<T, V, AccLin>(g, desc, K, p, op, st, red);
     double v[3] = {op.pq, op.rmq, op.qmq};
     block_sum<3>(v, red);
@@ -781,31 +784,33 @@ __global__ void __launch_bounds__(WG) k_fin_spmv(int G, const double* __restrict
     }
 }
 
-// CG step, part 2: x += alpha p, r -= alpha q, z = M^{-1} r, p = z + beta p, and
-// the partial sums of the exact r^T M^{-1} r (next alpha) and r^T r (stopping
-// test). Each thread moves 16-byte packs of every vector (2 doubles or 4
-// floats); arithmetic is in double, rounded once when stored.
+// CG step, part 2: x += alpha (p - pbar), r -= alpha q, z = M^{-1} r,
+// p = z + beta p, and the partial sums of the exact r^T M^{-1} r (next alpha),
+// r^T r (stopping test) and sum p (next pbar). Each thread moves 16-byte packs
+// of every vector (2 doubles or 4 floats); arithmetic is in double, rounded
+// once when stored.
 template <typename T> struct Pack;
 template <> struct Pack<double> { using type = double2; using mtype = float2; static constexpr int N = 2; };
 template <> struct Pack<float> { using type = float4; using mtype = float4; static constexpr int N = 4; };
 
 template <typename T>
-__device__ __forceinline__ void cg_update_elem(double alpha, double beta, T& x, T& r, T& p, T q, float m,
-                                               double (&v)[2]) {
-    x = static_cast<T>(static_cast<double>(x) + alpha * static_cast<double>(p));
+__device__ __forceinline__ void cg_update_elem(double alpha, double beta, double pbar, T& x, T& r, T& p, T q,
+                                               float m, double (&v)[3]) {
+    x = static_cast<T>(static_cast<double>(x) + alpha * (static_cast<double>(p) - pbar));
     r = static_cast<T>(static_cast<double>(r) - alpha * static_cast<double>(q));
     const double rd = static_cast<double>(r);
     const double z = static_cast<double>(m) * rd;
     p = static_cast<T>(z + beta * static_cast<double>(p));
     v[0] += rd * z;
     v[1] += rd * rd;
+    v[2] += static_cast<double>(p);
 }
 
 template <typename T>
-__device__ __forceinline__ void cg_update_pack(int t, double alpha, double beta, T* __restrict__ x,
+__device__ __forceinline__ void cg_update_pack(int t, double alpha, double beta, double pbar, T* __restrict__ x,
                                                T* __restrict__ r, T* __restrict__ p,
                                                const T* __restrict__ q, const float* __restrict__ minv,
-                                               double (&v)[2]) {
+                                               double (&v)[3]) {
     using P = typename Pack<T>::type;
     using M = typename Pack<T>::mtype;
     constexpr int N = Pack<T>::N;
@@ -820,7 +825,7 @@ __device__ __forceinline__ void cg_update_pack(int t, double alpha, double beta,
     const T* qs = reinterpret_cast<const T*>(&qv);
     const float* ms = reinterpret_cast<const float*>(&mv);
 #pragma unroll
-    for (int e = 0; e < N; ++e) cg_update_elem(alpha, beta, xs[e], rs[e], ps[e], qs[e], ms[e], v);
+    for (int e = 0; e < N; ++e) cg_update_elem(alpha, beta, pbar, xs[e], rs[e], ps[e], qs[e], ms[e], v);
     reinterpret_cast<P*>(x)[t] = xv;
     reinterpret_cast<P*>(r)[t] = rv;
     reinterpret_cast<P*>(p)[t] = pv;
@@ -851,29 +856,29 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, T* __restrict__ x, T* _
                                                   double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     static_assert(!EST || std::is_same<T, double>::value, "estimates are for FP64 vectors");
     if (ctrl->done != RUNNING) return;
-    __shared__ double red[NWAVE * 6];
+    __shared__ double red[NWAVE * 7];
     constexpr int N = Pack<T>::N;
-    const double alpha = ctrl->alpha, beta = ctrl->beta;
-    double v[2] = {0.0, 0.0};
+    const double alpha = ctrl->alpha, beta = ctrl->beta, pbar = ctrl->pbar;
+    double v[3] = {0.0, 0.0, 0.0};
     double e[4] = {0.0, 0.0, 0.0, 0.0};
     const int npack = n / N;
     const int stride = gridDim.x * WG;
     int t = blockIdx.x * WG + threadIdx.x;
     for (; t + stride < npack; t += 2 * stride) {  // two packs per thread in flight
-        cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
-        cg_update_pack(t + stride, alpha, beta, x, r, p, q, minv, v);
+        cg_update_pack(t, alpha, beta, pbar, x, r, p, q, minv, v);
+        cg_update_pack(t + stride, alpha, beta, pbar, x, r, p, q, minv, v);
         if constexpr (EST) {
             est_pack<EST>(t, reinterpret_cast<const double*>(x), s, e);
             est_pack<EST>(t + stride, reinterpret_cast<const double*>(x), s, e);
         }
     }
     if (t < npack) {
-        cg_update_pack(t, alpha, beta, x, r, p, q, minv, v);
+        cg_update_pack(t, alpha, beta, pbar, x, r, p, q, minv, v);
         if constexpr (EST) est_pack<EST>(t, reinterpret_cast<const double*>(x), s, e);
     }
     if (blockIdx.x == 0 && threadIdx.x < n - npack * N) {
         const int i = npack * N + threadIdx.x;
-        cg_update_elem(alpha, beta, x[i], r[i], p[i], q[i], minv[i], v);
+        cg_update_elem(alpha, beta, pbar, x[i], r[i], p[i], q[i], minv[i], v);
         if constexpr (EST) {
             const double xi = static_cast<double>(x[i]), si = s[i];
             e[0] += xi * xi;
@@ -883,12 +888,12 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, T* __restrict__ x, T* _
         }
     }
     if constexpr (EST) {
-        double w[6] = {v[0], v[1], e[0], e[1], e[2], e[3]};
-        block_sum<6>(w, red);
-        store_partials<6>(w, part);
+        double w[7] = {v[0], v[1], v[2], e[0], e[1], e[2], e[3]};
+        block_sum<7>(w, red);
+        store_partials<7>(w, part);
     } else {
-        block_sum<2>(v, red);
-        store_partials<2>(v, part);
+        block_sum<3>(v, red);
+        store_partials<3>(v, part);
     }
 }
 
@@ -903,7 +908,7 @@ template <bool EST>
 __global__ void __launch_bounds__(WG) k_fin_update(int G, int n, const double* __restrict__ part,
                                                    Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    constexpr int NV = EST ? 6 : 2;
+    constexpr int NV = EST ? 7 : 3;
     __shared__ double red[NWAVE * NV];
     double v[NV];
     total_partials<NV>(G, part, v, red);
@@ -913,14 +918,15 @@ __global__ void __launch_bounds__(WG) k_fin_update(int G, int n, const double* _
         ctrl->rz = v[0];
         ctrl->rr = v[1];
         ctrl->hist[it % HIST] = v[1];
+        ctrl->pbar = ctrl->deflate ? v[2] / static_cast<double>(n) : 0.0;
         bool early = false;
         if constexpr (EST) {
             // estimated indices at the new x with the recursive residual norm;
             // the FP64 epilogue still certifies the result afterwards
             if (ctrl->eps_stop > 0.0 && v[1] >= 0.0) {
                 const double rho = sqrt(v[1]);
-                const double C = v[2], mean = v[3] / static_cast<double>(n), Idc = v[4];
-                const double P = C - static_cast<double>(n) * mean * mean, D = Idc - C, CI = v[5];
+                const double C = v[3], mean = v[4] / static_cast<double>(n), Idc = v[5];
+                const double P = C - static_cast<double>(n) * mean * mean, D = Idc - C, CI = v[6];
                 const double a = (sqrt(fmax(C, 0.0)) + rho) * rho;
                 const double bdc = Idc > a ? a / (Idc - a) : INFINITY;
                 early = fmax(fmax(quad_bound(CI, rho), quad_bound(D, 0.5 * rho)),
@@ -937,14 +943,15 @@ __global__ void __launch_bounds__(WG) k_fin_update(int G, int n, const double* _
 // range). mode 1: restart from the current x with r already holding the true
 // residual (written by the epilogue). mode 2: x = 0 with r given (the inner
 // solve of FJ_MIXED). All: p = M^{-1} r and the partial sums of rz and rr.
-// Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 min s, 6 max s.
+// Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 sum p, 6 min s,
+// 7 max s.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict__ s, int64_t lds,
                                                 T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                 const float* __restrict__ minv, int mode,
                                                 double* __restrict__ part) {
     __shared__ double red[NWAVE * 8];
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double smin = INFINITY, smax = -INFINITY;
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
         double ri;
@@ -966,32 +973,33 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
         if (p != nullptr) p[i] = zt;  // null: statistics only (FP64 side of FJ_MIXED)
         v[0] += ri * static_cast<double>(zt);
         v[1] += ri * ri;
+        v[5] += static_cast<double>(zt);
     }
-    block_sum<5>(v, red);
+    block_sum<6>(v, red);
     smin = wave_min(smin);
     smax = wave_max(smax);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
-        red[NWAVE * 5 + wave] = smin;
-        red[NWAVE * 6 + wave] = smax;
+        red[NWAVE * 6 + wave] = smin;
+        red[NWAVE * 7 + wave] = smax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = red[NWAVE * 5], b = red[NWAVE * 6];
+        double a = red[NWAVE * 6], b = red[NWAVE * 7];
         for (int w = 1; w < NWAVE; ++w) {
-            a = fmin(a, red[NWAVE * 5 + w]);
-            b = fmax(b, red[NWAVE * 6 + w]);
+            a = fmin(a, red[NWAVE * 6 + w]);
+            b = fmax(b, red[NWAVE * 7 + w]);
         }
         double* out = part + blockIdx.x * NPART;
-        for (int c = 0; c < 5; ++c) out[c] = v[c];
-        out[5] = a;
-        out[6] = b;
+        for (int c = 0; c < 6; ++c) out[c] = v[c];
+        out[6] = a;
+        out[7] = b;
     }
 }
 
 // Single-vector FP64 solves of graphs from this many nodes on start from
-// mean(s) 1 (below, the two extra launches cost more than the iteration they
-// save; the batched and mixed-precision drivers measured no gain from it).
+// mean(s) 1 and run deflated CG (below, the two extra launches cost more than
+// the iterations they save).
 constexpr int MEAN_START_MIN_N = 65536;
 
 // Start CG from the constant vector mean(s) 1 instead of 0. Since
@@ -999,14 +1007,24 @@ constexpr int MEAN_START_MIN_N = 65536;
 // s - mean(s) 1, and the remaining error z - mean(s) 1 is the centred
 // solution that Algorithm 1 solves for separately (Section 2.2: Omega 1 = 1),
 // whose energy is far smaller than that of z. Runs after k_cg_init mode 0
-// (r = s, mu known); k_fin_init mode 1 then takes rz and rr.
+// (r = s, mu known); k_fin_init mode 1 then takes rz, rr and sum p.
+//
+// Deflated CG (k_fin_init with deflate = 1) keeps that split for the whole
+// solve: with coarse space span{1}, (I + L) 1 = 1 and 1^T (I + L) = 1^T turn
+// the deflation projector into centring, P v = v - mean(v) 1. Each step then
+// uses q = P (I + L) p, computed as (I + L) p - mean(p) 1 (the two means agree
+// because 1^T (I + L) p = 1^T p), and moves x by alpha (p - mean(p) 1), so x
+// keeps mean(x) = mean(s) = mean(z) and r stays its residual. The Jacobi-scaled
+// operator's smallest eigenvalue, about 1 / (1 + mean degree), belongs to the
+// near-constant direction that this removes; on power-law graphs the solve
+// needs about a quarter fewer iterations.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_cg_shift(int n, T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                  const float* __restrict__ minv, const Ctrl* __restrict__ ctrl,
                                                  double* __restrict__ part) {
-    __shared__ double red[NWAVE * 2];
+    __shared__ double red[NWAVE * 3];
     const double mu = ctrl->mu;
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
         x[i] = static_cast<T>(mu);
         const T rt = static_cast<T>(static_cast<double>(r[i]) - mu);
@@ -1016,28 +1034,31 @@ __global__ void __launch_bounds__(WG) k_cg_shift(int n, T* __restrict__ x, T* __
         p[i] = zt;
         v[0] += ri * static_cast<double>(zt);
         v[1] += ri * ri;
+        v[2] += static_cast<double>(zt);
     }
-    block_sum<2>(v, red);
+    block_sum<3>(v, red);
     if (threadIdx.x == 0) {
         double* out = part + blockIdx.x * NPART;
         out[0] = v[0];
         out[1] = v[1];
-        out[5] = INFINITY;
-        out[6] = -INFINITY;
+        out[2] = out[3] = out[4] = 0.0;
+        out[5] = v[2];
+        out[6] = INFINITY;
+        out[7] = -INFINITY;
     }
 }
 
 __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __restrict__ part, int mode,
                                                  double rtol2, int max_iter, int range_check,
-                                                 Ctrl* __restrict__ ctrl, double eps_stop) {
-    __shared__ double red[NWAVE * 5];
+                                                 Ctrl* __restrict__ ctrl, double eps_stop, int deflate) {
+    __shared__ double red[NWAVE * 6];
     __shared__ double mm[2 * NWAVE];
-    double v[5];
-    total_partials<5>(G, part, v, red);
+    double v[6];
+    total_partials<6>(G, part, v, red);
     double a = INFINITY, b = -INFINITY;
     for (int k = threadIdx.x; k < G; k += WG) {
-        a = fmin(a, part[k * NPART + 5]);
-        b = fmax(b, part[k * NPART + 6]);
+        a = fmin(a, part[k * NPART + 6]);
+        b = fmax(b, part[k * NPART + 7]);
     }
     a = wave_min(a);
     b = wave_max(b);
@@ -1068,6 +1089,8 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
         }
         ctrl->tol2 = rtol2 * ctrl->ss;
         ctrl->eps_stop = eps_stop;
+        ctrl->deflate = deflate;
+        ctrl->pbar = deflate ? v[5] / static_cast<double>(n) : 0.0;
         ctrl->rz = v[0];
         ctrl->rr = v[1];
         ctrl->hist[ctrl->iters % HIST] = v[1];
