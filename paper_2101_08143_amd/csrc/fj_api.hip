@@ -585,6 +585,7 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
     const double snorm = std::sqrt(cc.ss);
     double rho = snorm;
     double tau = 1e-4;
+    const bool deflate = !(o.flags & FJ_ZERO_START) && n >= MEAN_START_MIN_N;
     int inner_total = 0, outer = 0, status = FJ_ERR_NOT_CONVERGED;
     if (z0) {  // start the refinement from z0 and its true residual
         if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
@@ -603,6 +604,13 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
         k_mixed_cast<<<c.grid_vec, WG, 0, c.st>>>(n, S.r, I.r, mode, S.ctrl);
         HIPCHK(hipGetLastError());
         if (int rc = cg_init(c, I, nullptr, 0, 2, tau, max_iter - inner_total, false)) return rc;
+        if (deflate) {  // inner CG from mean(r32) 1, deflated (see k_cg_shift)
+            k_cg_shift<float><<<c.grid_vec, WG, 0, c.st>>>(n, I.x, I.r, I.p, c.minv(), I.ctrl, I.part);
+            HIPCHK(hipGetLastError());
+            k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, n, I.part, 1, tau * tau, max_iter - inner_total, 0, I.ctrl,
+                                           0.0, 1);
+            HIPCHK(hipGetLastError());
+        }
         if (int rc = cg_run(c, I, 0, max_iter - inner_total, &ci)) return rc;
         inner_total += ci.iters;
         if (ci.done == BREAKDOWN) {

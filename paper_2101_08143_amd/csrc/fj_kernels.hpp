@@ -942,7 +942,8 @@ __global__ void __launch_bounds__(WG) k_fin_update(int G, int n, const double* _
 // CG start. mode 0: x = 0, r = s, plus the statistics of s (mean, ||s||^2,
 // range). mode 1: restart from the current x with r already holding the true
 // residual (written by the epilogue). mode 2: x = 0 with r given (the inner
-// solve of FJ_MIXED). All: p = M^{-1} r and the partial sums of rz and rr.
+// solve of FJ_MIXED; mu becomes mean(r)). All: p = M^{-1} r and the partial
+// sums of rz and rr.
 // Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 sum p, 6 min s,
 // 7 max s.
 template <typename T>
@@ -968,6 +969,7 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
         } else {
             if (mode == 2) x[i] = T(0);
             ri = static_cast<double>(r[i]);
+            v[3] += ri;
         }
         const T zt = static_cast<T>(static_cast<double>(minv[i]) * ri);
         if (p != nullptr) p[i] = zt;  // null: statistics only (FP64 side of FJ_MIXED)
@@ -1083,6 +1085,7 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
         }
         if (mode == 2) {  // the inner solve of FJ_MIXED: tolerance relative to its own right-hand side
             ctrl->ss = v[1];
+            ctrl->mu = v[3] / static_cast<double>(n);
             ctrl->iters = 0;
             ctrl->max_iter = max_iter;
             ctrl->bad = 0;
