@@ -738,25 +738,25 @@ struct Spmm {
     }
     template <int CPL>
     static int go(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
-                  const T* P, const T* R, const float* minv, T* Q, double* part) {
-        if (ch.split) k_spmm_cg<Vc, T, KB, CPL, true><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
-        else k_spmm_cg<Vc, T, KB, CPL, false><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part);
+                  const T* P, const T* R, const float* minv, T* Q, double* part, const Ctrl* ctrl) {
+        if (ch.split) k_spmm_cg<Vc, T, KB, CPL, true><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part, ctrl);
+        else k_spmm_cg<Vc, T, KB, CPL, false><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part, ctrl);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
     static int launch(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
-                      const T* P, const T* R, const float* minv, T* Q, double* part) {
+                      const T* P, const T* R, const float* minv, T* Q, double* part, const Ctrl* ctrl) {
         if constexpr (KB % 4 == 0)
-            if (ch.cpl == 4) return go<4>(ch, st, G, desc, K, P, R, minv, Q, part);
+            if (ch.cpl == 4) return go<4>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
         if constexpr (KB % 2 == 0)
-            if (ch.cpl == 2) return go<2>(ch, st, G, desc, K, P, R, minv, Q, part);
-        return go<1>(ch, st, G, desc, K, P, R, minv, Q, part);
+            if (ch.cpl == 2) return go<2>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
+        return go<1>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
     }
     // The launch shape for this graph: cached, or tuned now on the caller's
     // vectors (Q and part are overwritten; the next SpMM recomputes them).
     static int choose(const fj_csr* g, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
-                      const T* P, const T* R, const float* minv, T* Q, double* part, bool tune,
-                      SpmmChoice* out) {
+                      const T* P, const T* R, const float* minv, T* Q, double* part, const Ctrl* ctrl,
+                      bool tune, SpmmChoice* out) {
         if (!tune) {
             out->cpl = 1;
             out->split = true;
@@ -791,9 +791,9 @@ struct Spmm {
         SpmmChoice pick = cand.front();
         int rc = FJ_OK;
         for (const SpmmChoice& ch : cand) {
-            if ((rc = launch(ch, st, G, desc, K, P, R, minv, Q, part))) break;  // warm-up
+            if ((rc = launch(ch, st, G, desc, K, P, R, minv, Q, part, ctrl))) break;  // warm-up
             if (hipEventRecord(e0, st) != hipSuccess) { rc = FJ_ERR_HIP; break; }
-            for (int r = 0; r < REPS && rc == FJ_OK; ++r) rc = launch(ch, st, G, desc, K, P, R, minv, Q, part);
+            for (int r = 0; r < REPS && rc == FJ_OK; ++r) rc = launch(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
             if (rc) break;
             float ms = 0.f;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -841,9 +841,11 @@ struct Batched {
         return grid_for(k_update_batched<double, KB, true>, units, &grid_vec);
     }
 
+    // deflate: start modes 0 and 2 from the column means and run deflated CG
+    // (k_init_batched mode 3); a restart (mode 1) keeps it on.
     template <typename T>
     int init(BState<T>& S, const double* src, int64_t lds, int k, int kcheck, int mode, uint64_t mask,
-             const double* rtol, int max_iter, bool range_check, double eps_stop = 0.0) {
+             const double* rtol, int max_iter, bool range_check, double eps_stop = 0.0, bool deflate = false) {
         ColumnTol tol{};
         for (int col = 0; col < KB; ++col) tol.rtol2[col] = rtol[col] * rtol[col];
         const int n = c.g->n;
@@ -851,12 +853,21 @@ struct Batched {
             k_ctrl_reset<<<1, WG, 0, c.st>>>(S.ctrl, KB);
             HIPCHK(hipGetLastError());
         }
+        const int rc_flag = range_check ? 1 : 0;
         k_init_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(n, k, src, lds, S.X, S.R, S.P, c.minv(), mode, mask, kcheck,
-                                                        S.part);
+                                                        S.part, S.ctrl);
         HIPCHK(hipGetLastError());
-        k_fin_init_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter,
-                                                   range_check ? 1 : 0, S.ctrl, 1, eps_stop);
+        k_fin_init_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, n, k, S.part, mode, mask, tol, max_iter, rc_flag,
+                                                   S.ctrl, 1, eps_stop, (deflate && mode == 1) ? 1 : 0);
         HIPCHK(hipGetLastError());
+        if (deflate && mode != 1) {
+            k_init_batched<T, KB><<<grid_vec, WG, 0, c.st>>>(n, k, nullptr, 0, S.X, S.R, S.P, c.minv(), 3, mask, 0,
+                                                            S.part, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_fin_init_batched<KB><<<KB, WG, 0, c.st>>>(grid_vec, n, k, S.part, 3, mask, tol, max_iter, rc_flag,
+                                                       S.ctrl, 1, eps_stop, 1);
+            HIPCHK(hipGetLastError());
+        }
         return FJ_OK;
     }
 
@@ -868,14 +879,15 @@ struct Batched {
             SpmmChoice& ch = sizeof(T) == sizeof(double) ? ch64 : ch32;
             if (ch.grid == 0)
                 if (int e = Spmm<Vc, T, KB>::choose(c.g, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part,
-                                                    tune, &ch))
+                                                    S.ctrl, tune, &ch))
                     return e;
             grid_win = ch.grid;
             if (c.profile) {
                 if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
                 HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
             }
-            if (int e = Spmm<Vc, T, KB>::launch(ch, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part))
+            if (int e = Spmm<Vc, T, KB>::launch(ch, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part,
+                                                S.ctrl))
                 return e;
             if (c.profile) {
                 HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
@@ -1023,6 +1035,7 @@ struct Batched {
     }
 
     static double rtol_target(const fj_opts& o) { return o.rtol > 0.0 ? o.rtol : o.eps * 1e-2; }
+    bool deflate_ok(const fj_opts& o) const { return !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N; }
 
     // FP64 for every column.
     int solve_fp64(BState<double>& S, const double* src, int64_t lds, int k, int kcheck, const fj_opts& o,
@@ -1043,7 +1056,8 @@ struct Batched {
             S.s_lds = lds;
             S.s_k = k;
         }
-        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, rtol, max_iter, range_check, eps_stop)) return rc;
+        const bool deflate = deflate_ok(o);
+        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, rtol, max_iter, range_check, eps_stop, deflate)) return rc;
         *passes = 0;
         for (;;) {
             ++*passes;
@@ -1055,7 +1069,7 @@ struct Batched {
             if (!again) break;
             for (int col = 0; col < k; ++col) prev_rho[col] = cs[col].res[5];
             S.s_est = nullptr;  // a restart runs to its residual target
-            if (int rc = init(S, src, lds, k, kcheck, 1, again, rtol, max_iter, range_check)) return rc;
+            if (int rc = init(S, src, lds, k, kcheck, 1, again, rtol, max_iter, range_check, 0.0, deflate)) return rc;
         }
         return FJ_OK;
     }
@@ -1093,7 +1107,8 @@ struct Batched {
             const int mode = *outer == 1 ? 0 : 1;
             k_mixed_cast_batched<KB><<<grid_vec, WG, 0, c.st>>>(n, S.R, I.R, mode, active, S.ctrl, 1);
             HIPCHK(hipGetLastError());
-            if (int rc = init(I, nullptr, 0, k, 0, 2, active, tau, max_iter - inner_total, false)) return rc;
+            if (int rc = init(I, nullptr, 0, k, 0, 2, active, tau, max_iter - inner_total, false, 0.0, deflate_ok(o)))
+                return rc;
             if (int rc = run(I, k, ci)) return rc;
             int most = 0;
             for (int col = 0; col < k; ++col) most = std::max(most, ci[col].iters);

@@ -413,10 +413,11 @@ struct OpSpmmCg {  // Q = (I + L) P and per-column p^T q, r^T M^{-1} q, q^T M^{-
     const T* __restrict__ R;
     const float* __restrict__ minv;
     T* __restrict__ Q;
+    double shift[CPL] = {};  // deflated columns: mean of P's column (see k_cg_shift)
     double v[3][CPL] = {};
     __device__ void row(int i, int q, int c, double pi, double lin, double) {
         const int64_t at = static_cast<int64_t>(i) * KB + c;
-        const T qt = static_cast<T>(pi + lin);
+        const T qt = static_cast<T>(pi + lin - shift[q]);
         Q[at] = qt;
         const double qd = static_cast<double>(qt);
         const double mq = static_cast<double>(minv[i]) * qd;
@@ -461,8 +462,10 @@ template <typename V, typename T, int KB, int CPL, bool SPLIT>
 __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                 const T* __restrict__ P, const T* __restrict__ R,
                                                 const float* __restrict__ minv, T* __restrict__ Q,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     OpSpmmCg<T, KB, CPL> op{R, minv, Q};
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) op.shift[q] = ctrl[(threadIdx.x % (KB / CPL)) * CPL + q].pbar;
     if constexpr (SPLIT) {
         __shared__ SpmmStage<V, KB, CPL> st;
         static_assert(sizeof(st) >= 3 * WG * CPL * sizeof(double), "stage too small to reuse for the partials");
@@ -542,11 +545,11 @@ __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X,
         }
     }
     if constexpr (EST) {
-        const double vv[6][1] = {{v[0]}, {v[1]}, {e[0]}, {e[1]}, {e[2]}, {e[3]}};
-        store_column_partials<6, KB, 1>(vv, lred, part);
+        const double vv[7][1] = {{v[0]}, {v[1]}, {v[2]}, {e[0]}, {e[1]}, {e[2]}, {e[3]}};
+        store_column_partials<7, KB, 1>(vv, lred, part);
     } else {
-        const double vv[2][1] = {{v[0]}, {v[1]}};
-        store_column_partials<2, KB, 1>(vv, lred, part);
+        const double vv[3][1] = {{v[0]}, {v[1]}, {v[2]}};
+        store_column_partials<3, KB, 1>(vv, lred, part);
     }
 }
 
@@ -555,7 +558,7 @@ __global__ void __launch_bounds__(WG) k_fin_update_batched(int G, int n, const d
                                                            Ctrl* __restrict__ ctrl) {
     Ctrl& c = ctrl[blockIdx.x];  // one workgroup per column
     if (c.done != RUNNING) return;
-    constexpr int NV = EST ? 6 : 2;
+    constexpr int NV = EST ? 7 : 3;
     __shared__ double red[NWAVE * NV];
     double tot[NV];
     column_totals<NV, KB>(G, part, tot, red);
@@ -567,12 +570,13 @@ __global__ void __launch_bounds__(WG) k_fin_update_batched(int G, int n, const d
         c.rz = rz;
         c.rr = rr;
         c.hist[it % HIST] = rr;
+        c.pbar = c.deflate ? tot[2] / static_cast<double>(n) : 0.0;
         bool early = false;
         if constexpr (EST) {  // as k_fin_update, for the columns the update summed
             if (est_on && rr >= 0.0) {
                 const double rho = sqrt(rr);
-                const double C = tot[2], mean = tot[3] / static_cast<double>(n), Idc = tot[4];
-                const double P = C - static_cast<double>(n) * mean * mean, D = Idc - C, CI = tot[5];
+                const double C = tot[3], mean = tot[4] / static_cast<double>(n), Idc = tot[5];
+                const double P = C - static_cast<double>(n) * mean * mean, D = Idc - C, CI = tot[6];
                 const double a = (sqrt(fmax(C, 0.0)) + rho) * rho;
                 const double bdc = Idc > a ? a / (Idc - a) : INFINITY;
                 early = fmax(fmax(quad_bound(CI, rho), quad_bound(D, 0.5 * rho)),
@@ -587,18 +591,22 @@ __global__ void __launch_bounds__(WG) k_fin_update_batched(int G, int n, const d
 
 // Batched CG start. mode 0: X = 0, R = S (zero in padding columns) and the
 // statistics of each column of S; mode 1: restart from the current X with R
-// holding the true residual; mode 2: X = 0, R given. Only columns in `mask`
-// are touched. Partial slots per column: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad
-// count (columns < kcheck only), 5 max of -s, 6 max of s.
+// holding the true residual; mode 2: X = 0, R given (the column means become
+// mu); mode 3, after mode 0 or 2: X = mu 1, R -= mu 1, the start of deflated
+// CG (see k_cg_shift). Only columns in `mask` are touched. Partial slots per
+// column: 0 rz, 1 rr, 2 ss, 3 sum s (sum r in modes 1-3), 4 bad count
+// (columns < kcheck only), 5 sum p, 6 max of -s, 7 max of s.
 template <typename T, int KB>
 __global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double* __restrict__ S, int64_t lds,
                                                      T* __restrict__ X, T* __restrict__ R, T* __restrict__ P,
                                                      const float* __restrict__ minv, int mode, uint64_t mask,
-                                                     int kcheck, double* __restrict__ part) {
+                                                     int kcheck, double* __restrict__ part,
+                                                     const Ctrl* __restrict__ ctrl) {
     __shared__ double lred[12 * WG];
     const int c = threadIdx.x % KB;
     const bool on = (mask >> c) & 1ull;
-    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY};  // 5: max of -s, 6: max of s
+    const double mu = mode == 3 ? ctrl[c].mu : 0.0;
+    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY};  // 6: max of -s, 7: max of s
     const int64_t total = static_cast<int64_t>(n) * KB;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
     if (on) {
@@ -613,28 +621,34 @@ __global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double*
                 v[2] += si * si;
                 v[3] += si;
                 if (c < kcheck && !(si >= 0.0 && si <= 1.0)) v[4] += 1.0;
-                v[5] = fmax(v[5], -si);
-                v[6] = fmax(v[6], si);
+                v[6] = fmax(v[6], -si);
+                v[7] = fmax(v[7], si);
             } else {
                 if (mode == 2) X[e] = T(0);
+                if (mode == 3) {
+                    X[e] = static_cast<T>(mu);
+                    R[e] = static_cast<T>(static_cast<double>(R[e]) - mu);
+                }
                 ri = static_cast<double>(R[e]);
+                v[3] += ri;
             }
             const T zt = static_cast<T>(static_cast<double>(minv[i]) * ri);
             if (P != nullptr) P[e] = zt;
             v[0] += ri * static_cast<double>(zt);
             v[1] += ri * ri;
+            v[5] += static_cast<double>(zt);
         }
     }
-    // per-column max of slots 5, 6 over the groups, sums of the others
+    // per-column max of slots 6, 7 over the groups, sums of the others
     constexpr int NG = WG / KB;
-    for (int a = 0; a < 7; ++a) lred[a * WG + threadIdx.x] = v[a];
+    for (int a = 0; a < 8; ++a) lred[a * WG + threadIdx.x] = v[a];
     __syncthreads();
     if (threadIdx.x < KB) {
-        for (int a = 0; a < 7; ++a) {
-            double t = a < 5 ? 0.0 : -INFINITY;
+        for (int a = 0; a < 8; ++a) {
+            double t = a < 6 ? 0.0 : -INFINITY;
             for (int gr = 0; gr < NG; ++gr) {
                 const double u = lred[a * WG + gr * KB + threadIdx.x];
-                t = a < 5 ? t + u : fmax(t, u);
+                t = a < 6 ? t + u : fmax(t, u);
             }
             part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a] = t;
         }
@@ -645,7 +659,7 @@ template <int KB>
 __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, const double* __restrict__ part,
                                                          int mode, uint64_t mask, ColumnTol tol, int max_iter,
                                                          int range_check, Ctrl* __restrict__ ctrl, int stop_others,
-                                                         double eps_stop) {
+                                                         double eps_stop, int deflate) {
     const int c = blockIdx.x;  // one workgroup per column
     Ctrl& C = ctrl[c];
     if (!((mask >> c) & 1ull)) {
@@ -654,15 +668,15 @@ __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, co
         if (mode == 2 && stop_others && threadIdx.x == 0) C.done = CONVERGED;
         return;
     }
-    __shared__ double red[NWAVE * 5];
-    double tot[5];
-    column_totals<5, KB>(G, part, tot, red);
-    // max of slots 5 (-min s) and 6 (max s) over the workgroups
+    __shared__ double red[NWAVE * 6];
+    double tot[6];
+    column_totals<6, KB>(G, part, tot, red);
+    // max of slots 6 (-min s) and 7 (max s) over the workgroups
     double mx[2] = {-INFINITY, -INFINITY};
     for (int b = threadIdx.x; b < G; b += WG) {
         const double* p = part + (static_cast<int64_t>(b) * KB + c) * BPART;
-        mx[0] = fmax(mx[0], p[5]);
-        mx[1] = fmax(mx[1], p[6]);
+        mx[0] = fmax(mx[0], p[6]);
+        mx[1] = fmax(mx[1], p[7]);
     }
     mx[0] = wave_max(mx[0]);
     mx[1] = wave_max(mx[1]);
@@ -687,12 +701,15 @@ __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, co
             C.max_iter = max_iter;
         } else if (mode == 2) {
             C.ss = rr;
+            C.mu = tot[3] / static_cast<double>(n);
             C.iters = 0;
             C.max_iter = max_iter;
             C.bad = 0;
         }
         C.tol2 = tol.rtol2[c] * C.ss;
         C.eps_stop = eps_stop;
+        C.deflate = deflate;
+        C.pbar = deflate ? tot[5] / static_cast<double>(n) : 0.0;
         C.rz = rz;
         C.rr = rr;
         C.hist[C.iters % HIST] = rr;

@@ -191,12 +191,12 @@ struct ServerOps {
             const float* minv = reinterpret_cast<const float*>(static_cast<const char*>(G.plan) + G.pl.minv);
             // the same tuned launch shape as the eager batched path of this graph, width and precision
             SpmmChoice ch{};
-            if (int e = Spmm<Vc, T, KB>::choose(&G.g, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part, true, &ch))
+            if (int e = Spmm<Vc, T, KB>::choose(&G.g, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part, cg, true, &ch))
                 return e;
             b->grid_win = ch.grid;
             HIPCHK(hipStreamBeginCapture(G.st, hipStreamCaptureModeThreadLocal));
             for (int t = 0; t < s.o.iters_per_replay; ++t) {
-                if (int e = Spmm<Vc, T, KB>::launch(ch, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part)) {
+                if (int e = Spmm<Vc, T, KB>::launch(ch, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part, cg)) {
                     hipGraph_t dropped = nullptr;
                     (void)hipStreamEndCapture(G.st, &dropped);
                     if (dropped) (void)hipGraphDestroy(dropped);
@@ -256,31 +256,42 @@ struct ServerOps {
     // residual). FP64: a CG pass to relative residual rtol. FJ_MIXED: mode 0
     // also sets z = 0, r = s and the statistics of s (outer control blocks,
     // with ||r|| = ||s|| recorded for the scaling); then an inner FP32 CG on
-    // r / ||r|| to tau.
+    // r / ||r|| to tau. On graphs of >= MEAN_START_MIN_N nodes the CG passes
+    // start from the column means and are deflated, as in the eager path.
     static int start(Server& s, ServerGraph& G, ServerBlock* b, uint64_t mask, int mode) {
         const int n = G.g.n;
         const float* minv = reinterpret_cast<const float*>(static_cast<const char*>(G.plan) + G.pl.minv);
         const int max_iter = s.o.max_iter > 0 ? s.o.max_iter : 2000;
+        const bool deflate = n >= MEAN_START_MIN_N;
         ColumnTol tol{};
         if (!b->mixed) {
             for (int c = 0; c < KB; ++c) tol.rtol2[c] = b->rtol[c] * b->rtol[c];
             k_init_batched<double, KB><<<b->grid_vec, WG, 0, G.st>>>(n, KB, b->S, KB, b->X, b->R, b->P, minv, mode,
-                                                                    mask, KB, b->part);
+                                                                    mask, KB, b->part, b->ctrl);
             HIPCHK(hipGetLastError());
             // the first pass may stop on the index estimates, as the eager path does
+            const double eps_stop = mode == 0 ? 0.8 * s.o.eps : 0.0;
             k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, mode, mask, tol, max_iter, 1,
-                                                        b->ctrl, 0, mode == 0 ? 0.8 * s.o.eps : 0.0);
+                                                        b->ctrl, 0, eps_stop, (deflate && mode == 1) ? 1 : 0);
             HIPCHK(hipGetLastError());
+            if (deflate && mode == 0) {
+                k_init_batched<double, KB><<<b->grid_vec, WG, 0, G.st>>>(n, KB, nullptr, 0, b->X, b->R, b->P, minv, 3,
+                                                                        mask, 0, b->part, b->ctrl);
+                HIPCHK(hipGetLastError());
+                k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, 3, mask, tol, max_iter, 1,
+                                                            b->ctrl, 0, eps_stop, 1);
+                HIPCHK(hipGetLastError());
+            }
             b->running |= mask;
             return FJ_OK;
         }
         if (mode == 0) {
             for (int c = 0; c < KB; ++c) tol.rtol2[c] = 1.0;
             k_init_batched<double, KB><<<b->grid_vec, WG, 0, G.st>>>(n, KB, b->S, KB, b->X, b->R, nullptr, minv, 0,
-                                                                    mask, KB, b->part);
+                                                                    mask, KB, b->part, b->ctrl);
             HIPCHK(hipGetLastError());
             k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, 0, mask, tol, max_iter, 1, b->ctrl,
-                                                        0, 0.0);
+                                                        0, 0.0, 0);
             HIPCHK(hipGetLastError());
             k_ctrl_rho_from_s<<<1, WG, 0, G.st>>>(b->ctrl, KB, mask);
             HIPCHK(hipGetLastError());
@@ -289,11 +300,19 @@ struct ServerOps {
         HIPCHK(hipGetLastError());
         for (int c = 0; c < KB; ++c) tol.rtol2[c] = b->tau[c] * b->tau[c];
         k_init_batched<float, KB><<<b->grid_vec, WG, 0, G.st>>>(n, KB, nullptr, 0, b->X32, b->R32, b->P32, minv, 2,
-                                                               mask, 0, b->part);
+                                                               mask, 0, b->part, b->ictrl);
         HIPCHK(hipGetLastError());
         k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, 2, mask, tol, max_iter, 0, b->ictrl,
-                                                    0, 0.0);
+                                                    0, 0.0, 0);
         HIPCHK(hipGetLastError());
+        if (deflate) {
+            k_init_batched<float, KB><<<b->grid_vec, WG, 0, G.st>>>(n, KB, nullptr, 0, b->X32, b->R32, b->P32, minv,
+                                                                   3, mask, 0, b->part, b->ictrl);
+            HIPCHK(hipGetLastError());
+            k_fin_init_batched<KB><<<KB, WG, 0, G.st>>>(b->grid_vec, n, KB, b->part, 3, mask, tol, max_iter, 0,
+                                                        b->ictrl, 0, 0.0, 1);
+            HIPCHK(hipGetLastError());
+        }
         b->running |= mask;
         return FJ_OK;
     }
