@@ -83,10 +83,10 @@ typedef struct fj_csr {
 #define FJ_PROFILE         8u  /* time every SpMV launch with HIP events (fills fj_info.ms_*) */
 #define FJ_NO_TUNE        16u  /* batched solves: skip the SpMM autotuner, use 1 column per lane and the full grid */
 #define FJ_WARM_START     32u  /* fj_solve, k = 1: Z holds the starting guess on entry (e.g. an earlier solution) */
-#define FJ_ZERO_START     64u  /* single-vector solves: plain Jacobi-PCG from z = 0. By default, on graphs
-                                  of >= 65536 nodes, CG (FP64, or the FP32 inner solves of FJ_MIXED) starts
-                                  from mean(rhs) 1 and is deflated by the constant vector: every step is
-                                  centred, so mean(z) = mean(s) holds throughout (fewer iterations) */
+#define FJ_ZERO_START     64u  /* plain Jacobi-PCG from z = 0. By default every CG solve (FP64, the FP32
+                                  inner solves of FJ_MIXED, batched columns) starts from mean(rhs) 1 and is
+                                  deflated by the constant vector: every step is centred, so mean(z) = mean(s)
+                                  holds throughout, and fewer iterations are needed */
 
 typedef struct fj_opts {
     double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */

@@ -498,15 +498,19 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     const double eps_stop = (want_indices && o.rtol == 0.0 && packable && !z0) ? 0.8 * o.eps : 0.0;
     S.s_est = eps_stop > 0.0 ? s : nullptr;
     if (int rc = cg_init(c, S, s, lds, 0, rtol, max_iter, range_check, eps_stop)) return rc;
-    // start from mean(s) 1 and deflate the constant vector (k_cg_shift)
-    const int deflate = (!z0 && !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N) ? 1 : 0;
-    if (deflate) {
+    // deflated CG: move the start by mean(r) (from 0: to mean(s) 1) and keep
+    // every step centred (k_cg_shift)
+    const int deflate = (o.flags & FJ_ZERO_START) ? 0 : 1;
+    auto shift_start = [&]() -> int {
         k_cg_shift<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.x, S.r, S.p, c.minv(), S.ctrl, S.part);
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
                                        S.ctrl, eps_stop, 1);
         HIPCHK(hipGetLastError());
-    }
+        return FJ_OK;
+    };
+    if (deflate && !z0)
+        if (int rc = shift_start()) return rc;
     if (z0) {
         if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
         const double snorm = cc.res[6], rho = cc.res[5];
@@ -518,6 +522,8 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
             status = -1;  // iterate from z0
             prev_rho = rho;
             if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check)) return rc;
+            if (deflate)
+                if (int rc = shift_start()) return rc;
         }
         if (status >= 0) {
             cc.iters = 0;
@@ -585,7 +591,7 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
     const double snorm = std::sqrt(cc.ss);
     double rho = snorm;
     double tau = 1e-4;
-    const bool deflate = !(o.flags & FJ_ZERO_START) && n >= MEAN_START_MIN_N;
+    const bool deflate = !(o.flags & FJ_ZERO_START);
     int inner_total = 0, outer = 0, status = FJ_ERR_NOT_CONVERGED;
     if (z0) {  // start the refinement from z0 and its true residual
         if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
@@ -1035,7 +1041,7 @@ struct Batched {
     }
 
     static double rtol_target(const fj_opts& o) { return o.rtol > 0.0 ? o.rtol : o.eps * 1e-2; }
-    bool deflate_ok(const fj_opts& o) const { return !(o.flags & FJ_ZERO_START) && c.g->n >= MEAN_START_MIN_N; }
+    static bool deflate_ok(const fj_opts& o) { return !(o.flags & FJ_ZERO_START); }
 
     // FP64 for every column.
     int solve_fp64(BState<double>& S, const double* src, int64_t lds, int k, int kcheck, const fj_opts& o,

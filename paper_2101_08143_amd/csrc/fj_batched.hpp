@@ -591,9 +591,9 @@ __global__ void __launch_bounds__(WG) k_fin_update_batched(int G, int n, const d
 
 // Batched CG start. mode 0: X = 0, R = S (zero in padding columns) and the
 // statistics of each column of S; mode 1: restart from the current X with R
-// holding the true residual; mode 2: X = 0, R given (the column means become
-// mu); mode 3, after mode 0 or 2: X = mu 1, R -= mu 1, the start of deflated
-// CG (see k_cg_shift). Only columns in `mask` are touched. Partial slots per
+// holding the true residual; mode 2: X = 0, R given; mode 3, after mode 0 or
+// 2: X += m 1, R -= m 1 with m the column's mean of R at that start (rmean),
+// the start of deflated CG (see k_cg_shift). Only columns in `mask` are touched. Partial slots per
 // column: 0 rz, 1 rr, 2 ss, 3 sum s (sum r in modes 1-3), 4 bad count
 // (columns < kcheck only), 5 sum p, 6 max of -s, 7 max of s.
 template <typename T, int KB>
@@ -605,7 +605,7 @@ __global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double*
     __shared__ double lred[12 * WG];
     const int c = threadIdx.x % KB;
     const bool on = (mask >> c) & 1ull;
-    const double mu = mode == 3 ? ctrl[c].mu : 0.0;
+    const double mu = mode == 3 ? ctrl[c].rmean : 0.0;
     double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, -INFINITY};  // 6: max of -s, 7: max of s
     const int64_t total = static_cast<int64_t>(n) * KB;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
@@ -626,7 +626,7 @@ __global__ void __launch_bounds__(WG) k_init_batched(int n, int k, const double*
             } else {
                 if (mode == 2) X[e] = T(0);
                 if (mode == 3) {
-                    X[e] = static_cast<T>(mu);
+                    X[e] = static_cast<T>(static_cast<double>(X[e]) + mu);
                     R[e] = static_cast<T>(static_cast<double>(R[e]) - mu);
                 }
                 ri = static_cast<double>(R[e]);
@@ -701,7 +701,6 @@ __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, co
             C.max_iter = max_iter;
         } else if (mode == 2) {
             C.ss = rr;
-            C.mu = tot[3] / static_cast<double>(n);
             C.iters = 0;
             C.max_iter = max_iter;
             C.bad = 0;
@@ -710,6 +709,7 @@ __global__ void __launch_bounds__(WG) k_fin_init_batched(int G, int n, int k, co
         C.eps_stop = eps_stop;
         C.deflate = deflate;
         C.pbar = deflate ? tot[5] / static_cast<double>(n) : 0.0;
+        C.rmean = tot[3] / static_cast<double>(n);
         C.rz = rz;
         C.rr = rr;
         C.hist[C.iters % HIST] = rr;

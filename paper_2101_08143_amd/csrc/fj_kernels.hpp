@@ -57,6 +57,7 @@ struct Ctrl {
     double bound[5];      // certified relative error bound of each index
     double eps_stop;      // > 0: also stop once the estimated bounds of all five indices are below it
     double pbar;          // deflated CG: mean of the current direction p (0 otherwise)
+    double rmean;         // mean of r at the last CG start (k_fin_init), the shift of k_cg_shift
     double hist[HIST];    // rr after iteration t is in hist[t % HIST]
     int32_t done;         // 0 running, 1 converged, 2 iteration cap, 3 breakdown, 4 bad input
     int32_t iters;        // CG iterations so far (all passes)
@@ -942,8 +943,8 @@ __global__ void __launch_bounds__(WG) k_fin_update(int G, int n, const double* _
 // CG start. mode 0: x = 0, r = s, plus the statistics of s (mean, ||s||^2,
 // range). mode 1: restart from the current x with r already holding the true
 // residual (written by the epilogue). mode 2: x = 0 with r given (the inner
-// solve of FJ_MIXED; mu becomes mean(r)). All: p = M^{-1} r and the partial
-// sums of rz and rr.
+// solve of FJ_MIXED). All: p = M^{-1} r, the partial sums of rz and rr, and
+// mean(r) for k_cg_shift.
 // Partial slots: 0 rz, 1 rr, 2 ss, 3 sum s, 4 bad count, 5 sum p, 6 min s,
 // 7 max s.
 template <typename T>
@@ -999,17 +1000,16 @@ __global__ void __launch_bounds__(WG) k_cg_init(int n, const double* __restrict_
     }
 }
 
-// Single-vector FP64 solves of graphs from this many nodes on start from
-// mean(s) 1 and run deflated CG (below, the two extra launches cost more than
-// the iterations they save).
-constexpr int MEAN_START_MIN_N = 65536;
-
-// Start CG from the constant vector mean(s) 1 instead of 0. Since
-// (I + L) 1 = 1 (L 1 = 0, Section 2.1), its residual is exactly the centred
-// s - mean(s) 1, and the remaining error z - mean(s) 1 is the centred
+// Every CG solve runs deflated (below) unless FJ_ZERO_START asks for plain
+// Jacobi-PCG from 0.
+// Move the CG start by the mean of its residual: x += mean(r) 1, r -= mean(r) 1
+// (the coarse-space correction of the deflation below). Since (I + L) 1 = 1
+// (L 1 = 0, Section 2.1), the new r is exactly the residual of the new x. From
+// x = 0 (k_cg_init modes 0 and 2) this starts from mean(s) 1, whose residual
+// is the centred s, and the remaining error z - mean(s) 1 is the centred
 // solution that Algorithm 1 solves for separately (Section 2.2: Omega 1 = 1),
-// whose energy is far smaller than that of z. Runs after k_cg_init mode 0
-// (r = s, mu known); k_fin_init mode 1 then takes rz, rr and sum p.
+// whose energy is far smaller than that of z. Runs after k_cg_init and
+// k_fin_init (rmean known); k_fin_init mode 1 then takes rz, rr and sum p.
 //
 // Deflated CG (k_fin_init with deflate = 1) keeps that split for the whole
 // solve: with coarse space span{1}, (I + L) 1 = 1 and 1^T (I + L) = 1^T turn
@@ -1025,10 +1025,10 @@ __global__ void __launch_bounds__(WG) k_cg_shift(int n, T* __restrict__ x, T* __
                                                  const float* __restrict__ minv, const Ctrl* __restrict__ ctrl,
                                                  double* __restrict__ part) {
     __shared__ double red[NWAVE * 3];
-    const double mu = ctrl->mu;
+    const double mu = ctrl->rmean;
     double v[3] = {0.0, 0.0, 0.0};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-        x[i] = static_cast<T>(mu);
+        x[i] = static_cast<T>(static_cast<double>(x[i]) + mu);
         const T rt = static_cast<T>(static_cast<double>(r[i]) - mu);
         r[i] = rt;
         const double ri = static_cast<double>(rt);
@@ -1085,7 +1085,6 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
         }
         if (mode == 2) {  // the inner solve of FJ_MIXED: tolerance relative to its own right-hand side
             ctrl->ss = v[1];
-            ctrl->mu = v[3] / static_cast<double>(n);
             ctrl->iters = 0;
             ctrl->max_iter = max_iter;
             ctrl->bad = 0;
@@ -1094,6 +1093,7 @@ __global__ void __launch_bounds__(WG) k_fin_init(int G, int n, const double* __r
         ctrl->eps_stop = eps_stop;
         ctrl->deflate = deflate;
         ctrl->pbar = deflate ? v[5] / static_cast<double>(n) : 0.0;
+        ctrl->rmean = v[3] / static_cast<double>(n);
         ctrl->rz = v[0];
         ctrl->rr = v[1];
         ctrl->hist[ctrl->iters % HIST] = v[1];

@@ -256,13 +256,13 @@ struct ServerOps {
     // residual). FP64: a CG pass to relative residual rtol. FJ_MIXED: mode 0
     // also sets z = 0, r = s and the statistics of s (outer control blocks,
     // with ||r|| = ||s|| recorded for the scaling); then an inner FP32 CG on
-    // r / ||r|| to tau. On graphs of >= MEAN_START_MIN_N nodes the CG passes
-    // start from the column means and are deflated, as in the eager path.
+    // r / ||r|| to tau. The CG passes start from the column means and are
+    // deflated, as in the eager path.
     static int start(Server& s, ServerGraph& G, ServerBlock* b, uint64_t mask, int mode) {
         const int n = G.g.n;
         const float* minv = reinterpret_cast<const float*>(static_cast<const char*>(G.plan) + G.pl.minv);
         const int max_iter = s.o.max_iter > 0 ? s.o.max_iter : 2000;
-        const bool deflate = n >= MEAN_START_MIN_N;
+        const bool deflate = true;
         ColumnTol tol{};
         if (!b->mixed) {
             for (int c = 0; c < KB; ++c) tol.rtol2[c] = b->rtol[c] * b->rtol[c];
