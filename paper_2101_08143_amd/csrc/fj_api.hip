@@ -761,8 +761,8 @@ struct Spmm {
     // The launch shape for this graph: cached, or tuned now on the caller's
     // vectors (Q and part are overwritten; the next SpMM recomputes them).
     static int choose(const fj_csr* g, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
-                      const T* P, const T* R, const float* minv, T* Q, double* part, const Ctrl* ctrl,
-                      bool tune, SpmmChoice* out) {
+                      const T* P, const T* R, const float* minv, T* Q, double* part, bool tune,
+                      SpmmChoice* out) {
         if (!tune) {
             out->cpl = 1;
             out->split = true;
@@ -797,9 +797,10 @@ struct Spmm {
         SpmmChoice pick = cand.front();
         int rc = FJ_OK;
         for (const SpmmChoice& ch : cand) {
-            if ((rc = launch(ch, st, G, desc, K, P, R, minv, Q, part, ctrl))) break;  // warm-up
+            // timed on every column (no control blocks: no early exit, no shift)
+            if ((rc = launch(ch, st, G, desc, K, P, R, minv, Q, part, nullptr))) break;  // warm-up
             if (hipEventRecord(e0, st) != hipSuccess) { rc = FJ_ERR_HIP; break; }
-            for (int r = 0; r < REPS && rc == FJ_OK; ++r) rc = launch(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
+            for (int r = 0; r < REPS && rc == FJ_OK; ++r) rc = launch(ch, st, G, desc, K, P, R, minv, Q, part, nullptr);
             if (rc) break;
             float ms = 0.f;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -885,7 +886,7 @@ struct Batched {
             SpmmChoice& ch = sizeof(T) == sizeof(double) ? ch64 : ch32;
             if (ch.grid == 0)
                 if (int e = Spmm<Vc, T, KB>::choose(c.g, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q, S.part,
-                                                    S.ctrl, tune, &ch))
+                                                    tune, &ch))
                     return e;
             grid_win = ch.grid;
             if (c.profile) {

@@ -463,9 +463,19 @@ __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restr
                                                 const T* __restrict__ P, const T* __restrict__ R,
                                                 const float* __restrict__ minv, T* __restrict__ Q,
                                                 double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    // launches queued past the last column's stop return at once; ctrl null
+    // (the autotuner's timing runs): every column, no shift
+    __shared__ int live;
+    if (threadIdx.x == 0) live = ctrl == nullptr ? 1 : 0;
+    __syncthreads();
+    if (ctrl != nullptr && threadIdx.x < KB && ctrl[threadIdx.x].done == RUNNING) live = 1;
+    __syncthreads();
+    if (!live) return;
     OpSpmmCg<T, KB, CPL> op{R, minv, Q};
+    if (ctrl != nullptr) {
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) op.shift[q] = ctrl[(threadIdx.x % (KB / CPL)) * CPL + q].pbar;
+        for (int q = 0; q < CPL; ++q) op.shift[q] = ctrl[(threadIdx.x % (KB / CPL)) * CPL + q].pbar;
+    }
     if constexpr (SPLIT) {
         __shared__ SpmmStage<V, KB, CPL> st;
         static_assert(sizeof(st) >= 3 * WG * CPL * sizeof(double), "stage too small to reuse for the partials");

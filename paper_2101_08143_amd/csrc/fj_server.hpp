@@ -191,7 +191,7 @@ struct ServerOps {
             const float* minv = reinterpret_cast<const float*>(static_cast<const char*>(G.plan) + G.pl.minv);
             // the same tuned launch shape as the eager batched path of this graph, width and precision
             SpmmChoice ch{};
-            if (int e = Spmm<Vc, T, KB>::choose(&G.g, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part, cg, true, &ch))
+            if (int e = Spmm<Vc, T, KB>::choose(&G.g, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part, true, &ch))
                 return e;
             b->grid_win = ch.grid;
             HIPCHK(hipStreamBeginCapture(G.st, hipStreamCaptureModeThreadLocal));

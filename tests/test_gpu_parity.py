@@ -555,3 +555,43 @@ def test_full_size_batched_k64(torch_fj, precision):
             assert err <= EPS, (c, k, err)
     del G
     torch.cuda.empty_cache()
+
+
+def test_concurrent_calls_on_distinct_workspaces(torch_fj, graphs):
+    """The ABI is thread-safe for calls that use distinct workspaces: four host
+    threads, each with its own stream and workspaces, run single, batched and
+    mixed-precision index solves on shared graphs at the same time; every
+    result is bitwise the one the same call gives alone."""
+    import threading
+    torch, fj = torch_fj
+    say("concurrent calls")
+    jobs = []
+    for t, (name, k, prec) in enumerate([("cl50k_f32", 1, fj.FJ_FP64), ("cl100k_unit", 4, fj.FJ_FP64),
+                                         ("ba3000", 1, fj.FJ_MIXED), ("cl50k_f32", 8, fj.FJ_MIXED)]):
+        g, G = graphs[name]
+        S = np.random.default_rng(60 + t).random((g.n, k))
+        Sd = torch.from_numpy(S if k > 1 else S[:, 0].copy()).to("cuda:0")
+        o = fj.make_opts(eps=EPS, precision=prec)
+        jobs.append((G, Sd, o, G.workspace(k, o), torch.cuda.Stream()))
+    ref = [fj.fj_indices(G, Sd, o, ws=ws)[0] for G, Sd, o, ws, _ in jobs]
+    torch.cuda.synchronize()
+    got = [[] for _ in jobs]
+    errors = []
+
+    def worker(j):
+        G, Sd, o, ws, st = jobs[j]
+        try:
+            for _ in range(3):
+                got[j].append(fj.fj_indices(G, Sd, o, ws=ws, stream=st)[0])
+        except Exception as e:  # reported below; the other threads keep going
+            errors.append((j, repr(e)))
+
+    threads = [threading.Thread(target=worker, args=(j,)) for j in range(len(jobs))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for j in range(len(jobs)):
+        assert len(got[j]) == 3 and all(v == ref[j] for v in got[j]), j
