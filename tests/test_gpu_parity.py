@@ -595,3 +595,26 @@ def test_concurrent_calls_on_distinct_workspaces(torch_fj, graphs):
     assert not errors, errors
     for j in range(len(jobs)):
         assert len(got[j]) == 3 and all(v == ref[j] for v in got[j]), j
+
+
+@pytest.mark.parametrize("k", [1, 4])
+@pytest.mark.parametrize("zero_start", [False, True])
+def test_restart_passes_certify(torch_fj, graphs, k, zero_start):
+    """A loose first-pass residual target (rtol 1e-3) cannot certify 1e-6, so
+    the solve restarts from the true residual with a tighter target (a second
+    pass, deflated or plain) and then certifies; the indices match the
+    oracle."""
+    torch, fj = torch_fj
+    g, G = graphs["cl50k_f32"]
+    say(f"restart passes k={k} zero_start={zero_start}")
+    S = _block(g.n, k, 700 + k)
+    Sd = torch.from_numpy(S if k > 1 else S[:, 0].copy()).to("cuda:0")
+    flags = fj.FJ_ZERO_START if zero_start else 0
+    vals, infos, rc = fj.fj_indices(G, Sd, fj.make_opts(eps=EPS, rtol=1e-3, flags=flags), check=False)
+    assert rc == fj.FJ_OK
+    assert max(i.passes for i in infos) >= 2
+    for c in range(k):
+        ref, _, _ = O.indices(g, S[:, c])
+        for j, nm in enumerate(NAMES):
+            err = abs(vals[c][nm] - ref[nm]) / abs(ref[nm])
+            assert err <= EPS and err <= infos[c].bound[j] + 1e-12, (c, nm, err)
