@@ -368,24 +368,29 @@ __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __rest
 // Per-column workgroup sums of N accumulators: lane l of every group holds
 // the workgroup's share for columns l*CPL + q in v[a][q]; groups are added in
 // order and the result goes to part[(blockIdx.x * KB + c) * BPART + a].
-template <int N, int KB, int CPL>
+// C sums at a time (lred holds C * WG * CPL doubles), so that a kernel can
+// reduce through LDS it already owns.
+template <int N, int KB, int CPL, int C = N>
 __device__ __forceinline__ void store_column_partials(const double (&v)[N][CPL], double* lred,
                                                       double* __restrict__ part) {
     constexpr int GW = KB / CPL;
     constexpr int NG = WG / GW;
-    static_assert(N * WG * CPL <= 12 * WG, "LDS buffer too small");
+    static_assert(C * WG * CPL <= 12 * WG, "LDS buffer too small");
     const int lane = threadIdx.x % GW, grp = threadIdx.x / GW;
-    for (int a = 0; a < N; ++a)
-        for (int q = 0; q < CPL; ++q) lred[a * NG * KB + grp * KB + lane * CPL + q] = v[a][q];
-    __syncthreads();
-    if (threadIdx.x < KB) {
-        for (int a = 0; a < N; ++a) {
-            double t = 0.0;
-            for (int gr = 0; gr < NG; ++gr) t += lred[a * NG * KB + gr * KB + threadIdx.x];
-            part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a] = t;
+    for (int a0 = 0; a0 < N; a0 += C) {
+        const int na = N - a0 < C ? N - a0 : C;
+        for (int a = 0; a < na; ++a)
+            for (int q = 0; q < CPL; ++q) lred[a * NG * KB + grp * KB + lane * CPL + q] = v[a0 + a][q];
+        __syncthreads();
+        if (threadIdx.x < KB) {
+            for (int a = 0; a < na; ++a) {
+                double t = 0.0;
+                for (int gr = 0; gr < NG; ++gr) t += lred[a * NG * KB + gr * KB + threadIdx.x];
+                part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a0 + a] = t;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // Totals of N partials of column c = blockIdx.x over G workgroups, for a
@@ -739,10 +744,11 @@ __global__ void __launch_bounds__(WG) k_epilogue_batched(Csr<V> g, const WinDesc
                                                          double* __restrict__ R, double* __restrict__ part,
                                                          const Ctrl* __restrict__ ctrl) {
     __shared__ SpmmStage<V, KB, 1> st;
-    __shared__ double lred[9 * WG];
     OpSpmmEpilogue<KB> op{S, lds, k, mask, ctrl, R};
     spmm_windows<double, V, AccLinSq, KB, 1>(g, desc, K, Z, op, st);
-    store_column_partials<9, KB, 1>(op.v, lred, part);
+    // the window pass ended with a barrier: its LDS takes the partial sums, three at a time
+    static_assert(sizeof(st) >= 3 * WG * sizeof(double), "stage too small to reuse for the partials");
+    store_column_partials<9, KB, 1, 3>(op.v, reinterpret_cast<double*>(&st), part);
 }
 
 template <int KB>
