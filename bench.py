@@ -1,6 +1,6 @@
 """Benchmark: certified FJ index solves per second on one MI355X.
 
-One step = one fj_indices call: the right-hand-side statistics, the
+One step = one fj_indices call: the right-hand-side statistics, the deflated
 Jacobi-preconditioned CG solve of (I+L)z = s and the fused index epilogue with
 its certificate (every index within eps = 1e-6 relative), on a graph and an
 opinion vector already resident in HBM; the per-graph fj_prepare runs once
