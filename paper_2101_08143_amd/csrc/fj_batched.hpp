@@ -244,6 +244,7 @@ __device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __r
 #pragma unroll
                 for (int q = 0; q < CPL; ++q) {
                     double LL = 0.0, SS = 0.0;
+#pragma unroll 4  // fully unrolled, the group loads of narrow blocks cost up to 100 registers
                     for (int gr = 0; gr < NG; ++gr) {
                         LL += st.plin[gr * KB + c0 + q];
                         SS += st.psq[gr * KB + c0 + q];
