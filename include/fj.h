@@ -155,6 +155,8 @@ int fj_apply(const fj_csr *g, const void *plan, const double *x, double *y, void
 /*
  * Z ~= (I + L)^{-1} S (Eq. FJmodel02) for k columns. S and Z are node-major:
  * column c of node i is S[i * lds + c] (lds >= k), likewise Z with ldz.
+ * Each column is solved by Jacobi-preconditioned CG deflated by the constant
+ * vector (see FJ_ZERO_START), independently of the other columns.
  * Stops when the true relative residual is <= opts->rtol (0 means eps*1e-2).
  * info: host array of k entries (may be NULL). Synchronises before returning.
  */
