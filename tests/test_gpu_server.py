@@ -173,3 +173,56 @@ def test_server_cancel(env, precision):
     for rid, ref in zip(ids[1:3], alone):
         assert res[rid]["status"] == fj.FJ_OK and res[rid]["values"] == ref["values"]
     srv.close()
+
+
+@pytest.fixture(scope="module")
+def serving_config():
+    """The serving workload at full size: 32 Chung-Lu graphs (n log-uniform in
+    [1e4, 2e6]) resident on the device, 16 U[0,1] vectors per graph."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_08143_amd import fj
+    graphs, G, pools = [], [], []
+    for p in W.serving_graph_params():
+        g = W.serving_graph(p)
+        say(f"serving graph seed={p['seed']} n={g.n} nnz={g.nnz}")
+        graphs.append(g)
+        G.append(fj.Graph.from_csr(g, device="cuda:0"))
+        pools.append(np.random.default_rng(p["seed"] + 11).random((g.n, 16)))
+    return torch, fj, graphs, G, pools
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_serving_full_size_sampled(serving_config, precision):
+    """96 requests of 1-16 vectors on the 32 full-size serving graphs, submitted
+    at once (16-column blocks, 8 captured iterations per replay, as the
+    benchmark runs them): every request certified; sampled columns on the
+    largest, the smallest and four other graphs within 1e-6 of the oracle."""
+    torch, fj, graphs, G, pools = serving_config
+    reqs = W.serving_requests(96, len(graphs), seed=3100, kmax=16)
+    srv = fj.Server(96 << 30, block_columns=16, iters_per_replay=8, precision=_prec(fj, precision))
+    gids = [srv.add_graph(g) for g in G]
+    say(f"serving full size {precision}")
+    ids = [srv.submit(gids[gi], torch.from_numpy(np.ascontiguousarray(pools[gi][:, :k])).to("cuda:0"))
+           for gi, k, _ in reqs]
+    res = {r["id"]: r for r in srv.drain(timeout_s=240)}
+    srv.close()
+    assert all(res[i]["status"] == fj.FJ_OK for i in ids)
+    by_size = sorted(range(len(graphs)), key=lambda gi: graphs[gi].nnz)
+    wanted = [by_size[-1], by_size[0]] + by_size[8:32:6]
+    checked = 0
+    for gi in wanted:
+        hits = [j for j, (g2, _, _) in enumerate(reqs) if g2 == gi]
+        if not hits:
+            continue
+        j = hits[0]
+        k = reqs[j][1]
+        for c in sorted({0, k - 1}):
+            say(f"oracle graph {gi} column {c}")
+            ref, _, _ = O.indices(graphs[gi], pools[gi][:, c])
+            for name in NAMES:
+                assert abs(res[ids[j]]["values"][c][name] - ref[name]) <= 1e-6 * abs(ref[name]), (gi, c, name)
+        checked += 1
+    assert checked >= 4
