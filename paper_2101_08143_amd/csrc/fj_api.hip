@@ -60,6 +60,10 @@ struct PlanLayout {
     size_t blk_row;   // int[K + 1]
     size_t desc;      // WinDesc[K]
     size_t minv;      // float[n]
+    size_t mate;      // int[n]: partner in the heavy-edge matching, -1 if none
+    size_t pc;        // float2[n]: coefficients of the 2x2 block preconditioner
+    size_t prop;      // int[n], float[n]: matching scratch (proposals, their weights)
+    size_t pw;
     size_t flags;     // int[64] scratch for validation
     size_t total;
 };
@@ -75,6 +79,14 @@ PlanLayout plan_layout(const fj_csr* g) {
     off = align_up(off + sizeof(WinDesc) * static_cast<size_t>(L.K));
     L.minv = off;
     off = align_up(off + sizeof(float) * static_cast<size_t>(g->n));
+    L.mate = off;
+    off = align_up(off + sizeof(int) * static_cast<size_t>(g->n));
+    L.pc = off;
+    off = align_up(off + sizeof(float2) * static_cast<size_t>(g->n));
+    L.prop = off;
+    off = align_up(off + sizeof(int) * static_cast<size_t>(g->n));
+    L.pw = off;
+    off = align_up(off + sizeof(float) * static_cast<size_t>(g->n));
     L.flags = off;
     off = align_up(off + sizeof(int) * 64);
     L.total = off;
@@ -84,6 +96,7 @@ PlanLayout plan_layout(const fj_csr* g) {
 struct WsLayout {
     int kp;                     // columns per block (1, or a power of two 2..KMAX)
     size_t x, r, p, q;          // FP64 vectors (p, q only for FJ_FP64)
+    size_t z, mq;               // one FP64 vector: M^{-1} r and M^{-1} q of the block preconditioner
     size_t x32, r32, p32, q32;  // FP32 vectors of the inner solve (FJ_MIXED only)
     size_t sblk;                // FJ_TWO_SOLVE: the block [s, s - mean(s)]
     size_t part, ctrl, total;   // partial sums; control blocks (outer kp, inner kp)
@@ -116,6 +129,10 @@ WsLayout ws_layout(const fj_csr* g, int k, int precision, uint32_t flags) {
     if (!mixed) {
         L.p = off; off += v64;
         L.q = off; off += v64;
+        if (L.kp == 1) {
+            L.z = off; off += v64;
+            L.mq = off; off += v64;
+        }
     } else {
         L.x32 = off; off += v32;
         L.r32 = off; off += v32;
@@ -261,6 +278,9 @@ struct CgState {
     Ctrl* ctrl;
     double* part;
     const double* s_est = nullptr;  // FP64 only: s (contiguous) for the on-device index estimates
+    double* z = nullptr;            // FP64 with the 2x2 block preconditioner: M^{-1} r, M^{-1} q
+    double* mq = nullptr;
+    bool pairs = false;
 };
 
 // What every launch of a solve needs.
@@ -275,6 +295,8 @@ struct Ctx {
     int grid_vec = 1;
     const WinDesc* desc() const { return reinterpret_cast<const WinDesc*>(plan + pl.desc); }
     const float* minv() const { return reinterpret_cast<const float*>(plan + pl.minv); }
+    const int* mate() const { return reinterpret_cast<const int*>(plan + pl.mate); }
+    const float2* pc() const { return reinterpret_cast<const float2*>(plan + pl.pc); }
 
     int profile_total(fj_info* info) {
         if (!profile || !info) return FJ_OK;
@@ -306,8 +328,48 @@ int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, doubl
     return FJ_OK;
 }
 
+// One CG step with the 2x2 block preconditioner (FP64, one vector).
+int cg_iteration_pair(Ctx& c, CgState<double>& S) {
+    int grid_win = 1;
+    int rc = with_graph(c.g, [&](auto G) -> int {
+        using Vc = typename decltype(G)::value_type;
+        if (int e = grid_for(k_cg_spmv_pq<Vc>, c.pl.K, &grid_win)) return e;
+        if (c.profile) {
+            if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
+            HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
+        }
+        k_cg_spmv_pq<Vc><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.q, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        if (c.profile) {
+            HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
+            ++c.n_prof;
+        }
+        return FJ_OK;
+    });
+    if (rc) return rc;
+    const int n = c.g->n;
+    k_pair_dots<<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, c.mate(), c.pc(), S.mq, S.part, S.ctrl);
+    HIPCHK(hipGetLastError());
+    k_fin_pair<<<1, WG, 0, c.st>>>(grid_win, c.grid_vec, S.part, S.ctrl);
+    HIPCHK(hipGetLastError());
+    if (S.s_est != nullptr) {
+        k_cg_update_pair<true><<<c.grid_vec, WG, 0, c.st>>>(n, S.x, S.r, S.p, S.q, S.z, S.mq, S.s_est, S.part, S.ctrl);
+        HIPCHK(hipGetLastError());
+        k_fin_update<true><<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, S.ctrl);
+    } else {
+        k_cg_update_pair<false><<<c.grid_vec, WG, 0, c.st>>>(n, S.x, S.r, S.p, S.q, S.z, S.mq, nullptr, S.part,
+                                                               S.ctrl);
+        HIPCHK(hipGetLastError());
+        k_fin_update<false><<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, S.ctrl);
+    }
+    HIPCHK(hipGetLastError());
+    return FJ_OK;
+}
+
 template <typename T>
 int cg_iteration(Ctx& c, CgState<T>& S) {
+    if constexpr (std::is_same<T, double>::value)
+        if (S.pairs) return cg_iteration_pair(c, S);
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
@@ -509,8 +571,22 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
         HIPCHK(hipGetLastError());
         return FJ_OK;
     };
+    // 2x2 block preconditioner on the plan's heavy-edge matching (default):
+    // z = M^{-1} r and p = z replace the Jacobi start every start leaves
+    S.pairs = S.z != nullptr && !(o.flags & FJ_DIAG_PRECOND) && c.g->n >= PAIR_MIN_N;
+    auto pair_start = [&](double stop) -> int {
+        if (!S.pairs) return FJ_OK;
+        k_pair_start<<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.r, S.z, S.p, c.mate(), c.pc(), S.part);
+        HIPCHK(hipGetLastError());
+        k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
+                                       S.ctrl, stop, deflate);
+        HIPCHK(hipGetLastError());
+        return FJ_OK;
+    };
     if (deflate && !z0)
         if (int rc = shift_start()) return rc;
+    if (!z0)
+        if (int rc = pair_start(eps_stop)) return rc;
     if (z0) {
         if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
         const double snorm = cc.res[6], rho = cc.res[5];
@@ -524,6 +600,7 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
             if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check)) return rc;
             if (deflate)
                 if (int rc = shift_start()) return rc;
+            if (int rc = pair_start(eps_stop)) return rc;
         }
         if (status >= 0) {
             cc.iters = 0;
@@ -562,6 +639,7 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
         S.s_est = nullptr;  // a restart runs to its residual target
         // (still deflated: x keeps mean(s), so the true residual is centred up to rounding)
         if (int rc = cg_init(c, S, s, lds, 1, rtol, max_iter, range_check, 0.0, deflate)) return rc;
+        if (int rc = pair_start(0.0)) return rc;
     }
     fill_outputs(cc, status, passes, 0, out, info);
     if (info)
@@ -676,6 +754,10 @@ int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, d
     CgState<double> S64{reinterpret_cast<double*>(W + wl.x), reinterpret_cast<double*>(W + wl.r),
                         mixed ? nullptr : reinterpret_cast<double*>(W + wl.p),
                         mixed ? nullptr : reinterpret_cast<double*>(W + wl.q), &ctrls[0], part};
+    if (!mixed) {
+        S64.z = reinterpret_cast<double*>(W + wl.z);
+        S64.mq = reinterpret_cast<double*>(W + wl.mq);
+    }
     int status;
     if (o.precision == FJ_MIXED) {
         CgState<float> S32{reinterpret_cast<float*>(W + wl.x32), reinterpret_cast<float*>(W + wl.r32),
@@ -1374,6 +1456,22 @@ int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_byt
         int grid = 1;
         if (int rc = grid_for(k_diag<Vc>, pl.K, &grid)) return rc;
         k_diag<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, minv);
+        HIPCHK(hipGetLastError());
+        // heavy-edge matching for the 2x2 block preconditioner
+        int* mate = reinterpret_cast<int*>(P + pl.mate);
+        int* prop = reinterpret_cast<int*>(P + pl.prop);
+        float* pw = reinterpret_cast<float*>(P + pl.pw);
+        float2* pc = reinterpret_cast<float2*>(P + pl.pc);
+        const int gv = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + WG - 1) / WG, 8192));
+        k_pair_init<<<gv, WG, 0, st>>>(g->n, mate);
+        HIPCHK(hipGetLastError());
+        for (int round = 0; round < PAIR_ROUNDS; ++round) {
+            k_pair_propose<Vc><<<gv, WG, 0, st>>>(G, mate, prop, pw);
+            HIPCHK(hipGetLastError());
+            k_pair_accept<<<gv, WG, 0, st>>>(g->n, prop, mate);
+            HIPCHK(hipGetLastError());
+        }
+        k_pair_coef<<<gv, WG, 0, st>>>(g->n, mate, pw, minv, pc);
         HIPCHK(hipGetLastError());
         return FJ_OK;
     });

@@ -618,3 +618,48 @@ def test_restart_passes_certify(torch_fj, graphs, k, zero_start):
         for j, nm in enumerate(NAMES):
             err = abs(vals[c][nm] - ref[nm]) / abs(ref[nm])
             assert err <= EPS and err <= infos[c].bound[j] + 1e-12, (c, nm, err)
+
+
+def _skewed_weights(g, span, seed):
+    """The same graph with weights log-uniform over a factor `span`, equal in
+    both directions of every edge (a hash of the edge's end points)."""
+    import dataclasses
+    rows = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr))
+    lo = np.minimum(rows, g.col.astype(np.uint64))
+    hi = np.maximum(rows, g.col.astype(np.uint64))
+    h = (lo * np.uint64(g.n) + hi + np.uint64(seed)) * np.uint64(0x9E3779B97F4A7C15)
+    u = (h >> np.uint64(11)).astype(np.float64) / 2.0 ** 53
+    w = np.exp(np.log(1.0 / np.sqrt(span)) + u * np.log(span))
+    return dataclasses.replace(g, val=w.astype(np.float64))
+
+
+@pytest.mark.parametrize("span", [4.0, 1e4])
+def test_pair_preconditioner(torch_fj, span):
+    """One-vector FP64 solves of graphs of >= 65536 nodes use 2x2 blocks of
+    I + L on a heavy-edge matching: on a graph whose weights spread over a
+    factor 1e4 they need far fewer iterations than Jacobi (FJ_DIAG_PRECOND;
+    a CPU model of both: 67 against 119 to relative residual 1e-9), and both
+    match the oracle's z and indices."""
+    torch, fj = torch_fj
+    g = _skewed_weights(W.chung_lu(100_000, 2.5, 10.0, 31), span, 7)
+    say(f"pair preconditioner span={span:g} n={g.n} nnz={g.nnz}")
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    s = W.opinions("uniform", g.n, 32)
+    sd = torch.from_numpy(s).to("cuda:0")
+    zref, _ = O.solve(g, s, rtol=1e-14)
+    ref, _, _ = O.indices(g, s)
+    its = {}
+    for flags in (0, fj.FJ_DIAG_PRECOND):
+        z, info, rc = fj.fj_solve(G, sd, fj.make_opts(rtol=1e-10, flags=flags))
+        assert rc == fj.FJ_OK
+        assert np.linalg.norm(z.cpu().numpy() - zref) <= 1.1e-10 * np.linalg.norm(s), flags
+        its[flags] = info[0].iters
+        vals, infos, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, flags=flags))
+        assert rc == fj.FJ_OK
+        for j, nm in enumerate(NAMES):
+            err = abs(vals[0][nm] - ref[nm]) / abs(ref[nm])
+            assert err <= EPS and err <= infos[0].bound[j] + 1e-12, (flags, nm, err)
+    if span > 100:
+        assert its[0] <= 0.75 * its[fj.FJ_DIAG_PRECOND], its
+    else:
+        assert its[0] <= its[fj.FJ_DIAG_PRECOND], its
