@@ -70,6 +70,18 @@ def spmv_bytes(n: int, nnz: int, val_bytes: int) -> int:
     return nnz * (4 + val_bytes) + 4 * (n + 1) + 8 * n + 8 * n + 4 * n + 8 * n
 
 
+def spmv_pq_bytes(n: int, nnz: int, val_bytes: int) -> int:
+    """Algorithmic bytes of one SpMV launch of the block-preconditioned CG
+    (k_cg_spmv_pq): col and val once, row_ptr once, p once (an ideal gather)
+    and q written once; the preconditioned products are formed elsewhere."""
+    return nnz * (4 + val_bytes) + 4 * (n + 1) + 8 * n + 8 * n
+
+
+# One-vector FP64 solves use the 2x2 block preconditioner from this many
+# nodes on (include/fj.h, FJ_DIAG_PRECOND), so their SpMV is k_cg_spmv_pq.
+PAIR_MIN_N = 65536
+
+
 def spmm_bytes(n: int, nnz: int, val_bytes: int, kb: int, elem: int) -> int:
     """Algorithmic bytes of one batched SpMM launch (k_spmm_cg) for kb columns of
     `elem`-byte values: col and val once, row_ptr once, each row's block of P
@@ -314,7 +326,10 @@ def main():
     print(f"[bench] mixed: {args.steps} steps in {mixed['elapsed']:.3f}s", file=sys.stderr, flush=True)
 
     val_bytes = 0 if g.val is None else g.val.dtype.itemsize
-    b_launch = spmv_bytes(g.n, g.nnz, val_bytes)
+    pairs = g.n >= PAIR_MIN_N
+    b_launch = (spmv_pq_bytes if pairs else spmv_bytes)(g.n, g.nnz, val_bytes)
+    vt = {0: "Unit", 4: "float", 8: "double"}[val_bytes]
+    spmv_name = f"k_cg_spmv_pq<{vt}>" if pairs else f"k_cg_spmv<{vt}, double>"
     avg_ms = fp64["ms_spmv"] / max(fp64["n_spmv"], 1)
     work_ms = fp64["ms_spmv"] / max(fp64["iters"], 1)  # launches past convergence return at once
     bytes_per_launch = b_launch * fp64["iters"] / max(fp64["n_spmv"], 1)  # launches after convergence do no work
@@ -364,12 +379,12 @@ def main():
                    "precision": "fp64", "rhs_per_solve": 1},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cg_spmv",
+            "kernel": spmv_name,
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": recorded_traffic("k_cg_spmv<float, double>"),
+            "traffic": recorded_traffic(spmv_name),
             "avg_launch_ms": avg_ms,
             "launches": fp64["n_spmv"],
             "working_launches": fp64["iters"],

@@ -24,6 +24,14 @@ def test_spmv_algorithmic_bytes_of_the_4m_node_workload():
     assert bench.spmv_bytes(n, nnz, 4) == nnz * 8 + 4 * (n + 1) + n * (3 * 8 + 4) == 1_082_488_372
 
 
+def test_block_preconditioned_spmv_algorithmic_bytes():
+    """The SpMV of the 2x2-block-preconditioned CG reads col + val, row_ptr
+    and p and writes q: 1,034,488,372 bytes per launch on the 4M-node graph."""
+    n, nnz = 4_000_000, 119_311_046
+    assert bench.spmv_pq_bytes(n, nnz, 4) == nnz * 8 + 4 * (n + 1) + 16 * n == 1_034_488_372
+    assert bench.PAIR_MIN_N == 65536
+
+
 def test_spmm_algorithmic_bytes():
     """k = 64 FP64 columns on the 1M-node unit-weight graph: col per entry,
     row_ptr, P read, R read, Q written, M^-1."""
