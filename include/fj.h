@@ -87,10 +87,11 @@ typedef struct fj_csr {
                                   inner solves of FJ_MIXED, batched columns) starts from mean(rhs) 1 and is
                                   deflated by the constant vector: every step is centred, so mean(z) = mean(s)
                                   holds throughout, and fewer iterations are needed */
-#define FJ_DIAG_PRECOND  128u  /* one-vector FP64 solves: Jacobi (diagonal) preconditioning only. By default,
-                                  on graphs of >= 65536 nodes, they use 2x2 blocks of I + L on a heavy-edge
-                                  matching made by fj_prepare (z_i = c1_i r_i + c2_i r_j for a pair i, j):
-                                  fewer iterations, most on graphs whose edge weights spread widely */
+#define FJ_DIAG_PRECOND  128u  /* one-vector solves: Jacobi (diagonal) preconditioning only. By default, on
+                                  graphs of >= 65536 nodes (FJ_MIXED: also mean degree >= 16), CG uses 2x2
+                                  blocks of I + L on a heavy-edge matching made by fj_prepare
+                                  (z_i = c1_i r_i + c2_i r_j for a pair i, j): fewer iterations, most on
+                                  graphs whose edge weights spread widely */
 
 typedef struct fj_opts {
     double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */

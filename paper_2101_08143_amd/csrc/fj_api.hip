@@ -96,7 +96,8 @@ PlanLayout plan_layout(const fj_csr* g) {
 struct WsLayout {
     int kp;                     // columns per block (1, or a power of two 2..KMAX)
     size_t x, r, p, q;          // FP64 vectors (p, q only for FJ_FP64)
-    size_t z, mq;               // one FP64 vector: M^{-1} r and M^{-1} q of the block preconditioner
+    size_t z, mq;               // one vector: M^{-1} r and M^{-1} q of the block preconditioner (FP64)
+    size_t z32, mq32;           // the same for the FP32 inner solve of FJ_MIXED
     size_t x32, r32, p32, q32;  // FP32 vectors of the inner solve (FJ_MIXED only)
     size_t sblk;                // FJ_TWO_SOLVE: the block [s, s - mean(s)]
     size_t part, ctrl, total;   // partial sums; control blocks (outer kp, inner kp)
@@ -138,6 +139,10 @@ WsLayout ws_layout(const fj_csr* g, int k, int precision, uint32_t flags) {
         L.r32 = off; off += v32;
         L.p32 = off; off += v32;
         L.q32 = off; off += v32;
+        if (L.kp == 1) {
+            L.z32 = off; off += v32;
+            L.mq32 = off; off += v32;
+        }
     }
     if (k == 1 && (flags & FJ_TWO_SOLVE)) {
         L.sblk = off;
@@ -278,8 +283,8 @@ struct CgState {
     Ctrl* ctrl;
     double* part;
     const double* s_est = nullptr;  // FP64 only: s (contiguous) for the on-device index estimates
-    double* z = nullptr;            // FP64 with the 2x2 block preconditioner: M^{-1} r, M^{-1} q
-    double* mq = nullptr;
+    T* z = nullptr;                 // with the 2x2 block preconditioner: M^{-1} r, M^{-1} q
+    T* mq = nullptr;
     bool pairs = false;
 };
 
@@ -328,17 +333,18 @@ int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, doubl
     return FJ_OK;
 }
 
-// One CG step with the 2x2 block preconditioner (FP64, one vector).
-int cg_iteration_pair(Ctx& c, CgState<double>& S) {
+// One CG step with the 2x2 block preconditioner (one vector).
+template <typename T>
+int cg_iteration_pair(Ctx& c, CgState<T>& S) {
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
-        if (int e = grid_for(k_cg_spmv_pq<Vc>, c.pl.K, &grid_win)) return e;
+        if (int e = grid_for(k_cg_spmv_pq<Vc, T>, c.pl.K, &grid_win)) return e;
         if (c.profile) {
             if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
         }
-        k_cg_spmv_pq<Vc><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.q, S.part, S.ctrl);
+        k_cg_spmv_pq<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.q, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
         if (c.profile) {
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
@@ -348,17 +354,22 @@ int cg_iteration_pair(Ctx& c, CgState<double>& S) {
     });
     if (rc) return rc;
     const int n = c.g->n;
-    k_pair_dots<<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, c.mate(), c.pc(), S.mq, S.part, S.ctrl);
+    k_pair_dots<T><<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, c.mate(), c.pc(), S.mq, S.part, S.ctrl);
     HIPCHK(hipGetLastError());
     k_fin_pair<<<1, WG, 0, c.st>>>(grid_win, c.grid_vec, S.part, S.ctrl);
     HIPCHK(hipGetLastError());
-    if (S.s_est != nullptr) {
-        k_cg_update_pair<true><<<c.grid_vec, WG, 0, c.st>>>(n, S.x, S.r, S.p, S.q, S.z, S.mq, S.s_est, S.part, S.ctrl);
-        HIPCHK(hipGetLastError());
-        k_fin_update<true><<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, S.ctrl);
+    bool est = false;
+    if constexpr (std::is_same<T, double>::value) est = S.s_est != nullptr;
+    if (est) {
+        if constexpr (std::is_same<T, double>::value) {
+            k_cg_update_pair<T, true><<<c.grid_vec, WG, 0, c.st>>>(n, S.x, S.r, S.p, S.q, S.z, S.mq, S.s_est, S.part,
+                                                                  S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_fin_update<true><<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, S.ctrl);
+        }
     } else {
-        k_cg_update_pair<false><<<c.grid_vec, WG, 0, c.st>>>(n, S.x, S.r, S.p, S.q, S.z, S.mq, nullptr, S.part,
-                                                               S.ctrl);
+        k_cg_update_pair<T, false><<<c.grid_vec, WG, 0, c.st>>>(n, S.x, S.r, S.p, S.q, S.z, S.mq, nullptr, S.part,
+                                                                 S.ctrl);
         HIPCHK(hipGetLastError());
         k_fin_update<false><<<1, WG, 0, c.st>>>(c.grid_vec, n, S.part, S.ctrl);
     }
@@ -368,8 +379,7 @@ int cg_iteration_pair(Ctx& c, CgState<double>& S) {
 
 template <typename T>
 int cg_iteration(Ctx& c, CgState<T>& S) {
-    if constexpr (std::is_same<T, double>::value)
-        if (S.pairs) return cg_iteration_pair(c, S);
+    if (S.pairs) return cg_iteration_pair(c, S);
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
@@ -576,7 +586,7 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     S.pairs = S.z != nullptr && !(o.flags & FJ_DIAG_PRECOND) && c.g->n >= PAIR_MIN_N;
     auto pair_start = [&](double stop) -> int {
         if (!S.pairs) return FJ_OK;
-        k_pair_start<<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.r, S.z, S.p, c.mate(), c.pc(), S.part);
+        k_pair_start<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.r, S.z, S.p, c.mate(), c.pc(), S.part);
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
                                        S.ctrl, stop, deflate);
@@ -670,6 +680,8 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
     double rho = snorm;
     double tau = 1e-4;
     const bool deflate = !(o.flags & FJ_ZERO_START);
+    I.pairs = I.z != nullptr && !(o.flags & FJ_DIAG_PRECOND) && n >= PAIR_MIN_N &&
+              c.g->nnz >= static_cast<int64_t>(PAIR_MIN_DEGREE_FP32) * n;
     int inner_total = 0, outer = 0, status = FJ_ERR_NOT_CONVERGED;
     if (z0) {  // start the refinement from z0 and its true residual
         if (int rc = warm_start(c, S, s, lds, z0, ldz, &cc)) return rc;
@@ -693,6 +705,13 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
             HIPCHK(hipGetLastError());
             k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, n, I.part, 1, tau * tau, max_iter - inner_total, 0, I.ctrl,
                                            0.0, 1);
+            HIPCHK(hipGetLastError());
+        }
+        if (I.pairs) {  // the 2x2 block preconditioner, as in the FP64 solve
+            k_pair_start<float><<<c.grid_vec, WG, 0, c.st>>>(n, I.r, I.z, I.p, c.mate(), c.pc(), I.part);
+            HIPCHK(hipGetLastError());
+            k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, n, I.part, 1, tau * tau, max_iter - inner_total, 0, I.ctrl,
+                                           0.0, deflate ? 1 : 0);
             HIPCHK(hipGetLastError());
         }
         if (int rc = cg_run(c, I, 0, max_iter - inner_total, &ci)) return rc;
@@ -763,6 +782,8 @@ int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, d
         CgState<float> S32{reinterpret_cast<float*>(W + wl.x32), reinterpret_cast<float*>(W + wl.r32),
                            reinterpret_cast<float*>(W + wl.p32), reinterpret_cast<float*>(W + wl.q32), &ctrls[1],
                            part};
+        S32.z = reinterpret_cast<float*>(W + wl.z32);
+        S32.mq = reinterpret_cast<float*>(W + wl.mq32);
         status = solve_mixed(c, S64, S32, S, lds, o, want_indices, out, info, warm ? Z : nullptr, ldz);
     } else {
         status = solve_fp64(c, S64, S, lds, o, want_indices, out, info, warm ? Z : nullptr, ldz);

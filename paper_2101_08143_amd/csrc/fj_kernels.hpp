@@ -564,16 +564,17 @@ struct OpCgSpmv {
 
 // q = (I + L) p - shift and p^T q only: with the 2x2 block preconditioner the
 // other two dot products need the partner's q and are formed by k_pair_dots.
+template <typename T>
 struct OpCgSpmvPq {
     using In = NoIn;
-    double* __restrict__ q;
+    T* __restrict__ q;
     double shift;
     double pq = 0.0;
     __device__ In load(int) const { return {}; }
-    __device__ void row(int i, double pi, double lin, double, const In&) {
-        const double qi = pi + lin - shift;
-        q[i] = qi;
-        pq += pi * qi;
+    __device__ void row(int i, T pi, double lin, double, const In&) {
+        const T qt = static_cast<T>(static_cast<double>(pi) + lin - shift);
+        q[i] = qt;
+        pq += static_cast<double>(pi) * static_cast<double>(qt);
     }
 };
 
@@ -972,6 +973,11 @@ constexpr int PAIR_ROUNDS = 4;  // handshake rounds (1: the locally dominant edg
 // (below, the extra launch per iteration costs more than the iterations it
 // saves: 0.54 against 0.44 ms on a 10K-node Barabasi-Albert graph).
 constexpr int PAIR_MIN_N = 65536;
+// The FP32 inner solves of FJ_MIXED use them only when the SpMV's work per
+// node (the mean degree) outweighs the pair pass's fixed work per node: on a
+// 1M-node graph of mean degree 10 they cost more than they saved (2.88
+// against 2.79 ms), on the 4M-node graph of mean degree 30 they save 14 %.
+constexpr int PAIR_MIN_DEGREE_FP32 = 16;
 
 __global__ void __launch_bounds__(WG) k_pair_init(int n, int* __restrict__ mate) {
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) mate[i] = -1;
@@ -1026,28 +1032,32 @@ __global__ void __launch_bounds__(WG) k_pair_coef(int n, const int* __restrict__
     }
 }
 
-__device__ __forceinline__ double pair_apply(int i, const double* __restrict__ v, const int* __restrict__ mate,
+template <typename T>
+__device__ __forceinline__ double pair_apply(int i, const T* __restrict__ v, const int* __restrict__ mate,
                                              const float2* __restrict__ pc) {
     const float2 c = pc[i];
     const int j = mate[i];
-    double y = static_cast<double>(c.x) * v[i];
-    if (j >= 0) y += static_cast<double>(c.y) * v[j];
+    double y = static_cast<double>(c.x) * static_cast<double>(v[i]);
+    if (j >= 0) y += static_cast<double>(c.y) * static_cast<double>(v[j]);
     return y;
 }
 
 // CG start with the block preconditioner, after k_cg_init (and k_cg_shift):
 // z = M^{-1} r, p = z, and the partial sums of rz, rr and sum p in the slots
-// k_fin_init mode 1 reads.
-__global__ void __launch_bounds__(WG) k_pair_start(int n, const double* __restrict__ r, double* __restrict__ z,
-                                                   double* __restrict__ p, const int* __restrict__ mate,
+// k_fin_init mode 1 reads. T: the vector precision (double, or float for the
+// inner solves of FJ_MIXED); sums in double, each value rounded once.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_pair_start(int n, const T* __restrict__ r, T* __restrict__ z,
+                                                   T* __restrict__ p, const int* __restrict__ mate,
                                                    const float2* __restrict__ pc, double* __restrict__ part) {
     __shared__ double red[NWAVE * 3];
     double v[3] = {0.0, 0.0, 0.0};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-        const double zi = pair_apply(i, r, mate, pc);
-        const double ri = r[i];
-        z[i] = zi;
-        p[i] = zi;
+        const T zt = static_cast<T>(pair_apply(i, r, mate, pc));
+        const double zi = static_cast<double>(zt);
+        const double ri = static_cast<double>(r[i]);
+        z[i] = zt;
+        p[i] = zt;
         v[0] += ri * zi;
         v[1] += ri * ri;
         v[2] += zi;
@@ -1066,15 +1076,15 @@ __global__ void __launch_bounds__(WG) k_pair_start(int n, const double* __restri
 
 // CG step with the block preconditioner, part 1: q = (I+L) p - pbar and p^T q
 // (partial slot 0).
-template <typename V>
+template <typename V, typename T>
 __global__ void __launch_bounds__(WG) k_cg_spmv_pq(Csr<V> g, const WinDesc* __restrict__ desc, int K,
-                                                   const double* __restrict__ p, double* __restrict__ q,
+                                                   const T* __restrict__ p, T* __restrict__ q,
                                                    double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ Stage<double, V, OpCgSpmvPq::In> st;
+    __shared__ Stage<T, V, typename OpCgSpmvPq<T>::In> st;
     __shared__ double red[NWAVE * 4];
-    OpCgSpmvPq op{q, ctrl->pbar};
-    my_windows<double, V, AccLin>(g, desc, K, p, op, st, red);
+    OpCgSpmvPq<T> op{q, ctrl->pbar};
+    my_windows<T, V, AccLin>(g, desc, K, p, op, st, red);
     double v[1] = {op.pq};
     block_sum<1>(v, red);
     store_partials<1>(v, part);
@@ -1082,18 +1092,20 @@ __global__ void __launch_bounds__(WG) k_cg_spmv_pq(Csr<V> g, const WinDesc* __re
 
 // Part 2: mq = M^{-1} q (the partner's q is final now), and the partial sums
 // of r^T M^{-1} q = z^T q and q^T M^{-1} q (slots 1 and 2).
-__global__ void __launch_bounds__(WG) k_pair_dots(int n, const double* __restrict__ q, const double* __restrict__ z,
+template <typename T>
+__global__ void __launch_bounds__(WG) k_pair_dots(int n, const T* __restrict__ q, const T* __restrict__ z,
                                                   const int* __restrict__ mate, const float2* __restrict__ pc,
-                                                  double* __restrict__ mq, double* __restrict__ part,
+                                                  T* __restrict__ mq, double* __restrict__ part,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
     __shared__ double red[NWAVE * 2];
     double v[2] = {0.0, 0.0};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-        const double m = pair_apply(i, q, mate, pc);
-        const double qi = q[i];
-        mq[i] = m;
-        v[0] += z[i] * qi;
+        const T mt = static_cast<T>(pair_apply(i, q, mate, pc));
+        const double m = static_cast<double>(mt);
+        const double qi = static_cast<double>(q[i]);
+        mq[i] = mt;
+        v[0] += static_cast<double>(z[i]) * qi;
         v[1] += qi * m;
     }
     block_sum<2>(v, red);
@@ -1135,26 +1147,30 @@ __global__ void __launch_bounds__(WG) k_fin_pair(int G1, int G2, const double* _
 // r by the same recurrence, so no thread reads a partner's r while it
 // changes), p = z + beta p, with the partials of k_cg_update (exact r^T z,
 // r^T r, sum p, and with EST the four index estimates) for k_fin_update.
-template <bool EST>
-__global__ void __launch_bounds__(WG) k_cg_update_pair(int n, double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ p, const double* __restrict__ q,
-                                                       double* __restrict__ z, const double* __restrict__ mq,
+template <typename T, bool EST>
+__global__ void __launch_bounds__(WG) k_cg_update_pair(int n, T* __restrict__ x, T* __restrict__ r,
+                                                       T* __restrict__ p, const T* __restrict__ q,
+                                                       T* __restrict__ z, const T* __restrict__ mq,
                                                        const double* __restrict__ s, double* __restrict__ part,
                                                        const Ctrl* __restrict__ ctrl) {
+    static_assert(!EST || std::is_same<T, double>::value, "estimates are for FP64 vectors");
     if (ctrl->done != RUNNING) return;
     __shared__ double red[NWAVE * 7];
     const double alpha = ctrl->alpha, beta = ctrl->beta, pbar = ctrl->pbar;
     double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-        const double pi = p[i];
-        const double xi = x[i] + alpha * (pi - pbar);
-        const double ri = r[i] - alpha * q[i];
-        const double zi = z[i] - alpha * mq[i];
-        const double pn = zi + beta * pi;
-        x[i] = xi;
-        r[i] = ri;
-        z[i] = zi;
-        p[i] = pn;
+        const double pi = static_cast<double>(p[i]);
+        const T xt = static_cast<T>(static_cast<double>(x[i]) + alpha * (pi - pbar));
+        const T rt = static_cast<T>(static_cast<double>(r[i]) - alpha * static_cast<double>(q[i]));
+        const T zt = static_cast<T>(static_cast<double>(z[i]) - alpha * static_cast<double>(mq[i]));
+        const double zi = static_cast<double>(zt);
+        const T pt = static_cast<T>(zi + beta * pi);
+        x[i] = xt;
+        r[i] = rt;
+        z[i] = zt;
+        p[i] = pt;
+        const double xi = static_cast<double>(xt), ri = static_cast<double>(rt), pn = static_cast<double>(pt);
+        (void)xi;
         v[0] += ri * zi;
         v[1] += ri * ri;
         v[2] += pn;
