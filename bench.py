@@ -329,7 +329,7 @@ def main():
     pairs = g.n >= PAIR_MIN_N
     b_launch = (spmv_pq_bytes if pairs else spmv_bytes)(g.n, g.nnz, val_bytes)
     vt = {0: "Unit", 4: "float", 8: "double"}[val_bytes]
-    spmv_name = f"k_cg_spmv_pq<{vt}>" if pairs else f"k_cg_spmv<{vt}, double>"
+    spmv_name = f"k_cg_spmv_pq<{vt}, double>" if pairs else f"k_cg_spmv<{vt}, double>"
     avg_ms = fp64["ms_spmv"] / max(fp64["n_spmv"], 1)
     work_ms = fp64["ms_spmv"] / max(fp64["iters"], 1)  # launches past convergence return at once
     bytes_per_launch = b_launch * fp64["iters"] / max(fp64["n_spmv"], 1)  # launches after convergence do no work
