@@ -1486,8 +1486,9 @@ int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_byt
         const int gv = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + WG - 1) / WG, 8192));
         k_pair_init<<<gv, WG, 0, st>>>(g->n, mate);
         HIPCHK(hipGetLastError());
+        const int gw = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + NWAVE - 1) / NWAVE, 65536));
         for (int round = 0; round < PAIR_ROUNDS; ++round) {
-            k_pair_propose<Vc><<<gv, WG, 0, st>>>(G, mate, prop, pw);
+            k_pair_propose<Vc><<<gw, WG, 0, st>>>(G, mate, prop, pw);
             HIPCHK(hipGetLastError());
             k_pair_accept<<<gv, WG, 0, st>>>(g->n, prop, mate);
             HIPCHK(hipGetLastError());

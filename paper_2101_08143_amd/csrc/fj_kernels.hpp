@@ -983,18 +983,22 @@ __global__ void __launch_bounds__(WG) k_pair_init(int n, int* __restrict__ mate)
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) mate[i] = -1;
 }
 
+// One wave per row (hub rows hold thousands of entries): lanes scan strided
+// parts of the row, then a wave reduction keeps the heaviest (weight, index).
 template <typename V>
 __global__ void __launch_bounds__(WG) k_pair_propose(Csr<V> g, const int* __restrict__ mate, int* __restrict__ prop,
                                                      float* __restrict__ pw) {
-    for (int i = blockIdx.x * WG + threadIdx.x; i < g.n; i += gridDim.x * WG) {
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * NWAVE;
+    for (int i = blockIdx.x * NWAVE + (threadIdx.x >> 6); i < g.n; i += waves) {
         if (mate[i] >= 0) {  // matched in an earlier round: keeps the weight of its pair's edge in pw
-            prop[i] = -1;
+            if (lane == 0) prop[i] = -1;
             continue;
         }
         int best = -1;
         double bw = -1.0;
         const int e1 = g.row_ptr[i + 1];
-        for (int e = g.row_ptr[i]; e < e1; ++e) {
+        for (int e = g.row_ptr[i] + lane; e < e1; e += 64) {
             const int j = g.col[e];
             if (j == i || mate[j] >= 0) continue;
             const double w = weight_at<V>(g.val, e);
@@ -1003,8 +1007,19 @@ __global__ void __launch_bounds__(WG) k_pair_propose(Csr<V> g, const int* __rest
                 bw = w;
             }
         }
-        prop[i] = best;
-        pw[i] = static_cast<float>(bw);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ow = __shfl_xor(bw, o, 64);
+            const int oj = __shfl_xor(best, o, 64);
+            if (ow > bw || (ow == bw && oj > best)) {
+                best = oj;
+                bw = ow;
+            }
+        }
+        if (lane == 0) {
+            prop[i] = best;
+            pw[i] = static_cast<float>(bw);
+        }
     }
 }
 
