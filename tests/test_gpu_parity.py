@@ -447,14 +447,16 @@ def test_deflated_cg_keeps_the_mean_and_saves_iterations(torch_fj, graphs, name,
     assert its[0] <= its[fj.FJ_ZERO_START] - 2, its
 
 
+@pytest.mark.parametrize("name", ["cl50k_f32", "cl100k_unit"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_warm_start(torch_fj, graphs, precision):
+def test_warm_start(torch_fj, graphs, precision, name):
     """FJ_WARM_START: from the converged z no iteration runs and z is returned
     as it was; from a perturbed z the solve converges to the oracle's z in
-    fewer iterations than from zero; k > 1 is refused."""
+    fewer iterations than from zero; k > 1 is refused. (cl100k_unit: with
+    the 2x2 block preconditioner.)"""
     torch, fj = torch_fj
-    g, G = graphs["cl50k_f32"]
-    say(f"warm start {precision}")
+    g, G = graphs[name]
+    say(f"warm start {name} {precision}")
     prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
     s = np.random.default_rng(41).random(g.n)
     sd = torch.from_numpy(s).to("cuda:0")
@@ -597,16 +599,17 @@ def test_concurrent_calls_on_distinct_workspaces(torch_fj, graphs):
         assert len(got[j]) == 3 and all(v == ref[j] for v in got[j]), j
 
 
+@pytest.mark.parametrize("name", ["cl50k_f32", "cl100k_unit"])
 @pytest.mark.parametrize("k", [1, 4])
 @pytest.mark.parametrize("zero_start", [False, True])
-def test_restart_passes_certify(torch_fj, graphs, k, zero_start):
+def test_restart_passes_certify(torch_fj, graphs, k, zero_start, name):
     """A loose first-pass residual target (rtol 1e-3) cannot certify 1e-6, so
     the solve restarts from the true residual with a tighter target (a second
-    pass, deflated or plain) and then certifies; the indices match the
-    oracle."""
+    pass, deflated or plain; on cl100k_unit with one vector, block
+    preconditioned) and then certifies; the indices match the oracle."""
     torch, fj = torch_fj
-    g, G = graphs["cl50k_f32"]
-    say(f"restart passes k={k} zero_start={zero_start}")
+    g, G = graphs[name]
+    say(f"restart passes {name} k={k} zero_start={zero_start}")
     S = _block(g.n, k, 700 + k)
     Sd = torch.from_numpy(S if k > 1 else S[:, 0].copy()).to("cuda:0")
     flags = fj.FJ_ZERO_START if zero_start else 0
