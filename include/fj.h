@@ -141,9 +141,10 @@ size_t fj_plan_bytes(const fj_csr *g);
 
 /*
  * One-time set-up of the operator I + L for graph g (Section 2.1): the
- * Jacobi preconditioner diag(I + D)^{-1} and the row-window partition that
- * balances the sparse passes. Writes `plan` (device, >= fj_plan_bytes, 256-byte
- * aligned). Asynchronous on `stream` unless opts->flags has FJ_VALIDATE_GRAPH,
+ * Jacobi preconditioner diag(I + D)^{-1}, the heavy-edge matching and the
+ * coefficients of the 2x2 block preconditioner (see FJ_DIAG_PRECOND), and the
+ * row-window partition that balances the sparse passes. Writes `plan`
+ * (device, >= fj_plan_bytes, 256-byte aligned). Asynchronous on `stream` unless opts->flags has FJ_VALIDATE_GRAPH,
  * which also checks the CSR contract and synchronises. opts may be NULL.
  */
 int fj_prepare(const fj_csr *g, const fj_opts *opts, void *plan, size_t plan_bytes, void *stream);
