@@ -222,6 +222,23 @@ def test_degenerate_cases(torch_fj, graphs):
     assert abs(vals[0]["polarization"] - sb @ sb) <= 1e-12 * (sb @ sb)
     assert abs(vals[0]["controversy"] - s @ s) <= 1e-12 * (s @ s)
     assert vals[0]["disagreement"] == 0.0 and vals[0]["internal_conflict"] == 0.0
+    # edgeless and large enough for the block preconditioner: no pairs, M = I
+    gb = W.csr_from_edges(70_000, np.zeros((0, 2), dtype=np.int64))
+    say("edgeless 70000")
+    Gb = fj.Graph.from_csr(gb, device=dev)
+    s = W.opinions("uniform", gb.n, 4)
+    z, _, rc = fj.fj_solve(Gb, torch.from_numpy(s).to(dev))
+    assert rc == fj.FJ_OK and np.abs(z.cpu().numpy() - s).max() <= 1e-15
+    # a star larger than the threshold: the hub pairs with one leaf, the other leaves stay single
+    gs = W.csr_from_edges(70_001, [(0, j) for j in range(1, 70_001)])
+    say("star 70001")
+    Gs = fj.Graph.from_csr(gs, device=dev, validate=True)
+    s = W.opinions("uniform", gs.n, 5)
+    vals, infos, rc = fj.fj_indices(Gs, torch.from_numpy(s).to(dev), check=False)
+    ref, _, _ = O.indices(gs, s)
+    assert rc == fj.FJ_OK
+    for nm in NAMES:
+        assert abs(vals[0][nm] - ref[nm]) <= EPS * abs(ref[nm]), nm
     # one node
     g1 = W.csr_from_edges(1, np.zeros((0, 2), dtype=np.int64))
     say("single node")
