@@ -577,16 +577,18 @@ def test_full_size_batched_k64(torch_fj, precision):
 
 
 def test_concurrent_calls_on_distinct_workspaces(torch_fj, graphs):
-    """The ABI is thread-safe for calls that use distinct workspaces: four host
-    threads, each with its own stream and workspaces, run single, batched and
-    mixed-precision index solves on shared graphs at the same time; every
-    result is bitwise the one the same call gives alone."""
+    """The ABI is thread-safe for calls that use distinct workspaces: six host
+    threads, each with its own stream and workspaces, run single (two of them
+    block preconditioned on one shared plan), batched and mixed-precision
+    index solves on shared graphs at the same time; every result is bitwise
+    the one the same call gives alone."""
     import threading
     torch, fj = torch_fj
     say("concurrent calls")
     jobs = []
     for t, (name, k, prec) in enumerate([("cl50k_f32", 1, fj.FJ_FP64), ("cl100k_unit", 4, fj.FJ_FP64),
-                                         ("ba3000", 1, fj.FJ_MIXED), ("cl50k_f32", 8, fj.FJ_MIXED)]):
+                                         ("ba3000", 1, fj.FJ_MIXED), ("cl50k_f32", 8, fj.FJ_MIXED),
+                                         ("cl100k_unit", 1, fj.FJ_FP64), ("cl100k_unit", 1, fj.FJ_MIXED)]):
         g, G = graphs[name]
         S = np.random.default_rng(60 + t).random((g.n, k))
         Sd = torch.from_numpy(S if k > 1 else S[:, 0].copy()).to("cuda:0")
