@@ -252,7 +252,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cl4m", choices=sorted(WORKLOAD_META))
     ap.add_argument("--eps", type=float, default=1e-6)
-    ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-solves", type=int, default=8,
+                    help="oracle solves timed for cpu_baseline (0 = skip; 8 take about 12 s on 16 host cores)")
     ap.add_argument("--batched-steps", type=int, default=3,
                     help="timed k=64 batched calls on the 1M-node graph (0 = skip that form)")
     ap.add_argument("--two-solve-steps", type=int, default=3,
