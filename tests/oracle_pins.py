@@ -180,7 +180,12 @@ def pin_circulant(indices_fn, solve_fn, circulant, sizes=((997, 0.7), (1000, Non
         zf = circulant.cycle_equilibrium(s, ww)
         if not np.allclose(z, zf, rtol=0, atol=1e-11):
             raise AssertionError(f"cycle n={n} equilibrium max err {np.abs(z - zf).max()}")
-        _close_dict(indices_fn(g, s), circulant.cycle_indices(s, ww), 1e-9, 0, f"cycle{n}")
+        v = indices_fn(g, s)
+        want = circulant.cycle_indices(s, ww)
+        _close_dict(v, want, 1e-9, 0, f"cycle{n}")
+        if "lz_norm2" in v:
+            _close(v["lz_norm2"], want["internal_conflict"], 1e-9, what=f"cycle{n} ||Lz||^2")
+            _close(v["zlz"], want["disagreement"], 1e-9, what=f"cycle{n} z^T L z")
     for a, b, w in torus:
         g = W.torus_graph(a, b, w)
         s = rng.random(a * b)
@@ -188,7 +193,12 @@ def pin_circulant(indices_fn, solve_fn, circulant, sizes=((997, 0.7), (1000, Non
         zf = circulant.torus_equilibrium(s, a, b, w)
         if not np.allclose(z, zf, rtol=0, atol=1e-11):
             raise AssertionError(f"torus {a}x{b} equilibrium max err {np.abs(z - zf).max()}")
-        _close_dict(indices_fn(g, s), circulant.torus_indices(s, a, b, w), 1e-9, 0, "torus")
+        v = indices_fn(g, s)
+        want = circulant.torus_indices(s, a, b, w)
+        _close_dict(v, want, 1e-9, 0, "torus")
+        if "lz_norm2" in v:
+            _close(v["lz_norm2"], want["internal_conflict"], 1e-9, what="torus ||Lz||^2")
+            _close(v["zlz"], want["disagreement"], 1e-9, what="torus z^T L z")
 
 
 def _permuted(g, perm):
@@ -218,6 +228,9 @@ def pin_identities(indices_fn, solve_fn):
                    what="P = C - n mean(s)^2")
             if z.min() < s.min() - 1e-12 or z.max() > s.max() + 1e-12:
                 raise AssertionError("z leaves [min s, max s]")
+            if "lz_norm2" in v:  # Lemma 4.1 and Proposition 1 forms, where the oracle reports them
+                _close(v["lz_norm2"], v["internal_conflict"], 1e-9, 1e-14 * ss, "||Lz||^2 = C_I")
+                _close(v["zlz"], v["disagreement"], 1e-9, 1e-14 * ss, "z^T L z = D")
         perm = np.random.default_rng(5).permutation(g.n)
         gp = _permuted(g, perm)
         sp = np.empty_like(s)
@@ -249,3 +262,143 @@ def pin_p5_sparse(solve_fn):
         z = solve_fn(g, np.eye(5)[:, j])
         if not np.allclose(z * total, M[:, j], rtol=0, atol=1e-10):
             raise AssertionError(f"P5 solve for s = e_{j + 1} differs from the printed Omega")
+
+
+# ------------------------------------------------ the oracle's certificate
+
+
+def _closed_form_cases():
+    """(name, graph, s, exact z, exact indices) for graphs whose equilibrium has
+    a closed form: no solver is involved, so these are the truth."""
+    rng = np.random.default_rng(17)
+    cases = []
+    for w in (0.001, 0.5, 2.5):  # single edge of weight w
+        s = np.array([0.9, 0.2])
+        dlt = s[0] - s[1]
+        k = 1.0 + 2.0 * w
+        z = np.array([(s.sum() + dlt / k) / 2, (s.sum() - dlt / k) / 2])
+        want = dict(internal_conflict=2 * w * w * dlt * dlt / k ** 2, disagreement=w * dlt * dlt / k ** 2,
+                    polarization=dlt * dlt / (2 * k ** 2), controversy=float(z @ z), dc_index=float(s @ z))
+        cases.append((f"edge w={w}", W.csr_from_edges(2, [(0, 1)], [w]), s, z, want))
+    for n, w in ((9, 1.0), (12, 0.75)):  # K_n: z = mean(s) 1 + sbar / (1 + w n)
+        s = rng.random(n)
+        mu = s.mean()
+        sb = s - mu
+        k = 1.0 + w * n
+        z = mu + sb / k
+        sb2 = float(sb @ sb)
+        want = dict(internal_conflict=(w * n) ** 2 * sb2 / k ** 2, disagreement=w * n * sb2 / k ** 2,
+                    polarization=sb2 / k ** 2, controversy=n * mu * mu + sb2 / k ** 2,
+                    dc_index=n * mu * mu + sb2 / k)
+        cases.append((f"K_{n}", W.complete_graph(n, None if w == 1.0 else w), s, z, want))
+    n = 7  # edgeless: z = s
+    s = rng.random(n)
+    sb = s - s.mean()
+    cases.append(("edgeless", W.csr_from_edges(n, np.zeros((0, 2), dtype=np.int64)), s, s.copy(),
+                  dict(internal_conflict=0.0, disagreement=0.0, polarization=float(sb @ sb),
+                       controversy=float(s @ s), dc_index=float(s @ s))))
+    g = W.barabasi_albert(300, 3, 8)  # constant opinions: z = s
+    s = np.full(g.n, 0.37)
+    cases.append(("constant s", g, s, s.copy(),
+                  dict(internal_conflict=0.0, disagreement=0.0, polarization=0.0,
+                       controversy=g.n * 0.37 ** 2, dc_index=g.n * 0.37 ** 2)))
+    return cases
+
+
+def _perturbations(z, s, rng):
+    u = rng.standard_normal(z.shape[0])
+    u /= np.linalg.norm(u)
+    sb = s - s.mean()
+    dirs = [z, -z, np.ones_like(z), np.linalg.norm(z) * u]
+    if np.linalg.norm(sb) > 0:
+        dirs += [sb, -sb]
+    for t in (1e-2, 1e-4, 1e-7):
+        for d in dirs:
+            yield t, t * d
+
+
+def pin_error_bounds(sparse):
+    """The oracle's certificate (reading of Algorithm 1's guarantee through the
+    Section 4 ordering I <= I + L) at perturbed points z~ = z + e of graphs
+    with a closed-form equilibrium, where the true error of every index is
+    known: each bound is at least the actual relative error, certifies
+    nothing (>= 1/2) where the true index is 0, and is within a stated
+    factor of the actual error where the perturbation attains the bound."""
+    rng = np.random.default_rng(23)
+    for name, g, s, z, want in _closed_form_cases():
+        for t, e in _perturbations(z, s, rng):
+            vals = sparse.indices_at(g, s, z + e)
+            bnd = sparse.error_bounds(vals)
+            for k in NAMES:
+                if want[k] == 0.0:
+                    # no relative bound exists; any value >= 1/2 certifies nothing for an
+                    # admissible eps (Algorithm 1 takes eps in (0, 1/2)). At the boundary
+                    # sqrt(X~) = rho rounding may give a huge finite value instead of inf.
+                    if not bnd[k] >= 0.5:
+                        raise AssertionError(f"{name}: relative bound {bnd[k]} for a zero {k}")
+                    continue
+                actual = abs(vals[k] - want[k]) / want[k]
+                if not actual <= bnd[k] * (1 + 1e-9) + 1e-13:
+                    raise AssertionError(f"{name} t={t}: {k} error {actual} above its bound {bnd[k]}")
+    # Perturbations that attain the bound to first order (factor 1 + O(t)).
+    t = 1e-4
+
+    def ratio(g, s, z, zt, want, k):
+        vals = sparse.indices_at(g, s, zt)
+        return sparse.error_bounds(vals)[k] / (abs(vals[k] - want[k]) / want[k])
+
+    cases = {c[0]: c[1:] for c in _closed_form_cases()}
+    g, s, z, want = cases["constant s"]
+    # e = -t z is constant, (I + L) e = e: rho = t ||z|| = |sqrt(C) - sqrt(C~)|
+    for k, hi in (("controversy", 1.001), ("dc_index", 1.001)):
+        r = ratio(g, s, z, (1 - t) * z, want, k)
+        if not 1.0 <= r <= hi:
+            raise AssertionError(f"constant s: {k} bound / error = {r}, expected in [1, {hi}]")
+    g, s, z, want = cases["edgeless"]  # L = 0: e = t sbar gives rho = sqrt(P~) - sqrt(P)
+    r = ratio(g, s, z, z + t * (s - s.mean()), want, "polarization")
+    if not 1.0 <= r <= 1.001:
+        raise AssertionError(f"edgeless: polarization bound / error = {r}")
+    # single edge: e along z - s (eigenvalue 2w of L): rho = (1 + 2w) |sqrt(C_I~) - sqrt(C_I)|,
+    # and at w = 1/2 the disagreement form sees half of rho (hence a factor 2 at best)
+    g, s, z, want = cases["edge w=0.001"]
+    r = ratio(g, s, z, z + t * (z - s), want, "internal_conflict")
+    if not 1.0 <= r <= 1.01:
+        raise AssertionError(f"edge: internal conflict bound / error = {r}")
+    g, s, z, want = cases["edge w=0.5"]
+    r = ratio(g, s, z, z + t * np.array([1.0, -1.0]), want, "disagreement")
+    if not 1.0 <= r <= 2.01:
+        raise AssertionError(f"edge: disagreement bound / error = {r}")
+
+
+def pin_certified_flag(sparse):
+    """indices() certifies only when every index meets the requested bound:
+    nearly constant opinions make P, D and C_I tiny, so a residual that
+    certifies C and I_dc to 1e-9 does not certify them."""
+    g = W.barabasi_albert(400, 3, 51)
+    s = 0.5 + 1e-6 * W.opinions("uniform", g.n, 52)
+    _, _, loose = sparse.indices(g, s, rtol=1e-9, certify=1e-9)
+    if loose["certified"]:
+        raise AssertionError(f"certified although some bound exceeds 1e-9: {loose['bounds']}")
+    if not min(loose["bounds"].values()) <= 1e-9:
+        raise AssertionError("case does not separate 'every index' from 'some index'")
+    _, _, tight = sparse.indices(g, W.opinions("uniform", g.n, 52))
+    if not tight["certified"]:
+        raise AssertionError(f"not certified at the oracle tolerance: {tight['bounds']}")
+
+
+def pin_sparse_forms(indices_at_fn, solve_fn):
+    """Lemma 4.1 (C_I = ||L z||^2) and Proposition 1 (D = z^T L z) against the
+    definitions: at the closed-form equilibria exactly, and at the solved z of
+    larger graphs to within the solve's residual."""
+    for name, g, s, z, want in _closed_form_cases():
+        v = indices_at_fn(g, s, z)
+        scale = float(s @ s)
+        _close(v["lz_norm2"], want["internal_conflict"], 1e-11, 1e-15 * scale, f"{name} ||Lz||^2")
+        _close(v["zlz"], want["disagreement"], 1e-11, 1e-15 * scale, f"{name} z^T L z")
+    graphs = [W.barabasi_albert(500, 3, 21), W.random_graph(200, 0.05, 22, weighted=True),
+              W.chung_lu(3000, 2.3, 8.0, 23, weighted=True)]
+    for g in graphs:
+        s = W.opinions("exp", g.n, 33)
+        v = indices_at_fn(g, s, solve_fn(g, s))
+        _close(v["lz_norm2"], v["internal_conflict"], 1e-9, what="Lemma 4.1 ||Lz||^2 = C_I")
+        _close(v["zlz"], v["disagreement"], 1e-9, what="Prop. 1 z^T L z = D")

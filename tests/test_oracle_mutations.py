@@ -60,6 +60,10 @@ C_MUTANTS = {
     "dc index uses s twice": ("nadd(&idc, s[i] * z[i]);", "nadd(&idc, s[i] * s[i]);"),
     "fj update drops self weight": ("nadd(&den, 1.0);", ";"),
     "fj update drops internal opinion": ("nadd(&num, s[i]);", ";"),
+    "Lemma 4.1 form drops the degree": ("lz[i] = nval(deg) * z[i] - nval(az);", "lz[i] = z[i] - nval(az);"),
+    "Lemma 4.1 norm not squared": ("nadd(&l2, lz[i] * lz[i]);", "nadd(&l2, lz[i]);"),
+    "Prop. 1 form uses s": ("nadd(&zlz, z[i] * lz[i]);", "nadd(&zlz, s[i] * lz[i]);"),
+    "residual norm squared": ("return sqrt(dot(n, r, r));", "return dot(n, r, r);"),
 }
 
 
@@ -83,7 +87,10 @@ def _sparse_pins():
             lambda: P.pin_closed_forms(ind),
             lambda: P.pin_circulant(ind, sol, circulant),
             lambda: P.pin_identities(ind, sol),
-            lambda: P.pin_fj_dynamics(fj, sol)]
+            lambda: P.pin_fj_dynamics(fj, sol),
+            lambda: P.pin_sparse_forms(sparse.indices_at, sol),
+            lambda: P.pin_error_bounds(sparse),
+            lambda: P.pin_certified_flag(sparse)]
 
 
 def test_unmutated_c_oracle_passes_every_pin(tmp_path):
@@ -169,3 +176,39 @@ def test_circulant_mutant_is_caught(name):
     old, new = CIRCULANT_MUTANTS[name]
     Cm = _module_from(_mutate(circulant.__file__, old, new), "circulant_mutant")
     assert _some_pin_fails([lambda: P.pin_circulant(dense.indices, dense.equilibrium, Cm)])
+
+
+# ------------------------------------------------ the oracle's certificate (sparse.py)
+
+# Not listed, because each still bounds the error:
+#  - dropping rho^2 from the numerator: rho (2 rx - rho) / (rx - rho)^2 is the exact worst
+#    case of |X - X~| / X given |sqrt(X) - sqrt(X~)| <= rho (the oracle's form is looser);
+#  - ||z~|| rho instead of (||z~|| + rho) rho for I_dc: the difference is of order rho^2,
+#    and the relative form a / (I_dc~ - a) over-covers it by more than that.
+SPARSE_MUTANTS = {
+    "bound denominator (rx + rho)^2": ("/ (rx - rho) ** 2", "/ (rx + rho) ** 2"),
+    "bound drops the factor 2": ("rho * (2 * rx + rho)", "rho * (rx + rho)"),
+    "residual norm squared": ('rho = vals["residual_norm"]', 'rho = vals["residual_norm"] ** 2'),
+    "certified when any index meets": ("all(b <= certify", "any(b <= certify"),
+}
+
+
+def _sparse_module_from(src):
+    mod = types.ModuleType("sparse_mutant")
+    mod.__dict__["__file__"] = sparse.__file__  # same C library
+    exec(compile(src, "sparse_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+def test_unmutated_sparse_module_passes_certificate_pins():
+    S = _sparse_module_from(open(sparse.__file__).read())
+    assert not _some_pin_fails([lambda: P.pin_error_bounds(S), lambda: P.pin_certified_flag(S)])
+
+
+@pytest.mark.parametrize("name", sorted(SPARSE_MUTANTS))
+def test_sparse_certificate_mutant_is_caught(name):
+    old, new = SPARSE_MUTANTS[name]
+    S = _sparse_module_from(_mutate(sparse.__file__, old, new))
+    with np.errstate(all="ignore"):
+        assert _some_pin_fails([lambda: P.pin_error_bounds(S), lambda: P.pin_certified_flag(S)]), \
+            f"no pin caught: {name}"

@@ -118,3 +118,15 @@ def test_oracle_certifies_itself_chung_lu():
     s = W.opinions("exp", g.n, 2003)
     vals, z, info = sparse.indices(g, s)
     assert info["status"] == 0 and info["certified"], info
+
+
+def test_error_bounds_against_known_errors():
+    P.pin_error_bounds(sparse)
+
+
+def test_certified_flag():
+    P.pin_certified_flag(sparse)
+
+
+def test_sparse_lemma41_prop1_forms():
+    P.pin_sparse_forms(sparse.indices_at, sparse_solve)
