@@ -22,7 +22,10 @@
  *     memory (fj_indices, fj_solve's info) synchronise with the stream before
  *     returning.
  *   - Every function returns an int status (FJ_OK = 0 on success). No C++
- *     exception crosses the ABI and the library never aborts the process.
+ *     exception crosses the ABI and the library never aborts the process: a
+ *     failed host allocation inside the library returns FJ_ERR_HOST_MEMORY,
+ *     any other C++ exception FJ_ERR_INTERNAL (fj_last_error has the detail).
+ *     After either from a fj_server_* call, destroy the server.
  *   - Calls are thread-safe when concurrent calls use distinct workspaces.
  *     A plan may be shared by concurrent calls once fj_prepare has completed.
  *   - Per calling thread and device the library keeps a small pinned host
@@ -46,9 +49,12 @@ extern "C" {
 #define FJ_ERR_WORKSPACE      4  /* plan or workspace smaller than the queried size, or misaligned */
 #define FJ_ERR_NOT_CONVERGED  5  /* max_iter reached; results and bounds are still written */
 #define FJ_ERR_BREAKDOWN      6  /* CG breakdown (p^T (I+L) p <= 0 or not finite) */
-#define FJ_ERR_UNCERTIFIABLE  7  /* an index is too close to 0 for a relative bound; bounds are written */
+#define FJ_ERR_UNCERTIFIABLE  7  /* an index is too close to 0 for a relative bound (bound[] = inf for it);
+                                    the indices, residual_norm and the finite abs_bound[] are written */
 #define FJ_ERR_HIP            8  /* a HIP runtime call failed */
 #define FJ_ERR_CANCELLED      9  /* the request was withdrawn with fj_server_cancel */
+#define FJ_ERR_HOST_MEMORY   10  /* a host allocation inside the library failed (std::bad_alloc) */
+#define FJ_ERR_INTERNAL      11  /* any other C++ exception inside the library (a bug) */
 
 /* ---- graph -------------------------------------------------------------- */
 #define FJ_VAL_UNIT 0  /* every edge has weight 1; val must be NULL */
@@ -125,6 +131,13 @@ typedef struct fj_info {
     double ms_spmv;        /* FJ_PROFILE: total milliseconds inside the CG SpMV kernel */
     int32_t n_spmv;        /* FJ_PROFILE: number of CG SpMV launches timed */
     int32_t reserved;
+    double residual_norm;  /* rho = ||s - (I+L) z||_2, the true FP64 residual the bounds are built from */
+    double abs_bound[5];   /* |X - X~| <= abs_bound[i] for each index X (order of fj_indices_t), from the
+                              same certificate as bound[] (Section 4: I <= I + L, so the error
+                              e = (I+L)^{-1} r has ||e||, ||L e||, ||e - mean(e) 1|| <= rho and
+                              ||W^{1/2} B e|| <= rho / 2): rho_X (2 sqrt(X~) + rho_X) for the four squared
+                              norms, (||z~|| + rho) rho for s^T z. Always finite: the error information
+                              for an index too close to 0 for a relative bound (FJ_ERR_UNCERTIFIABLE) */
 } fj_info;
 
 /* ---- entry points ------------------------------------------------------- */
@@ -284,16 +297,23 @@ int fj_server_create(const fj_server_opts *opts, fj_server **out);
 /* Waits for all device work of the server, then frees its host state and streams. */
 int fj_server_destroy(fj_server *srv);
 
-/* Register a prepared graph (fj_prepare) that stays resident; *graph_id receives its id. */
-int fj_server_add_graph(fj_server *srv, const fj_csr *g, const void *plan, int32_t *graph_id);
+/*
+ * Register a prepared graph (fj_prepare) that stays resident; *graph_id
+ * receives its id. `stream` is the stream on which the caller produced the
+ * graph and its plan (NULL: the default stream): the server's work on this
+ * graph is ordered after the work queued on it so far.
+ */
+int fj_server_add_graph(fj_server *srv, const fj_csr *g, const void *plan, int32_t *graph_id, void *stream);
 
 /*
  * Queue a request: k opinion vectors S (device, node-major, leading dimension
  * lds >= k, caller-owned until the request completes). out and info are host
  * arrays of k entries filled when the request completes (info may be NULL).
+ * `stream` is the stream on which S was produced (NULL: the default stream):
+ * the server reads S only after the work queued on it so far.
  */
 int fj_server_submit(fj_server *srv, int32_t graph_id, int32_t k, const double *S, int64_t lds,
-                     fj_indices_t *out, fj_info *info, uint64_t *request_id);
+                     fj_indices_t *out, fj_info *info, uint64_t *request_id, void *stream);
 
 /* One non-blocking scheduling round; *busy_blocks = blocks with work in flight. */
 int fj_server_step(fj_server *srv, int32_t *busy_blocks);

@@ -20,10 +20,13 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <utility>
 #include <vector>
 
 #include "../../include/fj.h"
+#include "fj_guard.hpp"
 #include "fj_kernels.hpp"
 #include "fj_batched.hpp"
 
@@ -37,8 +40,6 @@ constexpr int FIRST_CHUNK = 6;
 constexpr int MAX_PASSES = 5;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-
-thread_local char g_last_error[256] = "";
 
 void set_error(const char* what, hipError_t e) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
@@ -419,6 +420,27 @@ int cg_iteration(Ctx& c, CgState<T>& S) {
     return FJ_OK;
 }
 
+// Chunks of iterations in flight, each with its control-block slot. A
+// completed chunk queues at most one more, so at most two are pending; the
+// ring holds NSLOT (no host allocation on the solve path).
+struct Pending {
+    int q[NSLOT] = {};
+    int head = 0, count = 0;
+    bool empty() const { return count == 0; }
+    int front() const { return q[head]; }
+    int back() const { return q[(head + count - 1) % NSLOT]; }
+    void pop_front() {
+        head = (head + 1) % NSLOT;
+        --count;
+    }
+    bool push_back(int v) {
+        if (count == NSLOT) return false;
+        q[(head + count) % NSLOT] = v;
+        ++count;
+        return true;
+    }
+};
+
 // Absolute iteration count at which rr is expected to reach tol2, from the
 // geometric rate of the last few iterations.
 int predict(const Ctrl& c, int start) {
@@ -439,7 +461,7 @@ template <typename T>
 int cg_run(Ctx& c, CgState<T>& S, int start, int max_iter, Ctrl* out) {
     int queued = start;
     int slot_next = 0;
-    std::deque<int> pending;
+    Pending pending;
     auto enqueue = [&](int cnt) -> int {
         for (int t = 0; t < cnt; ++t)
             if (int rc = cg_iteration(c, S)) return rc;
@@ -447,7 +469,7 @@ int cg_run(Ctx& c, CgState<T>& S, int start, int max_iter, Ctrl* out) {
         const int sl = slot_next++ % NSLOT;
         HIPCHK(hipMemcpyAsync(c.hs->slot(sl), S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipEventRecord(c.hs->ev[sl], c.st));
-        pending.push_back(sl);
+        if (!pending.push_back(sl)) return FJ_ERR_INTERNAL;
         return FJ_OK;
     };
     for (int k = 0; k < 2 && queued < max_iter; ++k)
@@ -524,6 +546,20 @@ int stalled_status(const Ctrl& c, bool want_indices, unsigned which = ALL_INDICE
     return (want_indices && any_inf) ? FJ_ERR_UNCERTIFIABLE : FJ_ERR_NOT_CONVERGED;
 }
 
+// Absolute error bound of each index from the same certificate as the
+// relative bounds: |sqrt(X) - sqrt(X~)| <= rho_X gives
+// |X - X~| <= rho_X (2 sqrt(X~) + rho_X), and |s^T e| <= (||z~|| + rho) rho;
+// finite even where X~ is too close to 0 for a relative bound.
+void abs_bounds(const Ctrl& c, double* ab) {
+    const double rho = c.res[5];
+    const double rh[4] = {rho, 0.5 * rho, rho, rho};
+    for (int i = 0; i < 4; ++i) {
+        const double rx = std::sqrt(std::max(c.res[i], 0.0));
+        ab[i] = rh[i] * (2.0 * rx + rh[i]) + 1e-13 * std::fabs(c.res[i]);
+    }
+    ab[4] = (std::sqrt(std::max(c.res[3], 0.0)) + rho) * rho + 1e-13 * std::fabs(c.res[4]);
+}
+
 void fill_outputs(const Ctrl& c, int status, int passes, int outer, fj_indices_t* out, fj_info* info) {
     if (out) {
         out->internal_conflict = c.res[0];
@@ -538,7 +574,9 @@ void fill_outputs(const Ctrl& c, int status, int passes, int outer, fj_indices_t
         info->passes = passes;
         info->outer_iters = outer;
         info->rel_residual = c.res[6] > 0.0 ? c.res[5] / c.res[6] : 0.0;
+        info->residual_norm = c.res[5];
         for (int i = 0; i < 5; ++i) info->bound[i] = c.bound[i];
+        abs_bounds(c, info->abs_bound);
     }
 }
 
@@ -1049,7 +1087,7 @@ struct Batched {
             return FJ_OK;
         }
         int queued = 0, slot_next = 0;
-        std::deque<int> pending;
+        Pending pending;
         auto enqueue = [&](int cnt) -> int {
             for (int t = 0; t < cnt; ++t)
                 if (int rc = iteration(S)) return rc;
@@ -1057,7 +1095,7 @@ struct Batched {
             const int sl = slot_next++ % NSLOT;
             HIPCHK(hipMemcpyAsync(c.hs->slot(sl), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
             HIPCHK(hipEventRecord(c.hs->ev[sl], c.st));
-            pending.push_back(sl);
+            if (!pending.push_back(sl)) return FJ_ERR_INTERNAL;
             return FJ_OK;
         };
         for (int t = 0; t < 2 && queued < budget; ++t)
@@ -1336,6 +1374,15 @@ int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t ld
             info[0].bound[2] = b.bound[3];
             info[0].bound[3] = a.bound[3];
             info[0].bound[4] = std::max(b.bound[1], a.bound[3]);  // a sum of eps-approximations
+            info[0].residual_norm = std::max(a.res[5], b.res[5]);
+            double aa[5], ab[5];
+            abs_bounds(a, aa);
+            abs_bounds(b, ab);
+            info[0].abs_bound[0] = aa[0];
+            info[0].abs_bound[1] = ab[1];
+            info[0].abs_bound[2] = ab[3];
+            info[0].abs_bound[3] = aa[3];
+            info[0].abs_bound[4] = ab[1] + aa[3];
         }
         worst = st;
         if (Z) {
@@ -1419,6 +1466,8 @@ const char* fj_status_string(int status) {
         case FJ_ERR_UNCERTIFIABLE: return "an index is too close to zero to certify a relative error";
         case FJ_ERR_HIP: return "HIP runtime error";
         case FJ_ERR_CANCELLED: return "request cancelled";
+        case FJ_ERR_HOST_MEMORY: return "host memory allocation failed";
+        case FJ_ERR_INTERNAL: return "internal error (unexpected C++ exception)";
         default: return "unknown status";
     }
 }
@@ -1436,84 +1485,88 @@ size_t fj_workspace_bytes(const fj_csr* g, int32_t k, const fj_opts* opts) {
 }
 
 int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_bytes, void* stream) {
-    if (int rc = check_graph_args(g)) return rc;
-    const PlanLayout pl = plan_layout(g);
-    if (!plan || !aligned(plan) || plan_bytes < pl.total) return FJ_ERR_WORKSPACE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    char* P = static_cast<char*>(plan);
-    int* blk_row = reinterpret_cast<int*>(P + pl.blk_row);
-    WinDesc* desc = reinterpret_cast<WinDesc*>(P + pl.desc);
-    float* minv = reinterpret_cast<float*>(P + pl.minv);
-    int* flags = reinterpret_cast<int*>(P + pl.flags);
-    if (g->n == 0) return FJ_OK;
-    if (opts && (opts->flags & FJ_VALIDATE_GRAPH)) {
-        HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), st));
-        int rc = with_graph(g, [&](auto G) -> int {
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        const PlanLayout pl = plan_layout(g);
+        if (!plan || !aligned(plan) || plan_bytes < pl.total) return FJ_ERR_WORKSPACE;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        char* P = static_cast<char*>(plan);
+        int* blk_row = reinterpret_cast<int*>(P + pl.blk_row);
+        WinDesc* desc = reinterpret_cast<WinDesc*>(P + pl.desc);
+        float* minv = reinterpret_cast<float*>(P + pl.minv);
+        int* flags = reinterpret_cast<int*>(P + pl.flags);
+        if (g->n == 0) return FJ_OK;
+        if (opts && (opts->flags & FJ_VALIDATE_GRAPH)) {
+            HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), st));
+            int rc = with_graph(g, [&](auto G) -> int {
+                using Vc = typename decltype(G)::value_type;
+                const int64_t units = (std::max<int64_t>(g->nnz, g->n + 1) + WG - 1) / WG;
+                const int grid = static_cast<int>(std::min<int64_t>(units, 8192));
+                k_validate<Vc><<<grid, WG, 0, st>>>(G, g->nnz, flags);
+                HIPCHK(hipGetLastError());
+                return FJ_OK;
+            });
+            if (rc) return rc;
+            int h = 0;
+            HIPCHK(hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (h != 0) {
+                std::snprintf(g_last_error, sizeof g_last_error, "CSR contract violated (flags 0x%x)", h);
+                return FJ_ERR_INVALID_GRAPH;
+            }
+        }
+        {
+            const int grid = static_cast<int>(std::min<int64_t>((pl.K + 1 + WG - 1) / WG, 4096));
+            k_windows<<<grid, WG, 0, st>>>(g->n, g->row_ptr, pl.K, blk_row);
+            HIPCHK(hipGetLastError());
+            k_window_desc<<<grid, WG, 0, st>>>(g->n, g->row_ptr, pl.K, blk_row, desc);
+            HIPCHK(hipGetLastError());
+        }
+        return with_graph(g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
-            const int64_t units = (std::max<int64_t>(g->nnz, g->n + 1) + WG - 1) / WG;
-            const int grid = static_cast<int>(std::min<int64_t>(units, 8192));
-            k_validate<Vc><<<grid, WG, 0, st>>>(G, g->nnz, flags);
+            int grid = 1;
+            if (int rc = grid_for(k_diag<Vc>, pl.K, &grid)) return rc;
+            k_diag<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, minv);
+            HIPCHK(hipGetLastError());
+            // heavy-edge matching for the 2x2 block preconditioner
+            int* mate = reinterpret_cast<int*>(P + pl.mate);
+            int* prop = reinterpret_cast<int*>(P + pl.prop);
+            float* pw = reinterpret_cast<float*>(P + pl.pw);
+            float2* pc = reinterpret_cast<float2*>(P + pl.pc);
+            const int gv = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + WG - 1) / WG, 8192));
+            k_pair_init<<<gv, WG, 0, st>>>(g->n, mate);
+            HIPCHK(hipGetLastError());
+            const int gw = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + NWAVE - 1) / NWAVE, 65536));
+            for (int round = 0; round < PAIR_ROUNDS; ++round) {
+                k_pair_propose<Vc><<<gw, WG, 0, st>>>(G, mate, prop, pw);
+                HIPCHK(hipGetLastError());
+                k_pair_accept<<<gv, WG, 0, st>>>(g->n, prop, mate);
+                HIPCHK(hipGetLastError());
+            }
+            k_pair_coef<<<gv, WG, 0, st>>>(g->n, mate, pw, minv, pc);
             HIPCHK(hipGetLastError());
             return FJ_OK;
         });
-        if (rc) return rc;
-        int h = 0;
-        HIPCHK(hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (h != 0) {
-            std::snprintf(g_last_error, sizeof g_last_error, "CSR contract violated (flags 0x%x)", h);
-            return FJ_ERR_INVALID_GRAPH;
-        }
-    }
-    {
-        const int grid = static_cast<int>(std::min<int64_t>((pl.K + 1 + WG - 1) / WG, 4096));
-        k_windows<<<grid, WG, 0, st>>>(g->n, g->row_ptr, pl.K, blk_row);
-        HIPCHK(hipGetLastError());
-        k_window_desc<<<grid, WG, 0, st>>>(g->n, g->row_ptr, pl.K, blk_row, desc);
-        HIPCHK(hipGetLastError());
-    }
-    return with_graph(g, [&](auto G) -> int {
-        using Vc = typename decltype(G)::value_type;
-        int grid = 1;
-        if (int rc = grid_for(k_diag<Vc>, pl.K, &grid)) return rc;
-        k_diag<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, minv);
-        HIPCHK(hipGetLastError());
-        // heavy-edge matching for the 2x2 block preconditioner
-        int* mate = reinterpret_cast<int*>(P + pl.mate);
-        int* prop = reinterpret_cast<int*>(P + pl.prop);
-        float* pw = reinterpret_cast<float*>(P + pl.pw);
-        float2* pc = reinterpret_cast<float2*>(P + pl.pc);
-        const int gv = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + WG - 1) / WG, 8192));
-        k_pair_init<<<gv, WG, 0, st>>>(g->n, mate);
-        HIPCHK(hipGetLastError());
-        const int gw = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(g->n) + NWAVE - 1) / NWAVE, 65536));
-        for (int round = 0; round < PAIR_ROUNDS; ++round) {
-            k_pair_propose<Vc><<<gw, WG, 0, st>>>(G, mate, prop, pw);
-            HIPCHK(hipGetLastError());
-            k_pair_accept<<<gv, WG, 0, st>>>(g->n, prop, mate);
-            HIPCHK(hipGetLastError());
-        }
-        k_pair_coef<<<gv, WG, 0, st>>>(g->n, mate, pw, minv, pc);
-        HIPCHK(hipGetLastError());
-        return FJ_OK;
     });
 }
 
 int fj_apply(const fj_csr* g, const void* plan, const double* x, double* y, void* stream) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
-    if (g->n == 0) return FJ_OK;
-    if (!x || !y || x == y) return FJ_ERR_INVALID_ARG;
-    const PlanLayout pl = plan_layout(g);
-    const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(plan) + pl.desc);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    return with_graph(g, [&](auto G) -> int {
-        using Vc = typename decltype(G)::value_type;
-        int grid = 1;
-        if (int rc = grid_for(k_apply<Vc>, pl.K, &grid)) return rc;
-        k_apply<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, x, y);
-        HIPCHK(hipGetLastError());
-        return FJ_OK;
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
+        if (g->n == 0) return FJ_OK;
+        if (!x || !y || x == y) return FJ_ERR_INVALID_ARG;
+        const PlanLayout pl = plan_layout(g);
+        const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(plan) + pl.desc);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        return with_graph(g, [&](auto G) -> int {
+            using Vc = typename decltype(G)::value_type;
+            int grid = 1;
+            if (int rc = grid_for(k_apply<Vc>, pl.K, &grid)) return rc;
+            k_apply<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, x, y);
+            HIPCHK(hipGetLastError());
+            return FJ_OK;
+        });
     });
 }
 
@@ -1526,166 +1579,178 @@ double fj_apriori_delta(int64_t n, double w_min, double w_max, double sbar_norm,
 
 int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl, int32_t* grid,
                    int32_t* split) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (!cpl || !grid || !split || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
-    if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
-    SpmmKey key{};
-    if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it == g_tune.end()) return FJ_ERR_INVALID_ARG;
-    *cpl = it->second.cpl;
-    *grid = it->second.grid;
-    *split = it->second.split ? 1 : 0;
-    return FJ_OK;
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (!cpl || !grid || !split || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
+        if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
+        SpmmKey key{};
+        if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it == g_tune.end()) return FJ_ERR_INVALID_ARG;
+        *cpl = it->second.cpl;
+        *grid = it->second.grid;
+        *split = it->second.split ? 1 : 0;
+        return FJ_OK;
+    });
 }
 
 int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid, int32_t split) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
-    if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
-    if ((cpl != 1 && cpl != 2 && cpl != 4) || kb % cpl != 0 || grid < 1 || grid > GMAX) return FJ_ERR_INVALID_ARG;
-    if (split != 0 && split != 1) return FJ_ERR_INVALID_ARG;
-    SpmmKey key{};
-    if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[key] = SpmmChoice{cpl, grid, split == 1};
-    return FJ_OK;
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
+        if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
+        if ((cpl != 1 && cpl != 2 && cpl != 4) || kb % cpl != 0 || grid < 1 || grid > GMAX) return FJ_ERR_INVALID_ARG;
+        if (split != 0 && split != 1) return FJ_ERR_INVALID_ARG;
+        SpmmKey key{};
+        if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = SpmmChoice{cpl, grid, split == 1};
+        return FJ_OK;
+    });
 }
 
 int fj_gather_bound(const fj_csr* g, const double* x, double* y, void* stream) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (g->nnz == 0) return FJ_OK;
-    if (!x || !y) return FJ_ERR_INVALID_ARG;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    return with_graph(g, [&](auto G) -> int {
-        using Vc = typename decltype(G)::value_type;
-        int grid = 1;
-        if (int rc = grid_for(k_gather_bound<Vc>, (g->nnz / 8 + WG) / WG, &grid)) return rc;
-        k_gather_bound<Vc><<<grid, WG, 0, st>>>(G, x, y);
-        HIPCHK(hipGetLastError());
-        return FJ_OK;
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (g->nnz == 0) return FJ_OK;
+        if (!x || !y) return FJ_ERR_INVALID_ARG;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        return with_graph(g, [&](auto G) -> int {
+            using Vc = typename decltype(G)::value_type;
+            int grid = 1;
+            if (int rc = grid_for(k_gather_bound<Vc>, (g->nnz / 8 + WG) / WG, &grid)) return rc;
+            k_gather_bound<Vc><<<grid, WG, 0, st>>>(G, x, y);
+            HIPCHK(hipGetLastError());
+            return FJ_OK;
+        });
     });
 }
 
 int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,
                 int32_t steps, double tol, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (!plan || !ws || !aligned(plan) || !aligned(ws)) return FJ_ERR_WORKSPACE;
-    if (steps < 0 || !(tol == tol)) return FJ_ERR_INVALID_ARG;
-    if (g->n > 0 && (!s || !z)) return FJ_ERR_INVALID_ARG;
-    const WsLayout wl = ws_layout(g, 1, FJ_FP64, 0);
-    if (ws_bytes < wl.total) return FJ_ERR_WORKSPACE;
-    if (info) *info = fj_info{};
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int n = g->n;
-    if (!z0) z0 = s;
-    if (n == 0) return FJ_OK;
-    if (steps == 0) {
-        if (z0 != z) HIPCHK(hipMemcpyAsync(z, z0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-        return FJ_OK;
-    }
-    const PlanLayout pl = plan_layout(g);
-    const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(plan) + pl.desc);
-    char* W = static_cast<char*>(ws);
-    double* B = reinterpret_cast<double*>(W + wl.x);
-    double* part = reinterpret_cast<double*>(W + wl.part);
-    Ctrl* ctrl = reinterpret_cast<Ctrl*>(W + wl.ctrl);
-    HostSlots* hs = nullptr;
-    if (int rc = host_slots(&hs)) return rc;
-    if (z0 == z) {  // the first step must not read and write the same vector
-        HIPCHK(hipMemcpyAsync(B, z0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        z0 = B;
-    }
-    k_ctrl_reset<<<1, WG, 0, st>>>(ctrl, 1);
-    HIPCHK(hipGetLastError());
-    k_fj_ctrl_init<<<1, 64, 0, st>>>(ctrl, tol < 0.0 ? -1.0 : tol, steps);
-    HIPCHK(hipGetLastError());
-    // step t reads src(t) and writes dst(t): dst(t) = z for even t, B for odd t
-    auto src = [&](int t) -> const double* { return t == 0 ? z0 : (t % 2 == 1 ? z : B); };
-    auto dst = [&](int t) -> double* { return t % 2 == 0 ? z : B; };
-    int queued = 0, slot_next = 0;
-    std::deque<int> pending;
-    Ctrl fin{};
-    int rc = with_graph(g, [&](auto G) -> int {
-        using Vc = typename decltype(G)::value_type;
-        int grid = 1;
-        if (int e = grid_for(k_fj_sweep<Vc>, pl.K, &grid)) return e;
-        auto enqueue = [&](int cnt) -> int {
-            for (int c = 0; c < cnt; ++c, ++queued) {
-                k_fj_sweep<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, src(queued), s, dst(queued), part, ctrl);
-                HIPCHK(hipGetLastError());
-                k_fin_fj<<<1, WG, 0, st>>>(grid, part, ctrl);
-                HIPCHK(hipGetLastError());
-            }
-            const int sl = slot_next++ % NSLOT;
-            HIPCHK(hipMemcpyAsync(hs->slot(sl), ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipEventRecord(hs->ev[sl], st));
-            pending.push_back(sl);
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (!plan || !ws || !aligned(plan) || !aligned(ws)) return FJ_ERR_WORKSPACE;
+        if (steps < 0 || !(tol == tol)) return FJ_ERR_INVALID_ARG;
+        if (g->n > 0 && (!s || !z)) return FJ_ERR_INVALID_ARG;
+        const WsLayout wl = ws_layout(g, 1, FJ_FP64, 0);
+        if (ws_bytes < wl.total) return FJ_ERR_WORKSPACE;
+        if (info) *info = fj_info{};
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int n = g->n;
+        if (!z0) z0 = s;
+        if (n == 0) return FJ_OK;
+        if (steps == 0) {
+            if (z0 != z) HIPCHK(hipMemcpyAsync(z, z0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
             return FJ_OK;
-        };
-        constexpr int CHUNK = 32;
-        for (int k = 0; k < 2 && queued < steps; ++k)
-            if (int e = enqueue(std::min(CHUNK, steps - queued))) return e;
-        while (!pending.empty()) {
-            const int sl = pending.front();
-            pending.pop_front();
-            HIPCHK(hipEventSynchronize(hs->ev[sl]));
-            const Ctrl& cc = *hs->slot(sl);
-            if (cc.done != RUNNING) break;
-            if (queued < steps)
-                if (int e = enqueue(std::min(CHUNK, steps - queued))) return e;
         }
-        return FJ_OK;
-    });
-    if (rc) return rc;
-    // later chunks are empty launches once the control block says done
-    HIPCHK(hipMemcpyAsync(hs->slot(NSLOT), ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    std::memcpy(&fin, hs->slot(NSLOT), sizeof(Ctrl));
-    const int taken = fin.iters;
-    if (taken > 0 && dst(taken - 1) != z) {
-        HIPCHK(hipMemcpyAsync(z, B, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        const PlanLayout pl = plan_layout(g);
+        const WinDesc* desc = reinterpret_cast<const WinDesc*>(static_cast<const char*>(plan) + pl.desc);
+        char* W = static_cast<char*>(ws);
+        double* B = reinterpret_cast<double*>(W + wl.x);
+        double* part = reinterpret_cast<double*>(W + wl.part);
+        Ctrl* ctrl = reinterpret_cast<Ctrl*>(W + wl.ctrl);
+        HostSlots* hs = nullptr;
+        if (int rc = host_slots(&hs)) return rc;
+        if (z0 == z) {  // the first step must not read and write the same vector
+            HIPCHK(hipMemcpyAsync(B, z0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            z0 = B;
+        }
+        k_ctrl_reset<<<1, WG, 0, st>>>(ctrl, 1);
+        HIPCHK(hipGetLastError());
+        k_fj_ctrl_init<<<1, 64, 0, st>>>(ctrl, tol < 0.0 ? -1.0 : tol, steps);
+        HIPCHK(hipGetLastError());
+        // step t reads src(t) and writes dst(t): dst(t) = z for even t, B for odd t
+        auto src = [&](int t) -> const double* { return t == 0 ? z0 : (t % 2 == 1 ? z : B); };
+        auto dst = [&](int t) -> double* { return t % 2 == 0 ? z : B; };
+        int queued = 0, slot_next = 0;
+        Pending pending;
+        Ctrl fin{};
+        int rc = with_graph(g, [&](auto G) -> int {
+            using Vc = typename decltype(G)::value_type;
+            int grid = 1;
+            if (int e = grid_for(k_fj_sweep<Vc>, pl.K, &grid)) return e;
+            auto enqueue = [&](int cnt) -> int {
+                for (int c = 0; c < cnt; ++c, ++queued) {
+                    k_fj_sweep<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, src(queued), s, dst(queued), part, ctrl);
+                    HIPCHK(hipGetLastError());
+                    k_fin_fj<<<1, WG, 0, st>>>(grid, part, ctrl);
+                    HIPCHK(hipGetLastError());
+                }
+                const int sl = slot_next++ % NSLOT;
+                HIPCHK(hipMemcpyAsync(hs->slot(sl), ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipEventRecord(hs->ev[sl], st));
+                if (!pending.push_back(sl)) return FJ_ERR_INTERNAL;
+                return FJ_OK;
+            };
+            constexpr int CHUNK = 32;
+            for (int k = 0; k < 2 && queued < steps; ++k)
+                if (int e = enqueue(std::min(CHUNK, steps - queued))) return e;
+            while (!pending.empty()) {
+                const int sl = pending.front();
+                pending.pop_front();
+                HIPCHK(hipEventSynchronize(hs->ev[sl]));
+                const Ctrl& cc = *hs->slot(sl);
+                if (cc.done != RUNNING) break;
+                if (queued < steps)
+                    if (int e = enqueue(std::min(CHUNK, steps - queued))) return e;
+            }
+            return FJ_OK;
+        });
+        if (rc) return rc;
+        // later chunks are empty launches once the control block says done
+        HIPCHK(hipMemcpyAsync(hs->slot(NSLOT), ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-    }
-    int status = FJ_OK;
-    if (fin.done == BREAKDOWN) status = FJ_ERR_BREAKDOWN;
-    else if (fin.done != CONVERGED && tol >= 0.0) status = FJ_ERR_NOT_CONVERGED;
-    if (info) {
-        info->status = status;
-        info->iters = taken;
-        info->passes = 1;
-        info->rel_residual = fin.res[0];
-    }
-    return status;
+        std::memcpy(&fin, hs->slot(NSLOT), sizeof(Ctrl));
+        const int taken = fin.iters;
+        if (taken > 0 && dst(taken - 1) != z) {
+            HIPCHK(hipMemcpyAsync(z, B, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        int status = FJ_OK;
+        if (fin.done == BREAKDOWN) status = FJ_ERR_BREAKDOWN;
+        else if (fin.done != CONVERGED && tol >= 0.0) status = FJ_ERR_NOT_CONVERGED;
+        if (info) {
+            info->status = status;
+            info->iters = taken;
+            info->passes = 1;
+            info->rel_residual = fin.res[0];
+        }
+        return status;
+    });
 }
 
 int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int64_t lds, double* Z,
              int64_t ldz, const fj_opts* opts, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (int rc = check_opts(opts)) return rc;
-    if (k < 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
-    if ((opts->flags & FJ_WARM_START) && (k != 1 || (opts->flags & FJ_TWO_SOLVE))) {
-        std::snprintf(g_last_error, sizeof g_last_error, "FJ_WARM_START needs k = 1 without FJ_TWO_SOLVE");
-        return FJ_ERR_INVALID_ARG;
-    }
-    if (g->n == 0) return FJ_OK;
-    if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
-        return solve_one(g, plan, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
-    return solve_many(g, plan, k, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (int rc = check_opts(opts)) return rc;
+        if (k < 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
+        if ((opts->flags & FJ_WARM_START) && (k != 1 || (opts->flags & FJ_TWO_SOLVE))) {
+            std::snprintf(g_last_error, sizeof g_last_error, "FJ_WARM_START needs k = 1 without FJ_TWO_SOLVE");
+            return FJ_ERR_INVALID_ARG;
+        }
+        if (g->n == 0) return FJ_OK;
+        if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
+            return solve_one(g, plan, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
+        return solve_many(g, plan, k, S, lds, Z, ldz, *opts, ws, ws_bytes, stream, false, nullptr, info);
+    });
 }
 
 int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, int64_t lds,
                const fj_opts* opts, void* ws, size_t ws_bytes, void* stream, fj_indices_t* out,
                fj_info* info) {
-    if (int rc = check_graph_args(g)) return rc;
-    if (int rc = check_opts(opts)) return rc;
-    if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
-    if (g->n == 0) return FJ_ERR_INVALID_ARG;
-    if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
-        return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
-    return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (int rc = check_opts(opts)) return rc;
+        if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
+        if (g->n == 0) return FJ_ERR_INVALID_ARG;
+        if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
+            return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+        return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+    });
 }
 
 size_t fj_server_block_bytes(int32_t n, int32_t block_columns, int32_t precision) {
@@ -1695,151 +1760,187 @@ size_t fj_server_block_bytes(int32_t n, int32_t block_columns, int32_t precision
 }
 
 int fj_server_create(const fj_server_opts* opts, fj_server** out) {
-    if (!opts || !out) return FJ_ERR_INVALID_ARG;
-    if (opts->precision != FJ_FP64 && opts->precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
-    if (opts->block_columns != 16 && opts->block_columns != 64) return FJ_ERR_INVALID_ARG;
-    if (opts->iters_per_replay < 1 || opts->iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
-    if (!(opts->eps > 0.0 && opts->eps < 0.5) || opts->max_iter < 0) return FJ_ERR_INVALID_ARG;
-    if (!opts->arena || !aligned(opts->arena) || opts->arena_bytes == 0) return FJ_ERR_WORKSPACE;
-    Server* s = new Server();
-    s->o = *opts;
-    s->arena = static_cast<char*>(opts->arena);
-    s->free_list[0] = opts->arena_bytes / ALIGN * ALIGN;
-    if (int rc = current_device(&s->device)) {
-        delete s;
-        return rc;
-    }
-    *out = reinterpret_cast<fj_server*>(s);
-    return FJ_OK;
+    return guarded([&]() -> int {
+        if (!opts || !out) return FJ_ERR_INVALID_ARG;
+        if (opts->precision != FJ_FP64 && opts->precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
+        if (opts->block_columns != 16 && opts->block_columns != 64) return FJ_ERR_INVALID_ARG;
+        if (opts->iters_per_replay < 1 || opts->iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
+        if (!(opts->eps > 0.0 && opts->eps < 0.5) || opts->max_iter < 0) return FJ_ERR_INVALID_ARG;
+        if (!opts->arena || !aligned(opts->arena) || opts->arena_bytes == 0) return FJ_ERR_WORKSPACE;
+        Server* s = new Server();
+        s->o = *opts;
+        s->arena = static_cast<char*>(opts->arena);
+        s->free_list[0] = opts->arena_bytes / ALIGN * ALIGN;
+        if (int rc = current_device(&s->device)) {
+            delete s;
+            return rc;
+        }
+        *out = reinterpret_cast<fj_server*>(s);
+        return FJ_OK;
+    });
 }
 
 int fj_server_destroy(fj_server* srv) {
-    if (!srv) return FJ_ERR_INVALID_ARG;
-    Server* s = reinterpret_cast<Server*>(srv);
-    int status = FJ_OK;
-    for (auto& G : s->graphs) {
-        if (G.blk)
-            if (int rc = release_block(*s, G)) status = rc;
-        if (G.st) {
-            const hipError_t e = hipStreamDestroy(G.st);
-            if (e != hipSuccess && status == FJ_OK) {
-                set_error("hipStreamDestroy", e);
-                status = FJ_ERR_HIP;
+    return guarded([&]() -> int {
+        if (!srv) return FJ_ERR_INVALID_ARG;
+        Server* s = reinterpret_cast<Server*>(srv);
+        int status = FJ_OK;
+        for (auto& G : s->graphs) {
+            if (G.blk)
+                if (int rc = release_block(*s, G)) status = rc;
+            if (G.dep) (void)hipEventDestroy(G.dep);
+            if (G.st) {
+                const hipError_t e = hipStreamDestroy(G.st);
+                if (e != hipSuccess && status == FJ_OK) {
+                    set_error("hipStreamDestroy", e);
+                    status = FJ_ERR_HIP;
+                }
             }
         }
-    }
-    delete s;
-    return status;
+        delete s;
+        return status;
+    });
 }
 
-int fj_server_add_graph(fj_server* srv, const fj_csr* g, const void* plan, int32_t* graph_id) {
-    if (!srv || !graph_id) return FJ_ERR_INVALID_ARG;
-    if (int rc = check_graph_args(g)) return rc;
-    if (g->n < 1) return FJ_ERR_INVALID_ARG;
-    if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
-    Server* s = reinterpret_cast<Server*>(srv);
-    ServerGraph G;
-    G.g = *g;
-    G.plan = plan;
-    G.pl = plan_layout(g);
-    HIPCHK(hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking));
-    s->graphs.push_back(std::move(G));
-    *graph_id = static_cast<int32_t>(s->graphs.size() - 1);
-    return FJ_OK;
+int fj_server_add_graph(fj_server* srv, const fj_csr* g, const void* plan, int32_t* graph_id, void* stream) {
+    return guarded([&]() -> int {
+        if (!srv || !graph_id) return FJ_ERR_INVALID_ARG;
+        if (int rc = check_graph_args(g)) return rc;
+        if (g->n < 1) return FJ_ERR_INVALID_ARG;
+        if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
+        Server* s = reinterpret_cast<Server*>(srv);
+        s->graphs.reserve(s->graphs.size() + 1);  // may throw: nothing created yet
+        ServerGraph G;
+        G.g = *g;
+        G.plan = plan;
+        G.pl = plan_layout(g);
+        HIPCHK(hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking));
+        hipError_t e = hipEventCreateWithFlags(&G.dep, hipEventDisableTiming);
+        // the graph's stream waits for the caller's work so far (fj_prepare of this plan)
+        if (e == hipSuccess) e = hipEventRecord(G.dep, static_cast<hipStream_t>(stream));
+        if (e == hipSuccess) e = hipStreamWaitEvent(G.st, G.dep, 0);
+        if (e != hipSuccess) {
+            set_error("fj_server_add_graph: stream or event", e);
+            if (G.dep) (void)hipEventDestroy(G.dep);
+            (void)hipStreamDestroy(G.st);
+            return FJ_ERR_HIP;
+        }
+        s->graphs.push_back(std::move(G));  // capacity reserved: does not throw
+        *graph_id = static_cast<int32_t>(s->graphs.size() - 1);
+        return FJ_OK;
+    });
 }
 
 int fj_server_submit(fj_server* srv, int32_t graph_id, int32_t k, const double* S, int64_t lds, fj_indices_t* out,
-                     fj_info* info, uint64_t* request_id) {
-    if (!srv || !S || !out || !request_id) return FJ_ERR_INVALID_ARG;
-    Server* s = reinterpret_cast<Server*>(srv);
-    if (graph_id < 0 || graph_id >= static_cast<int32_t>(s->graphs.size())) return FJ_ERR_INVALID_ARG;
-    if (k < 1 || k > s->o.block_columns || lds < k) return FJ_ERR_INVALID_ARG;
-    ServerGraph& G = s->graphs[graph_id];
-    if (block_bytes(G.g.n, s->o.block_columns, s->o.precision == FJ_MIXED) > s->o.arena_bytes)
-        return FJ_ERR_WORKSPACE;  // could never run
-    ServerRequest r;
-    r.id = s->next_id++;
-    r.gid = graph_id;
-    r.k = k;
-    r.S = S;
-    r.lds = lds;
-    r.out = out;
-    r.info = info;
-    r.remaining = k;
-    r.t_submit = std::chrono::steady_clock::now();
-    s->requests[r.id] = r;
-    G.queue.push_back(r.id);
-    *request_id = r.id;
-    return FJ_OK;
+                     fj_info* info, uint64_t* request_id, void* stream) {
+    return guarded([&]() -> int {
+        if (!srv || !S || !out || !request_id) return FJ_ERR_INVALID_ARG;
+        Server* s = reinterpret_cast<Server*>(srv);
+        if (graph_id < 0 || graph_id >= static_cast<int32_t>(s->graphs.size())) return FJ_ERR_INVALID_ARG;
+        if (k < 1 || k > s->o.block_columns || lds < k) return FJ_ERR_INVALID_ARG;
+        ServerGraph& G = s->graphs[graph_id];
+        if (block_bytes(G.g.n, s->o.block_columns, s->o.precision == FJ_MIXED) > s->o.arena_bytes)
+            return FJ_ERR_WORKSPACE;  // could never run
+        ServerRequest r;
+        r.id = s->next_id;
+        r.gid = graph_id;
+        r.k = k;
+        r.S = S;
+        r.lds = lds;
+        r.out = out;
+        r.info = info;
+        r.remaining = k;
+        r.t_submit = std::chrono::steady_clock::now();
+        // whatever reads S later on the graph's stream waits for the caller's
+        // work queued so far (the producer of S)
+        HIPCHK(hipEventRecord(G.dep, static_cast<hipStream_t>(stream)));
+        HIPCHK(hipStreamWaitEvent(G.st, G.dep, 0));
+        auto ins = s->requests.emplace(r.id, r);  // may throw: nothing changed yet
+        try {
+            G.queue.push_back(r.id);
+        } catch (...) {
+            s->requests.erase(ins.first);
+            throw;
+        }
+        ++s->next_id;
+        *request_id = r.id;
+        return FJ_OK;
+    });
 }
 
 int fj_server_step(fj_server* srv, int32_t* busy_blocks) {
-    if (!srv) return FJ_ERR_INVALID_ARG;
-    Server* s = reinterpret_cast<Server*>(srv);
-    int busy = 0;
-    const int rc = s->o.block_columns == 64 ? server_step_kb<64>(*s, &busy) : server_step_kb<16>(*s, &busy);
-    if (busy_blocks) *busy_blocks = busy;
-    return rc;
+    return guarded([&]() -> int {
+        if (!srv) return FJ_ERR_INVALID_ARG;
+        Server* s = reinterpret_cast<Server*>(srv);
+        int busy = 0;
+        const int rc = s->o.block_columns == 64 ? server_step_kb<64>(*s, &busy) : server_step_kb<16>(*s, &busy);
+        if (busy_blocks) *busy_blocks = busy;
+        return rc;
+    });
 }
 
 int fj_server_poll(fj_server* srv, fj_server_done* done, int32_t max, int32_t* count) {
-    if (!srv || !count || (max > 0 && !done)) return FJ_ERR_INVALID_ARG;
-    Server* s = reinterpret_cast<Server*>(srv);
-    int32_t n = 0;
-    while (n < max && !s->completed.empty()) {
-        const uint64_t rid = s->completed.front();
-        s->completed.pop_front();
-        auto it = s->requests.find(rid);
-        if (it == s->requests.end()) continue;
-        const ServerRequest& r = it->second;
-        done[n].request_id = rid;
-        done[n].graph_id = r.gid;
-        done[n].status = r.status;
-        done[n].latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
-        s->requests.erase(it);
-        ++n;
-    }
-    *count = n;
-    return FJ_OK;
+    return guarded([&]() -> int {
+        if (!srv || !count || (max > 0 && !done)) return FJ_ERR_INVALID_ARG;
+        Server* s = reinterpret_cast<Server*>(srv);
+        int32_t n = 0;
+        while (n < max && !s->completed.empty()) {
+            const uint64_t rid = s->completed.front();
+            s->completed.pop_front();
+            auto it = s->requests.find(rid);
+            if (it == s->requests.end()) continue;
+            const ServerRequest& r = it->second;
+            done[n].request_id = rid;
+            done[n].graph_id = r.gid;
+            done[n].status = r.status;
+            done[n].latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+            s->requests.erase(it);
+            ++n;
+        }
+        *count = n;
+        return FJ_OK;
+    });
 }
 
 int fj_server_cancel(fj_server* srv, uint64_t request_id) {
-    if (!srv) return FJ_ERR_INVALID_ARG;
-    Server* s = reinterpret_cast<Server*>(srv);
-    auto it = s->requests.find(request_id);
-    if (it == s->requests.end() || it->second.remaining == 0) return FJ_ERR_INVALID_ARG;
-    ServerRequest& r = it->second;
-    ServerGraph& G = s->graphs[r.gid];
-    for (auto q = G.queue.begin(); q != G.queue.end(); ++q)
-        if (*q == request_id) {
-            G.queue.erase(q);
-            break;
-        }
-    if (ServerBlock* b = G.blk) {
-        uint64_t mask = 0;
-        for (int c = 0; c < s->o.block_columns; ++c)
-            if (b->slot_req[c] == static_cast<int64_t>(request_id)) {
-                mask |= 1ull << c;
-                b->slot_req[c] = -1;
+    return guarded([&]() -> int {
+        if (!srv) return FJ_ERR_INVALID_ARG;
+        Server* s = reinterpret_cast<Server*>(srv);
+        auto it = s->requests.find(request_id);
+        if (it == s->requests.end() || it->second.remaining == 0) return FJ_ERR_INVALID_ARG;
+        ServerRequest& r = it->second;
+        ServerGraph& G = s->graphs[r.gid];
+        for (auto q = G.queue.begin(); q != G.queue.end(); ++q)
+            if (*q == request_id) {
+                G.queue.erase(q);
+                break;
             }
-        if (mask) {  // stream-ordered after any replay or epilogue in flight
-            for (Ctrl* cb : {b->ctrl, b->ictrl}) {
-                if (!cb) continue;
-                k_ctrl_set_done<<<1, WG, 0, G.st>>>(cb, s->o.block_columns, mask, static_cast<int>(CONVERGED));
-                HIPCHK(hipGetLastError());
+        if (ServerBlock* b = G.blk) {
+            uint64_t mask = 0;
+            for (int c = 0; c < s->o.block_columns; ++c)
+                if (b->slot_req[c] == static_cast<int64_t>(request_id)) {
+                    mask |= 1ull << c;
+                    b->slot_req[c] = -1;
+                }
+            if (mask) {  // stream-ordered after any replay or epilogue in flight
+                for (Ctrl* cb : {b->ctrl, b->ictrl}) {
+                    if (!cb) continue;
+                    k_ctrl_set_done<<<1, WG, 0, G.st>>>(cb, s->o.block_columns, mask, static_cast<int>(CONVERGED));
+                    HIPCHK(hipGetLastError());
+                }
+                b->running &= ~mask;
+                b->finishing &= ~mask;
+                // the caller may free the request's opinion vectors once it is
+                // reported: let the scatter that read them finish first
+                HIPCHK(hipStreamSynchronize(G.st));
             }
-            b->running &= ~mask;
-            b->finishing &= ~mask;
-            // the caller may free the request's opinion vectors once it is
-            // reported: let the scatter that read them finish first
-            HIPCHK(hipStreamSynchronize(G.st));
         }
-    }
-    r.status = FJ_ERR_CANCELLED;
-    r.remaining = 0;
-    r.t_done = std::chrono::steady_clock::now();
-    s->completed.push_back(request_id);
-    return FJ_OK;
+        r.status = FJ_ERR_CANCELLED;
+        r.remaining = 0;
+        r.t_done = std::chrono::steady_clock::now();
+        s->completed.push_back(request_id);
+        return FJ_OK;
+    });
 }
 
 }  // extern "C"

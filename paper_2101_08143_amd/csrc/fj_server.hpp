@@ -69,6 +69,7 @@ struct ServerGraph {
     const void* plan = nullptr;
     PlanLayout pl{};
     hipStream_t st = nullptr;
+    hipEvent_t dep = nullptr;  // orders the stream after the caller's producer of plan / S
     std::deque<uint64_t> queue;
     ServerBlock* blk = nullptr;
 };

@@ -32,6 +32,8 @@ FJ_ERR_BREAKDOWN = 6
 FJ_ERR_UNCERTIFIABLE = 7
 FJ_ERR_HIP = 8
 FJ_ERR_CANCELLED = 9
+FJ_ERR_HOST_MEMORY = 10
+FJ_ERR_INTERNAL = 11
 
 FJ_VAL_UNIT, FJ_VAL_F32, FJ_VAL_F64 = 0, 1, 2
 FJ_FP64, FJ_MIXED = 0, 1
@@ -67,7 +69,8 @@ class fj_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("passes", ctypes.c_int32),
                 ("outer_iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("bound", ctypes.c_double * 5), ("ms_spmv", ctypes.c_double),
-                ("n_spmv", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_spmv", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("residual_norm", ctypes.c_double), ("abs_bound", ctypes.c_double * 5)]
 
 
 class fj_server_opts(ctypes.Structure):
@@ -127,8 +130,8 @@ def lib():
         L.fj_server_block_bytes.restype = sz
         L.fj_server_create.argtypes = [P(fj_server_opts), P(vp)]
         L.fj_server_destroy.argtypes = [vp]
-        L.fj_server_add_graph.argtypes = [vp, P(fj_csr), vp, P(i32)]
-        L.fj_server_submit.argtypes = [vp, i32, i32, vp, i64, P(fj_indices_t), P(fj_info), P(ctypes.c_uint64)]
+        L.fj_server_add_graph.argtypes = [vp, P(fj_csr), vp, P(i32), vp]
+        L.fj_server_submit.argtypes = [vp, i32, i32, vp, i64, P(fj_indices_t), P(fj_info), P(ctypes.c_uint64), vp]
         L.fj_server_step.argtypes = [vp, P(i32)]
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
@@ -348,7 +351,7 @@ def fj_indices(graph: Graph, S, opts: Optional[fj_opts] = None, ws=None, stream=
 def info_dict(inf: fj_info) -> dict:
     return dict(status=inf.status, iters=inf.iters, passes=inf.passes, outer_iters=inf.outer_iters,
                 rel_residual=inf.rel_residual, bound=list(inf.bound), ms_spmv=inf.ms_spmv,
-                n_spmv=inf.n_spmv)
+                n_spmv=inf.n_spmv, residual_norm=inf.residual_norm, abs_bound=list(inf.abs_bound))
 
 
 class Server:
@@ -374,21 +377,27 @@ class Server:
     def block_bytes(n, block_columns=16, precision=0):
         return lib().fj_server_block_bytes(int(n), int(block_columns), int(precision))
 
-    def add_graph(self, graph: Graph) -> int:
+    def add_graph(self, graph: Graph, stream=None) -> int:
+        """stream: where the graph and plan were produced (default: torch's current stream)."""
+        import torch
         gid = ctypes.c_int32()
-        rc = lib().fj_server_add_graph(self.handle, ctypes.byref(graph.csr), _ptr(graph.plan), ctypes.byref(gid))
+        rc = lib().fj_server_add_graph(self.handle, ctypes.byref(graph.csr), _ptr(graph.plan), ctypes.byref(gid),
+                                       _stream_handle(torch, stream))
         if rc != FJ_OK:
             raise FJError(rc, "fj_server_add_graph")
         self.graphs.append(graph)
         return gid.value
 
-    def submit(self, gid, S) -> int:
-        """S: device float64 tensor, n or n x k (k <= block_columns)."""
+    def submit(self, gid, S, stream=None) -> int:
+        """S: device float64 tensor, n or n x k (k <= block_columns), produced on
+        `stream` (default: torch's current stream)."""
+        import torch
         S2, k, lds = _check_block(self.graphs[gid], S, "S")
         out = (fj_indices_t * k)()
         info = (fj_info * k)()
         rid = ctypes.c_uint64()
-        rc = lib().fj_server_submit(self.handle, gid, k, _ptr(S2), lds, out, info, ctypes.byref(rid))
+        rc = lib().fj_server_submit(self.handle, gid, k, _ptr(S2), lds, out, info, ctypes.byref(rid),
+                                    _stream_handle(torch, stream))
         if rc != FJ_OK:
             raise FJError(rc, "fj_server_submit")
         self.pending[rid.value] = (S2, out, info, k)

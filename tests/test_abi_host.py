@@ -42,7 +42,7 @@ def test_library_exports_every_declared_function(lib):
 
 
 def test_status_strings(lib):
-    for code in range(0, 9):
+    for code in range(0, 12):
         assert fj.fj_status_string(code) not in ("", "unknown status")
     assert fj.fj_status_string(99) == "unknown status"
 
@@ -147,3 +147,63 @@ def test_apriori_delta(lib):
     assert fj.fj_apriori_delta(4_000_000, 0.5, 2.0, 100.0, 1e-6) < 1e-34
     assert math.isnan(fj.fj_apriori_delta(0, 1.0, 1.0, 1.0, 1e-6))
     assert math.isnan(fj.fj_apriori_delta(10, 1.0, 1.0, 1.0, 0.5))
+
+
+API = os.path.join(ROOT, "paper_2101_08143_amd", "csrc", "fj_api.hip")
+GUARD_DIR = os.path.join(ROOT, "paper_2101_08143_amd", "csrc")
+
+
+def test_every_status_entry_point_is_guarded():
+    """Every extern "C" function that returns a status runs its body through
+    guarded() (no C++ exception crosses the ABI)."""
+    src = open(API).read()
+    body = src.split('extern "C" {', 1)[1]
+    sigs = re.findall(r"^int (fj_\w+)\([^{]*\{\n([^\n]*)\n", body, flags=re.M)
+    assert len(sigs) >= 15
+    for name, first in sigs:
+        assert first.strip() == "return guarded([&]() -> int {", name
+
+
+def test_guard_maps_exceptions_to_status(tmp_path):
+    """An allocation failure planted on the CPU (and any other exception) comes
+    out of guarded() as a status code and a message, never as an exception."""
+    prog = tmp_path / "guard.cpp"
+    prog.write_text(r'''
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <type_traits>
+#include "fj_guard.hpp"
+char* volatile sink = nullptr;
+int main() {
+    auto ok = []() -> int { return 0; };
+    static_assert(noexcept(fj::guarded(ok)), "guarded must be noexcept");
+    const int a = fj::guarded([]() -> int {
+        volatile size_t huge = size_t(1) << 62;
+        sink = new char[huge];  // fails: no such address space (kept, so it cannot be elided)
+        return FJ_OK;
+    });
+    const bool ma = std::strstr(fj::g_last_error, "allocation") != nullptr;
+    const int b = fj::guarded([]() -> int { throw std::runtime_error("planted"); });
+    const bool mb = std::strstr(fj::g_last_error, "planted") != nullptr;
+    const int c = fj::guarded([]() -> int { throw 7; });
+    const int d = fj::guarded([]() -> int { return FJ_ERR_WORKSPACE; });
+    std::printf("%d %d %d %d %d %d\n", a, b, c, d, ma ? 1 : 0, mb ? 1 : 0);
+    return 0;
+}
+''')
+    exe = tmp_path / "guard"
+    import subprocess
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", GUARD_DIR, "-o", str(exe), str(prog)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert [int(x) for x in out] == [fj.FJ_ERR_HOST_MEMORY, fj.FJ_ERR_INTERNAL, fj.FJ_ERR_INTERNAL,
+                                    fj.FJ_ERR_WORKSPACE, 1, 1]
+
+
+def test_info_layout_matches_header():
+    """fj_info in the binding has the header's fields in the header's order."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct fj_info \{(.*?)\} fj_info;", src, flags=re.S).group(1)
+    fields = re.findall(r"(\w+)(?:\[\d+\])?;", body)
+    assert fields == [f[0] for f in fj.fj_info._fields_]

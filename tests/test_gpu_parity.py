@@ -105,16 +105,27 @@ def test_random_graphs_match_oracle(torch_fj, seed):
     g, s = _random_case(seed)
     say(f"random graph seed={seed} n={g.n} nnz={g.nnz}")
     G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
-    ref, _, _ = O.indices(g, s)
+    ref, zref, oinfo = O.indices(g, s)
+    # the oracle's own absolute error per index (its certificate, rho ~ 1e-13 ||s||)
+    rho_o = oinfo["relres"] * float(np.linalg.norm(s))
+    o_abs = [rho_o * (2 * np.sqrt(max(ref[nm], 0.0)) + rho_o) for nm in NAMES[:4]]
+    o_abs.append((np.sqrt(ref["controversy"]) + rho_o) * rho_o)
     sd = torch.from_numpy(s).to("cuda:0")
     for prec in (fj.FJ_FP64, fj.FJ_MIXED):
         vals, infos, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, precision=prec), check=False)
-        if rc == fj.FJ_ERR_UNCERTIFIABLE:  # an index too close to 0 (e.g. disagreement on a tiny graph)
-            continue
-        assert rc == fj.FJ_OK, (prec, fj.info_dict(infos[0]))
+        inf0 = infos[0]
+        # an uncertifiable index is only acceptable where the oracle cannot certify it either
+        if rc == fj.FJ_ERR_UNCERTIFIABLE:
+            assert not oinfo["certified"], (prec, fj.info_dict(inf0), oinfo["bounds"])
+        else:
+            assert rc == fj.FJ_OK, (prec, fj.info_dict(inf0))
         for j, nm in enumerate(NAMES):
-            err = abs(vals[0][nm] - ref[nm]) / abs(ref[nm])
-            assert err <= EPS and err <= infos[0].bound[j] + 1e-12, (prec, nm, err)
+            diff = abs(vals[0][nm] - ref[nm])
+            # every index: within the absolute bound of both certificates
+            assert diff <= inf0.abs_bound[j] + o_abs[j] + 1e-300, (prec, nm, diff, inf0.abs_bound[j])
+            if np.isfinite(inf0.bound[j]):  # and, where it has one, within its relative bound
+                err = diff / abs(ref[nm])
+                assert err <= EPS and err <= inf0.bound[j] + 1e-12, (prec, nm, err)
 
 
 @pytest.mark.parametrize("name", ["cl50k_f32", "gnp500_f64", "star6001", "isolated9000"])
@@ -211,6 +222,12 @@ def test_degenerate_cases(torch_fj, graphs):
     assert abs(vals[0]["dc_index"] - g.n * 0.16) <= 1e-9 * g.n * 0.16
     for k in ("internal_conflict", "disagreement", "polarization"):
         assert vals[0][k] <= 1e-20
+    # the absolute bounds stand in for the missing relative ones: exact values P = D = C_I = 0, C = I_dc = 0.16 n
+    exact = dict(internal_conflict=0.0, disagreement=0.0, polarization=0.0, controversy=g.n * 0.16,
+                 dc_index=g.n * 0.16)
+    for j, k in enumerate(NAMES):
+        assert np.isfinite(infos[0].abs_bound[j]) and abs(vals[0][k] - exact[k]) <= infos[0].abs_bound[j], k
+    assert infos[0].residual_norm >= 0.0 and np.isfinite(infos[0].residual_norm)
     # edgeless graph: z = s, D = C_I = 0
     ge = W.csr_from_edges(257, np.zeros((0, 2), dtype=np.int64))
     say("edgeless")
@@ -222,6 +239,11 @@ def test_degenerate_cases(torch_fj, graphs):
     assert abs(vals[0]["polarization"] - sb @ sb) <= 1e-12 * (sb @ sb)
     assert abs(vals[0]["controversy"] - s @ s) <= 1e-12 * (s @ s)
     assert vals[0]["disagreement"] == 0.0 and vals[0]["internal_conflict"] == 0.0
+    exact = dict(internal_conflict=0.0, disagreement=0.0, polarization=float(sb @ sb), controversy=float(s @ s),
+                 dc_index=float(s @ s))
+    for j, k in enumerate(NAMES):
+        assert abs(vals[0][k] - exact[k]) <= infos[0].abs_bound[j], k
+    assert not np.isfinite(infos[0].bound[0]) and not np.isfinite(infos[0].bound[1])
     # edgeless and large enough for the block preconditioner: no pairs, M = I
     gb = W.csr_from_edges(70_000, np.zeros((0, 2), dtype=np.int64))
     say("edgeless 70000")
