@@ -253,6 +253,27 @@ int fj_indices(const fj_csr *g, const void *plan, int32_t k, const double *S, in
                const fj_opts *opts, void *ws, size_t ws_bytes, void *stream,
                fj_indices_t *out, fj_info *info);
 
+/*
+ * fj_indices without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, results and statuses as
+ * fj_indices; the workspace is a static device array of
+ * FJ_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library, one per GPU, held
+ * until the process ends. A solve whose fj_workspace_bytes exceeds it returns
+ * FJ_ERR_WORKSPACE (FP64, one vector: up to about 1.39M nodes; FJ_MIXED up to
+ * about 1.67M). The call allocates no device memory and calls no allocating
+ * HIP or torch routine; its first call on each device sets up (the array's
+ * device address and a 2 KiB pinned control block). Batched columns always
+ * run with FJ_NO_TUNE; FJ_PROFILE is rejected (FJ_ERR_INVALID_ARG). All
+ * calls on one GPU share the array: the library runs them one at a time (a
+ * per-device lock), so calls from several threads on one GPU serialise, and
+ * each call initialises every scratch byte it reads (it keeps no state
+ * between calls). Synchronises before returning.
+ */
+#define FJ_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int fj_indices_noalloc(const fj_csr *g, const void *plan, int32_t k, const double *S, int64_t lds,
+                       const fj_opts *opts, void *stream, fj_indices_t *out, fj_info *info);
+
 /* ---- serving ------------------------------------------------------------ */
 /*
  * A continuous-batching server for index requests on resident graphs

@@ -783,7 +783,7 @@ int solve_mixed(Ctx& c, CgState<double>& S, CgState<float>& I, const double* s, 
 }
 
 int make_ctx(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k, void* stream,
-             const fj_opts* o, Ctx* c, WsLayout* wl) {
+             const fj_opts* o, Ctx* c, WsLayout* wl, HostSlots* slots = nullptr) {
     if (!plan || !ws || !aligned(plan) || !aligned(ws)) return FJ_ERR_WORKSPACE;
     c->g = g;
     c->pl = plan_layout(g);
@@ -792,17 +792,18 @@ int make_ctx(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k
     if (ws_bytes < wl->total) return FJ_ERR_WORKSPACE;
     c->st = static_cast<hipStream_t>(stream);
     c->profile = (o->flags & FJ_PROFILE) != 0;
-    if (int rc = host_slots(&c->hs)) return rc;
+    if (slots) c->hs = slots;
+    else if (int rc = host_slots(&c->hs)) return rc;
     return grid_for(k_cg_update<double, true>, (static_cast<int64_t>(g->n) + 2 * WG - 1) / (2 * WG), &c->grid_vec);
 }
 
 // Single right-hand side, either precision. Z (may be null) receives z.
 int solve_one(const fj_csr* g, const void* plan, const double* S, int64_t lds, double* Z, int64_t ldz,
               const fj_opts& o, void* ws, size_t ws_bytes, void* stream, bool want_indices, fj_indices_t* out,
-              fj_info* info) {
+              fj_info* info, HostSlots* slots = nullptr) {
     Ctx c{};
     WsLayout wl{};
-    if (int rc = make_ctx(g, plan, ws, ws_bytes, 1, stream, &o, &c, &wl)) return rc;
+    if (int rc = make_ctx(g, plan, ws, ws_bytes, 1, stream, &o, &c, &wl, slots)) return rc;
     char* W = static_cast<char*>(ws);
     Ctrl* ctrls = reinterpret_cast<Ctrl*>(W + wl.ctrl);
     double* part = reinterpret_cast<double*>(W + wl.part);
@@ -1411,10 +1412,10 @@ int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t ld
 // Any number of columns: blocks of up to KMAX columns.
 int solve_many(const fj_csr* g, const void* plan, int k, const double* S, int64_t lds, double* Z, int64_t ldz,
                const fj_opts& o, void* ws, size_t ws_bytes, void* stream, bool want_indices, fj_indices_t* out,
-               fj_info* info) {
+               fj_info* info, HostSlots* slots = nullptr) {
     Ctx c{};
     WsLayout wl{};
-    if (int rc = make_ctx(g, plan, ws, ws_bytes, k, stream, &o, &c, &wl)) return rc;
+    if (int rc = make_ctx(g, plan, ws, ws_bytes, k, stream, &o, &c, &wl, slots)) return rc;
     char* W = static_cast<char*>(ws);
     int worst = FJ_OK;
     for (int c0 = 0; c0 < k; c0 += KMAX) {
@@ -1440,6 +1441,46 @@ int solve_many(const fj_csr* g, const void* plan, int k, const double* S, int64_
 }
 
 #include "fj_server.hpp"
+
+}  // namespace
+
+// ---------------------------------------------------------------- no-allocation entry point
+//
+// fj_indices_noalloc keeps its workspace in this array: one copy per GPU the
+// library runs on, alive until the process ends. In host code `scratch` is a
+// host-side stand-in, never a device address: the device address of each
+// GPU's copy comes from hipGetSymbolAddress (once per device, with that
+// device current) and only that pointer is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[FJ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+struct NoAllocDevice {
+    std::once_flag once;
+    int rc = FJ_OK;
+    void* ptr = nullptr;    // this device's copy of `scratch`
+    HostSlots slots;        // pinned control-block slots and events for calls on this device
+    std::mutex mu;          // calls on one device share the array: one at a time
+};
+NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Set-up on the first call on a device (the device is current): the array's
+// address on this device, and the pinned slots the CG driver polls.
+int noalloc_setup(int dev, NoAllocDevice& d) {
+    std::call_once(d.once, [&]() {
+        d.rc = [&]() -> int {
+            HIPCHK(hipGetSymbolAddress(&d.ptr, HIP_SYMBOL(scratch)));
+            HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&d.slots.h), sizeof(Ctrl) * KMAX * (NSLOT + 1),
+                                 hipHostMallocDefault));
+            for (auto& e : d.slots.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            return FJ_OK;
+        }();
+        (void)dev;
+    });
+    return d.rc;
+}
 
 }  // namespace
 
@@ -1750,6 +1791,40 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
         if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
             return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
         return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
+    });
+}
+
+int fj_indices_noalloc(const fj_csr* g, const void* plan, int32_t k, const double* S, int64_t lds,
+                       const fj_opts* opts, void* stream, fj_indices_t* out, fj_info* info) {
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (int rc = check_opts(opts)) return rc;
+        if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
+        if (g->n == 0) return FJ_ERR_INVALID_ARG;
+        if (opts->flags & FJ_PROFILE) {  // profiling creates events
+            std::snprintf(g_last_error, sizeof g_last_error, "fj_indices_noalloc: FJ_PROFILE is not available");
+            return FJ_ERR_INVALID_ARG;
+        }
+        fj_opts o = *opts;
+        o.flags |= FJ_NO_TUNE;  // the SpMM autotuner times candidates with events of its own
+        const size_t need = ws_layout(g, k, o.precision, o.flags).total;
+        if (need > FJ_NOALLOC_SCRATCH_BYTES) {
+            std::snprintf(g_last_error, sizeof g_last_error,
+                          "fj_indices_noalloc: this solve needs %zu bytes of workspace, the static scratch holds %zu",
+                          need, static_cast<size_t>(FJ_NOALLOC_SCRATCH_BYTES));
+            return FJ_ERR_WORKSPACE;
+        }
+        int dev = 0;
+        if (int rc = current_device(&dev)) return rc;
+        if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return FJ_ERR_INVALID_ARG;
+        NoAllocDevice& d = g_noalloc[dev];
+        if (int rc = noalloc_setup(dev, d)) return rc;
+        std::lock_guard<std::mutex> lock(d.mu);
+        if (k == 1 && !(o.flags & FJ_TWO_SOLVE))
+            return solve_one(g, plan, S, lds, nullptr, 0, o, d.ptr, FJ_NOALLOC_SCRATCH_BYTES, stream, true, out, info,
+                             &d.slots);
+        return solve_many(g, plan, k, S, lds, nullptr, 0, o, d.ptr, FJ_NOALLOC_SCRATCH_BYTES, stream, true, out,
+                          info, &d.slots);
     });
 }
 

@@ -46,7 +46,8 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
            "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
-           "fj_spmm_set_choice", "fj_gather_bound", "fj_dynamics", "fj_indices", "fj_server_block_bytes",
+           "fj_spmm_set_choice", "fj_gather_bound", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
+           "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll", "fj_server_cancel")
 
@@ -126,6 +127,7 @@ def lib():
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
                                  P(fj_info)]
+        L.fj_indices_noalloc.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, P(fj_indices_t), P(fj_info)]
         L.fj_server_block_bytes.argtypes = [i32, i32, i32]
         L.fj_server_block_bytes.restype = sz
         L.fj_server_create.argtypes = [P(fj_server_opts), P(vp)]
@@ -136,7 +138,8 @@ def lib():
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
         for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
-                     "fj_dynamics", "fj_solve", "fj_indices", "fj_server_create", "fj_server_destroy",
+                     "fj_dynamics", "fj_solve", "fj_indices", "fj_indices_noalloc", "fj_server_create",
+                     "fj_server_destroy",
                      "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll",
                      "fj_server_cancel"):
             getattr(L, name).restype = ctypes.c_int
@@ -344,6 +347,22 @@ def fj_indices(graph: Graph, S, opts: Optional[fj_opts] = None, ws=None, stream=
                           _ptr(ws), ws.numel(), _stream_handle(torch, stream), out, info)
     if check and rc != FJ_OK:
         raise FJError(rc, "fj_indices")
+    vals = [{name: getattr(out[c], name) for name in INDEX_NAMES} for c in range(k)]
+    return vals, list(info), rc
+
+
+def fj_indices_noalloc(graph: Graph, S, opts: Optional[fj_opts] = None, stream=None, check=True):
+    """fj_indices with the library's static scratch instead of a workspace
+    (allocates no device memory). Returns (list of dicts, [fj_info]*k, status)."""
+    import torch
+    S2, k, lds = _check_block(graph, S, "S")
+    o = opts or fj_default_opts()
+    out = (fj_indices_t * k)()
+    info = (fj_info * k)()
+    rc = lib().fj_indices_noalloc(ctypes.byref(graph.csr), _ptr(graph.plan), k, _ptr(S2), lds, ctypes.byref(o),
+                                  _stream_handle(torch, stream), out, info)
+    if check and rc != FJ_OK:
+        raise FJError(rc, "fj_indices_noalloc")
     vals = [{name: getattr(out[c], name) for name in INDEX_NAMES} for c in range(k)]
     return vals, list(info), rc
 
