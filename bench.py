@@ -141,6 +141,16 @@ def batched_forms(args, fj, W, torch, dev):
             "spmm_default_shape_avg_launch_ms": untuned,
         }
         print(f"[bench] {name}: {1e3 * el:.1f} ms per call", file=sys.stderr, flush=True)
+    # per-index error against the oracle for two sampled columns (a uniform and
+    # a Pareto one) of each batched form
+    if args.cpu_solves > 0:
+        from oracle import sparse as O
+        for c in (0, 42):
+            ref, _, _ = O.indices(g, S[:, c].copy())
+            for name, prec in (("batched64_fp64", fj.FJ_FP64), ("batched64_mixed", fj.FJ_MIXED)):
+                vals, _, _ = fj.fj_indices(G, Sd, fj.make_opts(eps=args.eps, precision=prec))
+                out[name].setdefault("rel_err_vs_oracle_sampled", {})[f"column_{c}"] = {
+                    k: abs(vals[c][k] - ref[k]) / abs(ref[k]) for k in fj.INDEX_NAMES}
     # the plain comparison: the same 64 vectors one at a time in FP64
     o = fj.make_opts(eps=args.eps)
     ws = G.workspace(1, o)
@@ -158,6 +168,106 @@ def batched_forms(args, fj, W, torch, dev):
         out[name]["speedup_vs_sequential_fp64"] = out[name]["value"] / out["sequential64_fp64"]["value"]
     del G
     torch.cuda.empty_cache()
+    return out
+
+
+def small_configs_form(args, fj, W, torch, dev):
+    """The 10K-node Barabasi-Albert graph (microseconds per certified solve)
+    and the 1M-node Chung-Lu graph (FP64 against FP32-inner solves per
+    second), each against the oracle per index."""
+    out = {}
+    for name, steps in (("ba10k", 50), ("cl1m", 20)):
+        g, s, spec = W.workload(name)
+        G = fj.Graph.from_csr(g, device=dev, validate=False)
+        sd = torch.from_numpy(s).to(dev)
+        ref = None
+        if args.cpu_solves > 0:
+            from oracle import sparse as O
+            ref, _, _ = O.indices(g, s)
+        form = {"graph": {k: v for k, v in WORKLOAD_META[name].items()}, "nnz": g.nnz}
+        for prec_name, prec in (("fp64", fj.FJ_FP64), ("mixed", fj.FJ_MIXED)):
+            o = fj.make_opts(eps=args.eps, rtol=spec["rtol"], precision=prec)
+            ws = G.workspace(1, o)
+            for _ in range(3):
+                fj.fj_indices(G, sd, o, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                vals, infos, rc = fj.fj_indices(G, sd, o, ws=ws, check=False)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            entry = {"solves_per_s": 1.0 / el, "us_per_solve": 1e6 * el, "iters": infos[0].iters,
+                     "certified": bool(rc == fj.FJ_OK), "rel_residual": infos[0].rel_residual}
+            if ref is not None:
+                entry["rel_err_vs_oracle"] = {k: abs(vals[0][k] - ref[k]) / abs(ref[k]) for k in fj.INDEX_NAMES}
+            form[prec_name] = entry
+        form["mixed_speedup_vs_fp64"] = form["fp64"]["us_per_solve"] / form["mixed"]["us_per_solve"]
+        if name == "ba10k" and args.cpu_solves > 0:
+            # the paper's 'Exact' (dense I + L) as a dense LAPACK Cholesky solve on the host cores
+            import numpy as np
+            import scipy.linalg
+            from oracle import dense as D
+            t0 = time.perf_counter()
+            M = np.eye(g.n) + D.laplacian_dense(g)
+            t_form = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            z = scipy.linalg.solve(M, s, assume_a="pos")
+            t_solve = time.perf_counter() - t0
+            del M
+            form["dense_lapack_exact"] = {"seconds_solve": t_solve, "seconds_form_matrix": t_form,
+                                          "max_abs_diff_vs_oracle_z": float(np.abs(z - O.solve(g, s)[0]).max()),
+                                          "note": "dense Cholesky solve of I + L (the analogue of the paper's "
+                                                  "Exact, which inverts it) on the host cores"}
+        out[name] = form
+        print(f"[bench] {name}: fp64 {form['fp64']['us_per_solve']:.0f} us, mixed "
+              f"{form['mixed']['us_per_solve']:.0f} us per certified solve", file=sys.stderr, flush=True)
+        del G, sd
+    torch.cuda.empty_cache()
+    return out
+
+
+def fifo_baseline(args, fj, W, torch, graphs, pools, server_sat_rps):
+    """The same kind of request stream served the plain way: one FP64
+    single-vector fj_indices call per opinion vector, requests in arrival
+    order (FIFO), at the server's 0.5x arrival rate and at half of the FIFO's
+    own saturation rate. Latency from the scheduled arrival to the return of
+    the request's last call."""
+    import numpy as np
+    o = fj.make_opts(eps=args.eps)
+    big = max(range(len(graphs)), key=lambda i: graphs[i].n)
+    ws = graphs[big].workspace(1, o)  # large enough for every graph
+
+    def serve(reqs, arrivals):
+        start = time.perf_counter()
+        lat, solves = [], 0
+        for i, (gi, k, c0) in enumerate(reqs):
+            now = time.perf_counter() - start
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            for c in range(k):
+                fj.fj_indices(graphs[gi], pools[gi][:, c0 + c].contiguous(), o, ws=ws)
+            lat.append(1e3 * (time.perf_counter() - start - arrivals[i]))
+            solves += k
+        return np.array(lat), solves, time.perf_counter() - start
+
+    warm = max(args.fifo_requests // 10, 10)
+    reqs = W.serving_requests(warm + 64, len(graphs), seed=3100)
+    serve(reqs[:warm], [0.0] * warm)
+    lat, solves, el = serve(reqs[warm:], [0.0] * 64)
+    fifo_sat = 64 / el
+    out = {"description": "FIFO of plain FP64 single-vector fj_indices calls (one per opinion vector) on the same "
+                          "32 graphs and request mix",
+           "saturation": {"requests_per_s": fifo_sat, "solves_per_s": solves / el}}
+    for label, rate in (("server_0.50", 0.5 * server_sat_rps), ("own_0.50", 0.5 * fifo_sat)):
+        reqs = W.serving_requests(warm + args.fifo_requests, len(graphs), seed=3001 + 50)
+        arrivals = np.cumsum(np.random.default_rng(4050).exponential(1.0 / rate, len(reqs)))
+        lat, solves, el = serve(reqs, arrivals)
+        m = lat[warm:]
+        out[label] = {"offered_requests_per_s": rate, "p50_ms": float(np.percentile(m, 50)),
+                      "p99_ms": float(np.percentile(m, 99)), "max_ms": float(m.max()),
+                      "measured_requests": int(m.size), "warmup_requests": warm}
+        print(f"[bench] fifo fp64 at {label} ({rate:.1f} req/s): p50 {out[label]['p50_ms']:.1f} ms, "
+              f"p99 {out[label]['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
     return out
 
 
@@ -187,7 +297,12 @@ def serving_form(args, fj, W, torch, dev):
 
         def run(reqs, arrivals):
             """Submit request i at arrivals[i] seconds after the start; drive the
-            server until all complete. Returns per-request (latency_ms, k, status)."""
+            server until all complete. Returns per-request (index, latency from
+            the scheduled arrival in ms, k, status, latency inside the server
+            (submit to retire) in ms, submit lag in ms) and the elapsed time.
+            Latency counts from the scheduled arrival, not from the submit call,
+            so time the loop spends away from submitting is not dropped; a
+            completion is seen at the poll right after the step that retired it."""
             order = {}
             start = time.perf_counter()
             nxt = 0
@@ -197,12 +312,16 @@ def serving_form(args, fj, W, torch, dev):
                 while nxt < len(reqs) and arrivals[nxt] <= now:
                     gi, k, c0 = reqs[nxt]
                     rid = srv.submit(gids[gi], pools[gi][:, c0:c0 + k])
-                    order[rid] = (nxt, k)
+                    order[rid] = (nxt, k, time.perf_counter() - start)
                     nxt += 1
                 srv.step()
-                for r in srv.poll():
-                    i, k = order[r["id"]]
-                    res.append((i, r["latency_ms"], k, r["status"]))
+                done = srv.poll()
+                if done:
+                    seen = time.perf_counter() - start
+                    for r in done:
+                        i, k, t_sub = order[r["id"]]
+                        res.append((i, 1e3 * (seen - arrivals[i]), k, r["status"], r["latency_ms"],
+                                    1e3 * (t_sub - arrivals[i])))
             return res, time.perf_counter() - start
 
         n_sat = max(args.serve_requests // 2, 32)
@@ -212,29 +331,41 @@ def serving_form(args, fj, W, torch, dev):
         run([(gi, 1, 0) for gi in range(len(graphs))], [0.0] * len(graphs))
         run(reqs[:32], [0.0] * 32)
         res, el = run(reqs[32:], [0.0] * (len(reqs) - 32))
-        solves = sum(k for _, _, k, _ in res)
+        solves = sum(r[2] for r in res)
         sat_rps = len(res) / el
         sat = {"requests_per_s": sat_rps, "solves_per_s": solves / el, "requests": len(res),
-               "all_certified": all(st == 0 for *_, st in res)}
+               "all_certified": all(r[3] == 0 for r in res)}
         print(f"[bench] {name} saturation: {sat_rps:.1f} req/s, {solves / el:.1f} solves/s", file=sys.stderr,
               flush=True)
         levels = {}
         for f in (0.5, 0.8, 0.95):
             rate = f * sat_rps
-            warm = max(args.serve_requests // 10, 10)
-            reqs = W.serving_requests(warm + args.serve_requests, len(graphs), seed=3001 + int(100 * f))
-            gaps = np.random.default_rng(4000 + int(100 * f)).exponential(1.0 / rate, len(reqs))
-            res, el = run(reqs, np.cumsum(gaps))
-            meas = sorted((i, lat, k, st) for i, lat, k, st in res if i >= warm)
+            long_run = prec == fj.FJ_FP64 and f == 0.5 and args.serve_requests_long > 0
+            count = args.serve_requests_long if long_run else args.serve_requests
+            warm = 500 if long_run else max(count // 10, 10)
+            reqs = W.serving_requests(warm + count, len(graphs), seed=3001 + int(100 * f))
+            arrivals = np.cumsum(np.random.default_rng(4000 + int(100 * f)).exponential(1.0 / rate, len(reqs)))
+            res, el = run(reqs, arrivals)
+            meas = sorted(r for r in res if r[0] >= warm)
             lat = np.array([m[1] for m in meas])
+            inner = np.array([m[4] for m in meas])
+            lag = np.array([m[5] for m in meas])
             solves = sum(m[2] for m in meas)
+            span = arrivals[-1] - arrivals[warm] if len(arrivals) > warm + 1 else el
             levels[f"{f:.2f}"] = {"offered_requests_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
                                   "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-                                  "solves_per_s": solves / el, "measured_requests": len(meas),
+                                  "max_ms": float(lat.max()),
+                                  "server_p50_ms": float(np.percentile(inner, 50)),
+                                  "server_p99_ms": float(np.percentile(inner, 99)),
+                                  "submit_lag_p99_ms": float(np.percentile(lag, 99)),
+                                  "solves_per_s": solves / max(span, 1e-9), "measured_requests": len(meas),
+                                  "warmup_requests": warm,
                                   "all_certified": all(m[3] == 0 for m in meas)}
             print(f"[bench] {name} load {f}: p50 {levels[f'{f:.2f}']['p50_ms']:.1f} ms, "
                   f"p99 {levels[f'{f:.2f}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
         srv.close()
+        if prec == fj.FJ_FP64 and args.fifo_requests > 0:
+            out["serving_fifo_fp64"] = fifo_baseline(args, fj, W, torch, graphs, pools, sat_rps)
         out[name] = {"description": "32 resident Chung-Lu graphs (n log-uniform in [1e4, 2e6], gamma U[2.1,2.8], "
                                     "mean degree U[5,40]); requests of 1-16 U[0,1] vectors, graph uniform, Poisson "
                                     "arrivals; 16-column blocks, 8 captured CG iterations per replay, "
@@ -252,16 +383,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cl4m", choices=sorted(WORKLOAD_META))
     ap.add_argument("--eps", type=float, default=1e-6)
-    ap.add_argument("--cpu-solves", type=int, default=8,
-                    help="oracle solves timed for cpu_baseline (0 = skip; 8 take about 12 s on 16 host cores)")
+    ap.add_argument("--cpu-solves", type=int, default=5,
+                    help="oracle solves timed for cpu_baseline, median reported (0 = skip; 5 take about 8 s on 16 "
+                         "host cores, plus a warm-up and one 1-thread solve)")
     ap.add_argument("--batched-steps", type=int, default=3,
                     help="timed k=64 batched calls on the 1M-node graph (0 = skip that form)")
     ap.add_argument("--two-solve-steps", type=int, default=3,
                     help="timed FJ_TWO_SOLVE calls (Algorithm 1 as printed) on the main workload (0 = skip)")
     ap.add_argument("--dynamics-steps", type=int, default=3000,
                     help="step cap of the FJ dynamics form (0 = skip it)")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--small-configs", type=int, default=1,
+                    help="also time the 10K-node BA and 1M-node Chung-Lu workloads (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests per load level of the serving form (0 = skip it)")
+    ap.add_argument("--serve-requests-long", type=int, default=10000,
+                    help="measured requests (after 500 warm-up) of the FP64 server at 0.5x saturation")
+    ap.add_argument("--fifo-requests", type=int, default=300,
+                    help="measured requests per level of the plain FP64 FIFO baseline (0 = skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -469,25 +607,50 @@ def main():
         }
         print(f"[bench] dynamics: {dinfo['iters']} steps in {t_dyn:.3f}s", file=sys.stderr, flush=True)
         del z_dyn, ws
+    if args.small_configs:
+        result["forms"].update(small_configs_form(args, fj, W, torch, dev))
     if args.batched_steps > 0:
         result["forms"].update(batched_forms(args, fj, W, torch, dev))
     if args.serve_requests > 0:
         result["forms"].update(serving_form(args, fj, W, torch, dev))
 
     if args.cpu_solves > 0:
+        import statistics
         from oracle import sparse as O
-        t0 = time.perf_counter()
-        for _ in range(args.cpu_solves):
-            z, oinfo = O.solve(g, s, rtol=spec["rtol"] if spec["rtol"] > 0 else args.eps * 1e-2)
+        rtol_gpu = spec["rtol"] if spec["rtol"] > 0 else args.eps * 1e-2
+
+        def cpu_solve():
+            t0 = time.perf_counter()
+            z, _ = O.solve(g, s, rtol=rtol_gpu)
             O.indices_at(g, s, z)
-        t_cpu = time.perf_counter() - t0
+            return time.perf_counter() - t0
+
+        cpu_solve()  # warm-up
+        times = [cpu_solve() for _ in range(args.cpu_solves)]
+        med = statistics.median(times)
+        one_thread = None
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="openmp"):
+                one_thread = cpu_solve()
+        except Exception as exc:  # noqa: BLE001 - the 1-thread time is a report, not a requirement
+            print(f"[bench] 1-thread oracle time skipped: {exc}", file=sys.stderr, flush=True)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         result["cpu_baseline"] = {
-            "value": args.cpu_solves / t_cpu,
+            "value": 1.0 / med,
             "unit": "solves/s",
             "cores": O.threads(),
             "kind": "oracle",
-            "sample": f"{args.cpu_solves} full oracle solves (FP64 Jacobi-PCG in C/OpenMP, same graph and s, "
-                      f"same first-pass residual target) plus the index definitions",
+            "sample": f"median of {args.cpu_solves} full oracle solves after 1 warm-up (FP64 Jacobi-PCG in "
+                      f"C/OpenMP, same graph and s, same first-pass residual target) plus the index definitions",
+            "seconds_per_solve_runs": times,
+            "cpu_model": model,
+            "one_thread_solves_per_s": (1.0 / one_thread) if one_thread else None,
         }
         t0 = time.perf_counter()
         ref, _, oinfo = O.indices(g, s)  # tight oracle (relative residual 1e-13) for the error report
