@@ -141,14 +141,39 @@ def batched_forms(args, fj, W, torch, dev):
             "spmm_default_shape_avg_launch_ms": untuned,
         }
         print(f"[bench] {name}: {1e3 * el:.1f} ms per call", file=sys.stderr, flush=True)
+    # O'Leary's block CG on the same 64 vectors (one shared Krylov space)
+    o = fj.make_opts(eps=args.eps, flags=fj.FJ_BLOCK_CG)
+    po = fj.make_opts(eps=args.eps, flags=fj.FJ_BLOCK_CG | fj.FJ_PROFILE)
+    ws = G.workspace(64, o)
+    fj.fj_indices(G, Sd, o, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = 0.0
+    for _ in range(args.batched_steps):
+        vals, infos, rc = fj.fj_indices(G, Sd, po, ws=ws, check=False)
+        ms += infos[0].ms_spmv
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.batched_steps
+    out["batched64_block_cg"] = {
+        "description": "k=64 opinion vectors of the 1M-node Chung-Lu graph per call, FP64 block CG (one Krylov "
+                       "space shared by the 64 columns, A-orthonormal search block, k x k products on the matrix "
+                       "cores)",
+        "value": 64.0 / el, "unit": "solves/s", "ms_per_call": 1e3 * el,
+        "all_certified": bool(rc == fj.FJ_OK), "iters": infos[0].iters, "passes": infos[0].passes,
+        "per_column_cg_iters_max": out["batched64_fp64"]["iters_max"],
+        "spmm_ms_per_call": ms / args.batched_steps,
+    }
+    print(f"[bench] batched64_block_cg: {1e3 * el:.1f} ms per call, {infos[0].iters} iterations", file=sys.stderr,
+          flush=True)
     # per-index error against the oracle for two sampled columns (a uniform and
     # a Pareto one) of each batched form
     if args.cpu_solves > 0:
         from oracle import sparse as O
         for c in (0, 42):
             ref, _, _ = O.indices(g, S[:, c].copy())
-            for name, prec in (("batched64_fp64", fj.FJ_FP64), ("batched64_mixed", fj.FJ_MIXED)):
-                vals, _, _ = fj.fj_indices(G, Sd, fj.make_opts(eps=args.eps, precision=prec))
+            for name, prec, fl in (("batched64_fp64", fj.FJ_FP64, 0), ("batched64_mixed", fj.FJ_MIXED, 0),
+                                   ("batched64_block_cg", fj.FJ_FP64, fj.FJ_BLOCK_CG)):
+                vals, _, _ = fj.fj_indices(G, Sd, fj.make_opts(eps=args.eps, precision=prec, flags=fl))
                 out[name].setdefault("rel_err_vs_oracle_sampled", {})[f"column_{c}"] = {
                     k: abs(vals[c][k] - ref[k]) / abs(ref[k]) for k in fj.INDEX_NAMES}
     # the plain comparison: the same 64 vectors one at a time in FP64
@@ -164,7 +189,7 @@ def batched_forms(args, fj, W, torch, dev):
     el = time.perf_counter() - t0
     out["sequential64_fp64"] = {"description": "the same 64 vectors, one fp64 call each",
                                 "value": 64.0 / el, "unit": "solves/s", "ms_total": 1e3 * el}
-    for name in ("batched64_fp64", "batched64_mixed"):
+    for name in ("batched64_fp64", "batched64_mixed", "batched64_block_cg"):
         out[name]["speedup_vs_sequential_fp64"] = out[name]["value"] / out["sequential64_fp64"]["value"]
     del G
     torch.cuda.empty_cache()

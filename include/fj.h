@@ -98,6 +98,12 @@ typedef struct fj_csr {
                                   blocks of I + L on a heavy-edge matching made by fj_prepare
                                   (z_i = c1_i r_i + c2_i r_j for a pair i, j): fewer iterations, most on
                                   graphs whose edge weights spread widely */
+#define FJ_BLOCK_CG      256u  /* k >= 2 opinion vectors, FJ_FP64: O'Leary's block CG, one Krylov space shared by
+                                  the columns of each block of up to 64 (at least 16 wide: narrower blocks are
+                                  padded), its search block kept A-orthonormal; the k x k products run on the
+                                  matrix cores. By default (and in the server) every column runs its own CG, so
+                                  a column's result does not depend on the others; with this flag it does.
+                                  Not with FJ_TWO_SOLVE or FJ_WARM_START */
 
 typedef struct fj_opts {
     double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */

@@ -29,6 +29,7 @@
 #include "fj_guard.hpp"
 #include "fj_kernels.hpp"
 #include "fj_batched.hpp"
+#include "fj_blockcg.hpp"
 
 using namespace fj;
 
@@ -101,6 +102,7 @@ struct WsLayout {
     size_t z32, mq32;           // the same for the FP32 inner solve of FJ_MIXED
     size_t x32, r32, p32, q32;  // FP32 vectors of the inner solve (FJ_MIXED only)
     size_t sblk;                // FJ_TWO_SOLVE: the block [s, s - mean(s)]
+    size_t zb, gpart, gm, wm, cm, zmean;  // FJ_BLOCK_CG: Z block, Gram partials, KB x KB matrices, column data
     size_t part, ctrl, total;   // partial sums; control blocks (outer kp, inner kp)
 };
 
@@ -112,8 +114,10 @@ int padded_columns(int k) {
 
 // Columns handled by one batched solve: a single right-hand side runs alone
 // (kp = 1) unless Algorithm 1 is asked for literally (two columns); more than
-// KMAX columns are solved KMAX at a time.
+// KMAX columns are solved KMAX at a time. Block CG works on blocks of at
+// least 16 columns (its KB x KB products use 16 x 16 matrix-core tiles).
 int block_columns(int k, uint32_t flags) {
+    if (flags & FJ_BLOCK_CG) return std::max(16, padded_columns(std::min(k, KMAX)));
     if (k == 1) return (flags & FJ_TWO_SOLVE) ? 2 : 1;
     return padded_columns(std::min(k, KMAX));
 }
@@ -148,6 +152,15 @@ WsLayout ws_layout(const fj_csr* g, int k, int precision, uint32_t flags) {
     if (k == 1 && (flags & FJ_TWO_SOLVE)) {
         L.sblk = off;
         off += align_up(sizeof(double) * 2 * static_cast<size_t>(g->n));
+    }
+    if (flags & FJ_BLOCK_CG) {
+        const size_t kk = static_cast<size_t>(L.kp) * L.kp;
+        L.zb = off; off += v64;
+        L.gpart = off; off += align_up(sizeof(double) * GRAM_G * 2 * kk);
+        L.gm = off; off += align_up(sizeof(double) * 2 * kk);  // [P^T Q, P^T R], or Q^T Z
+        L.wm = off; off += align_up(sizeof(double) * kk);      // W = (P^T Q)^+
+        L.cm = off; off += align_up(sizeof(double) * (kk + 2 * L.kp));  // alpha or beta, then column totals
+        L.zmean = off; off += align_up(sizeof(double) * 2 * L.kp);
     }
     L.part = off; off = align_up(off + sizeof(double) * GMAX * std::max(NPART, BPART * L.kp));
     L.ctrl = off; off = align_up(off + sizeof(Ctrl) * 2 * static_cast<size_t>(L.kp));
@@ -258,6 +271,12 @@ bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % ALIGN) ==
 
 int check_opts(const fj_opts* o) {
     if (!o) return FJ_ERR_INVALID_ARG;
+    if ((o->flags & FJ_BLOCK_CG) &&
+        (o->precision != FJ_FP64 || (o->flags & (FJ_TWO_SOLVE | FJ_WARM_START)))) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "FJ_BLOCK_CG needs FJ_FP64 and neither FJ_TWO_SOLVE nor FJ_WARM_START");
+        return FJ_ERR_INVALID_ARG;
+    }
     if (!(o->eps > 0.0 && o->eps < 0.5)) return FJ_ERR_INVALID_ARG;
     if (!(o->rtol >= 0.0 && o->rtol < 1.0)) return FJ_ERR_INVALID_ARG;
     if (o->max_iter < 0 || o->reserved != 0) return FJ_ERR_INVALID_ARG;
@@ -983,6 +1002,10 @@ struct Batched {
     bool tune = true;
     int grid_vec = 1;
     SpmmChoice ch64{1, 0}, ch32{1, 0};  // grid 0: not chosen yet
+    // FJ_BLOCK_CG (FP64, KB >= 16): the shared-Krylov iteration and its buffers
+    bool block = false;
+    double *Zb = nullptr, *gpart = nullptr, *Gm = nullptr, *Wm = nullptr, *Cm = nullptr, *zmean = nullptr;
+    int grid_mul = 1;
     static constexpr uint64_t ALL = KB >= 64 ? ~0ull : ((1ull << KB) - 1ull);
 
     int setup() {
@@ -1020,8 +1043,89 @@ struct Batched {
         return FJ_OK;
     }
 
+    // One step of block CG (see fj_blockcg.hpp): Q = A P; W = (P^T Q)^+ and
+    // alpha = W P^T R; X += P alpha, R -= Q alpha; Z = Pi M^-1 R; beta =
+    // -W Q^T Z; P = (Z + P beta) D.
+    int block_iteration(BState<double>& S) {
+        if constexpr (KB >= 16) {
+            const int n = c.g->n;
+            int rc = with_graph(c.g, [&](auto G) -> int {
+                using Vc = typename decltype(G)::value_type;
+                if (ch64.grid == 0)
+                    if (int e = Spmm<Vc, double, KB>::choose(c.g, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q,
+                                                             S.part, tune, &ch64))
+                        return e;
+                if (c.profile) {
+                    if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
+                    HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
+                }
+                if (int e = Spmm<Vc, double, KB>::launch(ch64, c.st, G, c.desc(), c.pl.K, S.P, S.R, c.minv(), S.Q,
+                                                         S.part, S.ctrl))
+                    return e;
+                if (c.profile) {
+                    HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
+                    ++c.n_prof;
+                }
+                return FJ_OK;
+            });
+            if (rc) return rc;
+            constexpr int KK = KB * KB;
+            // [P^T Q, P^T R] in one pass over P, Q, R
+            k_gram<KB, 2><<<GRAM_G, WG, 0, c.st>>>(n, S.P, S.Q, S.R, gpart, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_gram_fin<<<2 * KK / 16, WG, 0, c.st>>>(GRAM_G, 2 * KK, gpart, 1.0, Gm, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_bcg_chol<KB><<<1, WG, 0, c.st>>>(Gm, Wm, Cm, S.ctrl);  // W and alpha (in Cm)
+            HIPCHK(hipGetLastError());
+            k_block_mul<KB><<<grid_mul, WG, 0, c.st>>>(n, S.P, Cm, 1.0, S.X, 1.0, nullptr, nullptr, S.X, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_block_mul<KB><<<grid_mul, WG, 0, c.st>>>(n, S.Q, Cm, -1.0, S.R, 1.0, nullptr, nullptr, S.R, S.ctrl);
+            HIPCHK(hipGetLastError());
+            if (int e = precondition(S, 0)) return e;
+            k_gram<KB, 1><<<GRAM_G, WG, 0, c.st>>>(n, S.Q, Zb, nullptr, gpart, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_gram_fin<<<KK / 16, WG, 0, c.st>>>(GRAM_G, KK, gpart, 1.0, Gm, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_small_mul<KB><<<1, WG, 0, c.st>>>(Wm, Gm, -1.0, Cm, S.ctrl);  // beta
+            HIPCHK(hipGetLastError());
+            k_block_mul<KB><<<grid_mul, WG, 0, c.st>>>(n, S.P, Cm, 1.0, Zb, 1.0, zmean, zmean + KB, S.P, S.ctrl);
+            HIPCHK(hipGetLastError());
+        }
+        return FJ_OK;
+    }
+
+    // Z = M^-1 R, its column means and the residual norms; the block's
+    // stopping test (first = 1: a start, the iteration count stays).
+    int precondition(BState<double>& S, int first) {
+        if constexpr (KB >= 16) {
+            const int n = c.g->n;
+            k_bcg_precond<KB><<<grid_vec, WG, 0, c.st>>>(n, S.R, c.minv(), Zb, S.part, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_bcg_colsum<KB><<<KB, WG, 0, c.st>>>(grid_vec, S.part, Cm + KB * KB, S.ctrl);
+            HIPCHK(hipGetLastError());
+            k_bcg_decide<KB><<<1, 64, 0, c.st>>>(n, Cm + KB * KB, first, zmean, S.ctrl);
+            HIPCHK(hipGetLastError());
+        }
+        return FJ_OK;
+    }
+
+    // The first search block of a block CG pass: Z = Pi M^-1 R and P = Z D.
+    int block_start(BState<double>& S) {
+        if constexpr (KB >= 16) {
+            k_bcg_start<KB><<<1, 64, 0, c.st>>>(S.ctrl);
+            HIPCHK(hipGetLastError());
+            if (int e = precondition(S, 1)) return e;
+            k_block_mul<KB><<<grid_mul, WG, 0, c.st>>>(c.g->n, nullptr, Cm, 1.0, Zb, 1.0, zmean, zmean + KB, S.P,
+                                                      S.ctrl);
+            HIPCHK(hipGetLastError());
+        }
+        return FJ_OK;
+    }
+
     template <typename T>
     int iteration(BState<T>& S) {
+        if constexpr (std::is_same<T, double>::value)
+            if (block) return block_iteration(S);
         int grid_win = 1;
         int rc = with_graph(c.g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
@@ -1223,6 +1327,42 @@ struct Batched {
         return FJ_OK;
     }
 
+    // FJ_BLOCK_CG: the passes of solve_fp64 with block CG inside; every pass
+    // runs to the residual target (no index-estimate stop), then the
+    // epilogue certifies each column and uncertified columns restart from
+    // their true residuals (the whole block iterates again).
+    int solve_block_cg(BState<double>& S, const double* src, int64_t lds, int k, int kcheck, const fj_opts& o,
+                       bool want_indices, const unsigned* which, Ctrl* cs, int* status, int* passes) {
+        const int max_iter = o.max_iter > 0 ? o.max_iter : 2000;
+        const bool range_check = !(o.flags & FJ_NO_RANGE_CHECK);
+        double rtol[KMAX], prev_rho[KMAX];
+        for (int col = 0; col < KMAX; ++col) {
+            rtol[col] = rtol_target(o);
+            prev_rho[col] = INFINITY;
+            if (col < k) status[col] = FJ_ERR_NOT_CONVERGED;
+        }
+        if (int rc = init(S, src, lds, k, kcheck, 0, ALL, rtol, max_iter, range_check, 0.0, true)) return rc;
+        HIPCHK(hipMemcpyAsync(c.hs->slot(NSLOT), S.ctrl, sizeof(Ctrl) * KB, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        for (int col = 0; col < kcheck; ++col)
+            if (c.hs->slot(NSLOT)[col].done == BAD_INPUT) return FJ_ERR_OPINION_RANGE;
+        if (int rc = block_start(S)) return rc;
+        *passes = 0;
+        for (;;) {
+            ++*passes;
+            if (int rc = run(S, k, cs)) return rc;
+            if (int rc = epilogue(S, src, lds, k, cs)) return rc;
+            const uint64_t again = triage(cs, k, o, want_indices, which, rtol, prev_rho, status, *passes >= MAX_PASSES);
+            if (!again) break;
+            for (int col = 0; col < k; ++col) prev_rho[col] = cs[col].res[5];
+            // the shared space restarts for every column from its true residual;
+            // columns already final keep their targets (their residual stays small)
+            if (int rc = init(S, src, lds, k, kcheck, 1, ALL, rtol, max_iter, range_check, 0.0, true)) return rc;
+            if (int rc = block_start(S)) return rc;
+        }
+        return FJ_OK;
+    }
+
     // FJ_MIXED for every column: FP32 inner CG, FP64 refinement per column.
     int solve_mixed(BState<double>& S, BState<float>& I, const double* src, int64_t lds, int k, int kcheck,
                     const fj_opts& o, bool want_indices, const unsigned* which, Ctrl* cs, int* status, int* outer) {
@@ -1349,6 +1489,22 @@ int solve_block(Ctx& c, const WsLayout& wl, char* W, const double* S, int64_t ld
         BState<float> S32{reinterpret_cast<float*>(W + wl.x32), reinterpret_cast<float*>(W + wl.r32),
                           reinterpret_cast<float*>(W + wl.p32), reinterpret_cast<float*>(W + wl.q32), ctrls + KB, part};
         rc = B.solve_mixed(S64, S32, src, ld, kk, kcheck, o, want_indices, which, cs, status, &outer);
+    } else if (o.flags & FJ_BLOCK_CG) {
+        if constexpr (KB >= 16) {
+            B.block = true;
+            B.Zb = reinterpret_cast<double*>(W + wl.zb);
+            B.gpart = reinterpret_cast<double*>(W + wl.gpart);
+            B.Gm = reinterpret_cast<double*>(W + wl.gm);
+            B.Wm = reinterpret_cast<double*>(W + wl.wm);
+            B.Cm = reinterpret_cast<double*>(W + wl.cm);
+            B.zmean = reinterpret_cast<double*>(W + wl.zmean);
+            if (int e = grid_for(k_block_mul<KB>, (static_cast<int64_t>(c.g->n) + 16 * NWAVE - 1) / (16 * NWAVE),
+                                 &B.grid_mul))
+                return e;
+            rc = B.solve_block_cg(S64, src, ld, kk, kcheck, o, want_indices, which, cs, status, &passes);
+        } else {
+            return FJ_ERR_INVALID_ARG;  // block_columns gives at least 16
+        }
     } else {
         rc = B.solve_fp64(S64, src, ld, kk, kcheck, o, want_indices, which, cs, status, &passes);
     }
@@ -1769,6 +1925,7 @@ int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int6
         if (int rc = check_graph_args(g)) return rc;
         if (int rc = check_opts(opts)) return rc;
         if (k < 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
+        if ((opts->flags & FJ_BLOCK_CG) && k < 2) return FJ_ERR_INVALID_ARG;
         if ((opts->flags & FJ_WARM_START) && (k != 1 || (opts->flags & FJ_TWO_SOLVE))) {
             std::snprintf(g_last_error, sizeof g_last_error, "FJ_WARM_START needs k = 1 without FJ_TWO_SOLVE");
             return FJ_ERR_INVALID_ARG;
@@ -1788,6 +1945,7 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
         if (int rc = check_opts(opts)) return rc;
         if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
         if (g->n == 0) return FJ_ERR_INVALID_ARG;
+        if ((opts->flags & FJ_BLOCK_CG) && k < 2) return FJ_ERR_INVALID_ARG;
         if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
             return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
         return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);

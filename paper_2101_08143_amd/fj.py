@@ -40,6 +40,7 @@ FJ_FP64, FJ_MIXED = 0, 1
 FJ_TWO_SOLVE, FJ_NO_RANGE_CHECK, FJ_VALIDATE_GRAPH, FJ_PROFILE, FJ_NO_TUNE, FJ_WARM_START, FJ_ZERO_START = \
     1, 2, 4, 8, 16, 32, 64
 FJ_DIAG_PRECOND = 128
+FJ_BLOCK_CG = 256
 
 INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
 

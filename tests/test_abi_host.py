@@ -207,3 +207,20 @@ def test_info_layout_matches_header():
     body = re.search(r"typedef struct fj_info \{(.*?)\} fj_info;", src, flags=re.S).group(1)
     fields = re.findall(r"(\w+)(?:\[\d+\])?;", body)
     assert fields == [f[0] for f in fj.fj_info._fields_]
+
+
+def test_block_cg_argument_errors(lib):
+    """FJ_BLOCK_CG is FP64 only, needs k >= 2, and excludes FJ_TWO_SOLVE and
+    FJ_WARM_START (checked before any device work)."""
+    csr = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=None, val_type=fj.FJ_VAL_UNIT)
+    out = (fj.fj_indices_t * 4)()
+    for prec, flags, k in ((fj.FJ_MIXED, fj.FJ_BLOCK_CG, 4), (fj.FJ_FP64, fj.FJ_BLOCK_CG, 1),
+                           (fj.FJ_FP64, fj.FJ_BLOCK_CG | fj.FJ_TWO_SOLVE, 4),
+                           (fj.FJ_FP64, fj.FJ_BLOCK_CG | fj.FJ_WARM_START, 4)):
+        o = fj.make_opts(precision=prec, flags=flags)
+        rc = lib.fj_indices(ctypes.byref(csr), ctypes.c_void_p(256), k, ctypes.c_void_p(256), k,
+                            ctypes.byref(o), ctypes.c_void_p(256), 1 << 30, None, out, None)
+        assert rc == fj.FJ_ERR_INVALID_ARG, (prec, flags, k)
+    o = fj.make_opts(flags=fj.FJ_BLOCK_CG)
+    assert lib.fj_workspace_bytes(ctypes.byref(csr), 3, ctypes.byref(o)) > \
+        lib.fj_workspace_bytes(ctypes.byref(csr), 3, ctypes.byref(fj.make_opts()))
