@@ -393,7 +393,8 @@ def serving_form(args, fj, W, torch, dev):
             out["serving_fifo_fp64"] = fifo_baseline(args, fj, W, torch, graphs, pools, sat_rps)
         out[name] = {"description": "32 resident Chung-Lu graphs (n log-uniform in [1e4, 2e6], gamma U[2.1,2.8], "
                                     "mean degree U[5,40]); requests of 1-16 U[0,1] vectors, graph uniform, Poisson "
-                                    "arrivals; 16-column blocks, 8 captured CG iterations per replay, "
+                                    "arrivals; 16-column blocks, 8 captured CG iterations per replay (2 for graphs "
+                                    "with n + nnz >= 2^22, which share 2 streams; the others share a third), "
                                     + ("FP64" if prec == fj.FJ_FP64 else "FP32 inner CG with FP64 refinement"),
                      "setup_s": t_gen, "saturation": sat, "load_levels": levels}
     del graphs, pools

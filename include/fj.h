@@ -292,8 +292,8 @@ int fj_indices_noalloc(const fj_csr *g, const void *plan, int32_t k, const doubl
  * columns of its graph's block in arrival order as soon as columns free up,
  * a request possibly in several pieces, while the other columns keep
  * iterating (continuous batching). Blocks replay HIP graphs of captured CG
- * iterations on one stream per graph, so different graphs overlap on the
- * device. Every column is certified to eps exactly as fj_indices would, and
+ * iterations on lanes (streams) by graph size, so different graphs overlap
+ * on the device and small graphs' work does not queue behind large graphs'. Every column is certified to eps exactly as fj_indices would, and
  * its result does not depend on the other requests in its block.
  * The server is driven by one host thread calling fj_server_step.
  */
@@ -307,6 +307,13 @@ typedef struct fj_server_opts {
     double eps;                 /* certified relative error of every index, in (0, 1/2) */
     int32_t max_iter;           /* CG iterations per column over all passes; 0 = 2000 */
     int32_t precision;          /* FJ_FP64, or FJ_MIXED (FP32 inner CG, FP64 refinement, as fj_indices) */
+    int32_t large_lanes;        /* streams shared by the blocks of large graphs, 1..8; 0 = 2. One more stream
+                                   carries every other graph, so short work never waits in a hardware queue
+                                   behind a large graph's replay */
+    int32_t large_iters_per_replay;  /* CG iterations per replay for large graphs (shorter replays let requests
+                                        join sooner); 0 = max(1, iters_per_replay / 4) */
+    int32_t reserved;                /* must be 0 */
+    int64_t large_entries;      /* a graph with n + nnz >= this is large; 0 = 2^22 */
 } fj_server_opts;
 
 typedef struct fj_server_done {

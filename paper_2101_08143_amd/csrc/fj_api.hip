@@ -2000,11 +2000,30 @@ int fj_server_create(const fj_server_opts* opts, fj_server** out) {
         if (opts->iters_per_replay < 1 || opts->iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
         if (!(opts->eps > 0.0 && opts->eps < 0.5) || opts->max_iter < 0) return FJ_ERR_INVALID_ARG;
         if (!opts->arena || !aligned(opts->arena) || opts->arena_bytes == 0) return FJ_ERR_WORKSPACE;
+        if (opts->large_lanes < 0 || opts->large_lanes > 8 || opts->large_entries < 0) return FJ_ERR_INVALID_ARG;
+        if (opts->large_iters_per_replay < 0 || opts->large_iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
+        if (opts->reserved != 0) return FJ_ERR_INVALID_ARG;
         Server* s = new Server();
         s->o = *opts;
+        if (s->o.large_lanes == 0) s->o.large_lanes = 2;
+        if (s->o.large_entries == 0) s->o.large_entries = int64_t(1) << 22;
+        if (s->o.large_iters_per_replay == 0) s->o.large_iters_per_replay = std::max(1, s->o.iters_per_replay / 4);
         s->arena = static_cast<char*>(opts->arena);
         s->free_list[0] = opts->arena_bytes / ALIGN * ALIGN;
-        if (int rc = current_device(&s->device)) {
+        int rc = current_device(&s->device);
+        // the lanes: large_lanes streams for large graphs, then one for the others
+        for (int l = 0; rc == FJ_OK && l <= s->o.large_lanes; ++l) {
+            hipStream_t ls = nullptr;
+            const hipError_t e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                set_error("fj_server_create: hipStreamCreateWithFlags", e);
+                rc = FJ_ERR_HIP;
+                break;
+            }
+            s->lanes.push_back(ls);
+        }
+        if (rc) {
+            for (hipStream_t ls : s->lanes) (void)hipStreamDestroy(ls);
             delete s;
             return rc;
         }
@@ -2022,12 +2041,13 @@ int fj_server_destroy(fj_server* srv) {
             if (G.blk)
                 if (int rc = release_block(*s, G)) status = rc;
             if (G.dep) (void)hipEventDestroy(G.dep);
-            if (G.st) {
-                const hipError_t e = hipStreamDestroy(G.st);
-                if (e != hipSuccess && status == FJ_OK) {
-                    set_error("hipStreamDestroy", e);
-                    status = FJ_ERR_HIP;
-                }
+        }
+        for (hipStream_t ls : s->lanes) {
+            hipError_t e = hipStreamSynchronize(ls);
+            if (e == hipSuccess) e = hipStreamDestroy(ls);
+            if (e != hipSuccess && status == FJ_OK) {
+                set_error("fj_server_destroy: lane stream", e);
+                status = FJ_ERR_HIP;
             }
         }
         delete s;
@@ -2047,15 +2067,17 @@ int fj_server_add_graph(fj_server* srv, const fj_csr* g, const void* plan, int32
         G.g = *g;
         G.plan = plan;
         G.pl = plan_layout(g);
-        HIPCHK(hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking));
+        // a large graph shares one of the large lanes (in turn), any other the last lane
+        const int nl = s->o.large_lanes;
+        G.large = static_cast<int64_t>(g->n) + g->nnz >= s->o.large_entries;
+        G.st = G.large ? s->lanes[(s->n_large++) % nl] : s->lanes[nl];
         hipError_t e = hipEventCreateWithFlags(&G.dep, hipEventDisableTiming);
-        // the graph's stream waits for the caller's work so far (fj_prepare of this plan)
+        // the graph's work waits for the caller's work so far (fj_prepare of this plan)
         if (e == hipSuccess) e = hipEventRecord(G.dep, static_cast<hipStream_t>(stream));
         if (e == hipSuccess) e = hipStreamWaitEvent(G.st, G.dep, 0);
         if (e != hipSuccess) {
-            set_error("fj_server_add_graph: stream or event", e);
+            set_error("fj_server_add_graph: event", e);
             if (G.dep) (void)hipEventDestroy(G.dep);
-            (void)hipStreamDestroy(G.st);
             return FJ_ERR_HIP;
         }
         s->graphs.push_back(std::move(G));  // capacity reserved: does not throw

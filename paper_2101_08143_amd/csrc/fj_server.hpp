@@ -11,8 +11,14 @@
 // (graph, k opinion vectors) enter free columns of the block in arrival
 // order, at an iteration boundary, while the other columns keep iterating.
 // Each block replays a HIP graph of `iters` captured CG iterations (FP32
-// inner iterations for FJ_MIXED) on its own stream, so blocks of different
-// graphs overlap on the device. After each replay the host reads the control
+// inner iterations for FJ_MIXED) on its graph's lane: large graphs (n + nnz
+// at least large_entries) share large_lanes streams in turn, all other
+// graphs one more stream. A hardware queue runs its work in order, so with
+// one stream per graph a small graph's short replay could wait behind a
+// large graph's long one sharing its queue; the lanes keep short and long
+// work on different queues, and blocks on different lanes overlap. Large
+// graphs also replay fewer iterations at a time (large_iters_per_replay), so
+// that requests join their blocks sooner. After each replay the host reads the control
 // blocks; columns whose CG stopped are finished by the batched epilogue
 // (after the FP64 correction z += ||r|| d for FJ_MIXED), then retired
 // (certified, or final) or restarted from their true residual with a
@@ -68,8 +74,9 @@ struct ServerGraph {
     fj_csr g{};
     const void* plan = nullptr;
     PlanLayout pl{};
-    hipStream_t st = nullptr;
-    hipEvent_t dep = nullptr;  // orders the stream after the caller's producer of plan / S
+    hipStream_t st = nullptr;  // the graph's lane (shared with other graphs of its size class)
+    bool large = false;        // n + nnz >= large_entries: a large lane and shorter replays
+    hipEvent_t dep = nullptr;  // orders the lane after the caller's producer of plan / S
     std::deque<uint64_t> queue;
     ServerBlock* blk = nullptr;
 };
@@ -81,6 +88,8 @@ struct Server {
     std::vector<ServerGraph> graphs;
     std::unordered_map<uint64_t, ServerRequest> requests;
     std::deque<uint64_t> completed;
+    std::vector<hipStream_t> lanes;  // large_lanes streams for large graphs, then one for the others
+    int n_large = 0;                 // large graphs so far (they take the large lanes in turn)
     uint64_t next_id = 1;
     uint64_t tick = 0;  // scheduling steps so far
     int device = 0;
@@ -196,7 +205,8 @@ struct ServerOps {
                 return e;
             b->grid_win = ch.grid;
             HIPCHK(hipStreamBeginCapture(G.st, hipStreamCaptureModeThreadLocal));
-            for (int t = 0; t < s.o.iters_per_replay; ++t) {
+            const int iters = G.large ? s.o.large_iters_per_replay : s.o.iters_per_replay;
+            for (int t = 0; t < iters; ++t) {
                 if (int e = Spmm<Vc, T, KB>::launch(ch, G.st, Gc, desc, G.pl.K, P, R, minv, Q, b->part, cg)) {
                     hipGraph_t dropped = nullptr;
                     (void)hipStreamEndCapture(G.st, &dropped);
