@@ -26,6 +26,7 @@ METRIC = "FJ index solves/sec at 1e-6 rel err; achieved HBM GB/s; serving p50/p9
 PEAK_HBM_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["paper_2101_08143_amd/csrc/fj_kernels.hpp", "paper_2101_08143_amd/csrc/fj_batched.hpp",
+                  "paper_2101_08143_amd/csrc/fj_blockcg.hpp",
                   "paper_2101_08143_amd/csrc/fj_server.hpp", "paper_2101_08143_amd/csrc/fj_api.hip", "include/fj.h"]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_cl4m.json")
 
@@ -136,7 +137,8 @@ def batched_forms(args, fj, W, torch, dev):
             "spmm_working_launches": working,
             "spmm_achieved_GBs": b / (avg * 1e-3) / 1e9 if avg > 0 else None,
             "spmm_algorithmic_bytes_per_launch": b,
-            "spmm_tuned_shape": {"columns_per_lane": shape[0], "grid": shape[1], "split_rows": bool(shape[2])}
+            "spmm_tuned_shape": {"columns_per_lane": shape[0], "grid": shape[1], "split_rows": bool(shape[2]),
+                                 "column_passes": shape[3]}
             if shape else None,
             "spmm_default_shape_avg_launch_ms": untuned,
         }

@@ -204,23 +204,27 @@ double fj_apriori_delta(int64_t n, double w_min, double w_max, double sbar_norm,
  * and nnz), block width kb (2, 4, ..., 64) and precision (FJ_FP64: FP64
  * vectors; FJ_MIXED: the FP32 inner vectors) on the current device:
  * *cpl columns per lane (kb / *cpl lanes work together), *grid workgroups,
- * and *split = 1 when each window's rows and entries are split evenly over
- * the lane groups (0: one lane group per row). The first batched solve of
- * such a combination times every candidate shape once and keeps the fastest
- * for the life of the process. Returns FJ_ERR_INVALID_ARG when nothing has
- * been tuned for it yet.
+ * *split = 1 when each window's rows and entries are split evenly over
+ * the lane groups (0: one lane group per row), and *passes column passes
+ * over the CSR (1; or 2 or 4 for 32- and 64-column blocks, one lane group per
+ * row: each pass gathers kb / *passes values per neighbour, so the gathered
+ * part of a wide block stays in the 256 MB Infinity Cache). The first batched
+ * solve of such a combination times every candidate shape once and keeps
+ * the fastest for the life of the process. Returns FJ_ERR_INVALID_ARG when
+ * nothing has been tuned for it yet.
  */
 int fj_spmm_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t *cpl, int32_t *grid,
-                   int32_t *split);
+                   int32_t *split, int32_t *passes);
 
 /*
  * Pin the SpMM launch shape for this graph, kb and precision on the current
  * device instead of tuning it (for instance to reproduce another process's
  * choice bit for bit): cpl in {1, 2, 4} dividing kb, grid in [1, 4096],
- * split 0 or 1. Later batched solves and servers created afterwards use it.
+ * split 0 or 1, passes 1, or 2 or 4 with split 0, cpl <= 2 and at least 16
+ * columns per pass. Later batched solves and servers created afterwards use it.
  */
 int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid,
-                       int32_t split);
+                       int32_t split, int32_t passes);
 
 /*
  * Measurement aid (not part of any solve): the bare gather of an SpMV over

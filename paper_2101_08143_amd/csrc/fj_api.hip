@@ -878,7 +878,17 @@ struct SpmmKey {
 struct SpmmChoice {
     int cpl = 1, grid = 1;
     bool split = true;  // merge-path item split over lane groups, or one group per row
+    int passes = 1;     // column passes (rows design): 2 or 4 for 32- and 64-column blocks
 };
+
+// A shape the SpMM can run: column passes need the rows design, a pass of at
+// least 16 columns (2 or 4 of them) and CPL dividing the pass width.
+bool spmm_shape_ok(int kb, int cpl, bool split, int passes) {
+    if (cpl != 1 && cpl != 2 && cpl != 4) return false;
+    if (passes == 1) return kb % cpl == 0;
+    if (passes != 2 && passes != 4) return false;
+    return !split && cpl <= 2 && kb / passes >= 16 && (kb / passes) % cpl == 0;
+}
 std::mutex g_tune_mu;
 std::map<SpmmKey, SpmmChoice> g_tune;
 
@@ -896,7 +906,16 @@ struct Spmm {
         return split ? grid_for(k_spmm_cg<Vc, T, KB, CPL, true>, K, grid)
                      : grid_for(k_spmm_cg<Vc, T, KB, CPL, false>, K, grid);
     }
-    static int full_grid(int cpl, bool split, int K, int* grid) {
+    // grid of a column pass of KB / NP columns (rows design)
+    template <int NP, int CPL>
+    static int grid_pass(int K, int* grid) {
+        if constexpr (NP > 1 && KB / NP >= 16 && (KB / NP) % CPL == 0)
+            return grid_for(k_spmm_cg<Vc, T, KB / NP, CPL, false, KB>, K, grid);
+        return FJ_ERR_INVALID_ARG;
+    }
+    static int full_grid(int cpl, bool split, int K, int* grid, int passes = 1) {
+        if (passes == 2) return cpl == 2 ? grid_pass<2, 2>(K, grid) : grid_pass<2, 1>(K, grid);
+        if (passes == 4) return cpl == 2 ? grid_pass<4, 2>(K, grid) : grid_pass<4, 1>(K, grid);
         if constexpr (KB % 4 == 0)
             if (cpl == 4) return grid_of<4>(split, K, grid);
         if constexpr (KB % 2 == 0)
@@ -911,8 +930,29 @@ struct Spmm {
         HIPCHK(hipGetLastError());
         return FJ_OK;
     }
+    // NP passes of KB / NP columns over the CSR (partials land in the KB-wide layout)
+    template <int NP, int CPL>
+    static int go_passes(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
+                         const T* P, const T* R, const float* minv, T* Q, double* part, const Ctrl* ctrl) {
+        if constexpr (NP > 1 && KB / NP >= 16 && (KB / NP) % CPL == 0) {
+            constexpr int KP = KB / NP;
+            for (int j = 0; j < NP; ++j) {
+                k_spmm_cg<Vc, T, KP, CPL, false, KB><<<ch.grid, WG, 0, st>>>(G, desc, K, P, R, minv, Q, part, ctrl,
+                                                                             j * KP);
+                HIPCHK(hipGetLastError());
+            }
+            return FJ_OK;
+        }
+        return FJ_ERR_INVALID_ARG;
+    }
     static int launch(const SpmmChoice& ch, hipStream_t st, const Csr<Vc>& G, const WinDesc* desc, int K,
                       const T* P, const T* R, const float* minv, T* Q, double* part, const Ctrl* ctrl) {
+        if (ch.passes == 2)
+            return ch.cpl == 2 ? go_passes<2, 2>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl)
+                               : go_passes<2, 1>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
+        if (ch.passes == 4)
+            return ch.cpl == 2 ? go_passes<4, 2>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl)
+                               : go_passes<4, 1>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
         if constexpr (KB % 4 == 0)
             if (ch.cpl == 4) return go<4>(ch, st, G, desc, K, P, R, minv, Q, part, ctrl);
         if constexpr (KB % 2 == 0)
@@ -946,8 +986,18 @@ struct Spmm {
                 if (!split && KB / cpl < 8) continue;  // a row per group of < 8 lanes serialises long rows
                 int full = 1;
                 if (int rc = full_grid(cpl, split, K, &full)) return rc;
-                cand.push_back({cpl, full, split});
-                if (full >= 2) cand.push_back({cpl, full / 2, split});
+                cand.push_back({cpl, full, split, 1});
+                if (full >= 2) cand.push_back({cpl, full / 2, split, 1});
+            }
+        }
+        // wide blocks: column passes keep each pass's gathered rows small
+        for (int passes : {2, 4}) {
+            for (int cpl : {1, 2}) {
+                if (!spmm_shape_ok(KB, cpl, false, passes)) continue;
+                int full = 1;
+                if (int rc = full_grid(cpl, false, K, &full, passes)) return rc;
+                cand.push_back({cpl, full, false, passes});
+                if (full >= 2) cand.push_back({cpl, full / 2, false, passes});
             }
         }
         hipEvent_t e0, e1;
@@ -1775,10 +1825,11 @@ double fj_apriori_delta(int64_t n, double w_min, double w_max, double sbar_norm,
 }
 
 int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl, int32_t* grid,
-                   int32_t* split) {
+                   int32_t* split, int32_t* passes) {
     return guarded([&]() -> int {
         if (int rc = check_graph_args(g)) return rc;
-        if (!cpl || !grid || !split || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
+        if (!cpl || !grid || !split || !passes || kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0)
+            return FJ_ERR_INVALID_ARG;
         if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
         SpmmKey key{};
         if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
@@ -1788,21 +1839,24 @@ int fj_spmm_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t* cpl,
         *cpl = it->second.cpl;
         *grid = it->second.grid;
         *split = it->second.split ? 1 : 0;
+        *passes = it->second.passes;
         return FJ_OK;
     });
 }
 
-int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid, int32_t split) {
+int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid, int32_t split,
+                       int32_t passes) {
     return guarded([&]() -> int {
         if (int rc = check_graph_args(g)) return rc;
         if (kb < 2 || kb > KMAX || (kb & (kb - 1)) != 0) return FJ_ERR_INVALID_ARG;
         if (precision != FJ_FP64 && precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
         if ((cpl != 1 && cpl != 2 && cpl != 4) || kb % cpl != 0 || grid < 1 || grid > GMAX) return FJ_ERR_INVALID_ARG;
         if (split != 0 && split != 1) return FJ_ERR_INVALID_ARG;
+        if (!spmm_shape_ok(kb, cpl, split == 1, passes)) return FJ_ERR_INVALID_ARG;
         SpmmKey key{};
         if (int rc = spmm_key(g, kb, precision == FJ_FP64 ? 8 : 4, &key)) return rc;
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        g_tune[key] = SpmmChoice{cpl, grid, split == 1};
+        g_tune[key] = SpmmChoice{cpl, grid, split == 1, passes};
         return FJ_OK;
     });
 }

@@ -148,16 +148,26 @@ __device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __r
                         }
                     }
                 }
-                for (; u < run; ++u) {
-                    const int jc = st.col[j + u];
-                    const double w = WEIGHTED ? static_cast<double>(st.w[j + u]) : 1.0;
-                    double xj[CPL];
-                    load_cols<T, CPL>(X + static_cast<int64_t>(jc) * KB + c0, xj);
+                if (u < run) {  // the last 1-3 entries of the run in one round (as in spmm_rows)
+                    int jj[4];
+                    double w[4], xj[4][CPL];
 #pragma unroll
-                    for (int q = 0; q < CPL; ++q) {
-                        const double df = xi[q] - xj[q];
-                        lin[q] += w * df;
-                        if constexpr (Acc::SQ) sq[q] += w * df * df;
+                    for (int v = 0; v < 4; ++v) {
+                        const int at = j + min(u + v, run - 1);
+                        jj[v] = st.col[at];
+                        w[v] = WEIGHTED ? static_cast<double>(st.w[at]) : 1.0;
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) load_cols<T, CPL>(X + static_cast<int64_t>(jj[v]) * KB + c0, xj[v]);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (u + v >= run) break;  // uniform over the lane group
+#pragma unroll
+                        for (int q = 0; q < CPL; ++q) {
+                            const double df = xi[q] - xj[v][q];
+                            lin[q] += w[v] * df;
+                            if constexpr (Acc::SQ) sq[q] += w[v] * df * df;
+                        }
                     }
                 }
                 j += run;
@@ -265,8 +275,9 @@ __device__ __forceinline__ void spmm_windows(const Csr<V>& g, const WinDesc* __r
 // (q = c - l*CPL). Each column's row sum runs over the row's entries in CSR
 // order whatever CPL is. A long last row is split over all groups of the
 // workgroup and combined in LDS in group order. lred must hold
-// 2 * WG * CPL doubles.
-template <typename T, typename V, typename Acc, int KB, int CPL, typename Op>
+// 2 * WG * CPL doubles. The block's rows are LDX values apart: a pass may
+// cover KB of LDX columns (X then points at the pass's first column).
+template <typename T, typename V, typename Acc, int KB, int CPL, int LDX, typename Op>
 __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __restrict__ desc, int K,
                                              const T* __restrict__ X, Op& op, double* lred) {
     static_assert(KB % CPL == 0, "CPL must divide KB");
@@ -297,7 +308,7 @@ __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __rest
                     w[u] = WEIGHTED ? shfl_d(wl, t + u, GW) : 1.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) load_cols<T, CPL>(X + static_cast<int64_t>(j[u]) * KB + c0, xj[u]);
+                for (int u = 0; u < 4; ++u) load_cols<T, CPL>(X + static_cast<int64_t>(j[u]) * LDX + c0, xj[u]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -308,16 +319,26 @@ __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __rest
                     }
                 }
             }
-            for (; t < cnt; ++t) {
-                const int j = __shfl(jl, t, GW);
-                const double w = WEIGHTED ? shfl_d(wl, t, GW) : 1.0;
-                double xj[CPL];
-                load_cols<T, CPL>(X + static_cast<int64_t>(j) * KB + c0, xj);
+            if (t < cnt) {  // the last 1-3 entries in one round: slots past the end repeat the last
+                int j[4];      // entry's address (a cached line) and are not summed
+                double w[4], xj[4][CPL];
 #pragma unroll
-                for (int q = 0; q < CPL; ++q) {
-                    const double d = xi[q] - xj[q];
-                    lin[q] += w * d;
-                    if constexpr (Acc::SQ) sq[q] += w * d * d;
+                for (int u = 0; u < 4; ++u) {
+                    const int tu = min(t + u, cnt - 1);
+                    j[u] = __shfl(jl, tu, GW);
+                    w[u] = WEIGHTED ? shfl_d(wl, tu, GW) : 1.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) load_cols<T, CPL>(X + static_cast<int64_t>(j[u]) * LDX + c0, xj[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (t + u >= cnt) break;  // uniform over the lane group
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) {
+                        const double d = xi[q] - xj[u][q];
+                        lin[q] += w[u] * d;
+                        if constexpr (Acc::SQ) sq[q] += w[u] * d * d;
+                    }
                 }
             }
         }
@@ -328,7 +349,7 @@ __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __rest
         for (int a = grp; a < d.nrs; a += NG) {
             const int i = d.r0 + a;
             double xi[CPL], lin[CPL], sq[CPL];
-            load_cols<T, CPL>(X + static_cast<int64_t>(i) * KB + c0, xi);
+            load_cols<T, CPL>(X + static_cast<int64_t>(i) * LDX + c0, xi);
 #pragma unroll
             for (int q = 0; q < CPL; ++q) lin[q] = sq[q] = 0.0;
             row_sum(g.row_ptr[i], g.row_ptr[i + 1], xi, lin, sq);
@@ -338,7 +359,7 @@ __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __rest
         if (d.long_last) {  // workgroup-uniform
             const int i = d.r1 - 1;
             double xi[CPL], lin[CPL], sq[CPL];
-            load_cols<T, CPL>(X + static_cast<int64_t>(i) * KB + c0, xi);
+            load_cols<T, CPL>(X + static_cast<int64_t>(i) * LDX + c0, xi);
 #pragma unroll
             for (int q = 0; q < CPL; ++q) lin[q] = sq[q] = 0.0;
             // group gr takes entry chunks elast + gr*GW, elast + (gr+NG)*GW, ...
@@ -368,12 +389,13 @@ __device__ __forceinline__ void spmm_rows(const Csr<V>& g, const WinDesc* __rest
 
 // Per-column workgroup sums of N accumulators: lane l of every group holds
 // the workgroup's share for columns l*CPL + q in v[a][q]; groups are added in
-// order and the result goes to part[(blockIdx.x * KB + c) * BPART + a].
+// order and the result goes to part[(blockIdx.x * LDP + coff + c) * BPART + a]
+// (LDP columns per workgroup row; a column pass writes at its offset coff).
 // C sums at a time (lred holds C * WG * CPL doubles), so that a kernel can
 // reduce through LDS it already owns.
-template <int N, int KB, int CPL, int C = N>
+template <int N, int KB, int CPL, int C = N, int LDP = KB>
 __device__ __forceinline__ void store_column_partials(const double (&v)[N][CPL], double* lred,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, int coff = 0) {
     constexpr int GW = KB / CPL;
     constexpr int NG = WG / GW;
     static_assert(C * WG * CPL <= 12 * WG, "LDS buffer too small");
@@ -387,7 +409,7 @@ __device__ __forceinline__ void store_column_partials(const double (&v)[N][CPL],
             for (int a = 0; a < na; ++a) {
                 double t = 0.0;
                 for (int gr = 0; gr < NG; ++gr) t += lred[a * NG * KB + gr * KB + threadIdx.x];
-                part[(static_cast<int64_t>(blockIdx.x) * KB + threadIdx.x) * BPART + a0 + a] = t;
+                part[(static_cast<int64_t>(blockIdx.x) * LDP + coff + threadIdx.x) * BPART + a0 + a] = t;
             }
         }
         __syncthreads();
@@ -414,7 +436,7 @@ __device__ __forceinline__ void column_totals(int G, const double* __restrict__ 
 
 // ------------------------------------------------------------ row operations
 
-template <typename T, int KB, int CPL>
+template <typename T, int KB, int CPL, int LDX = KB>
 struct OpSpmmCg {  // Q = (I + L) P and per-column p^T q, r^T M^{-1} q, q^T M^{-1} q
     const T* __restrict__ R;
     const float* __restrict__ minv;
@@ -422,13 +444,14 @@ struct OpSpmmCg {  // Q = (I + L) P and per-column p^T q, r^T M^{-1} q, q^T M^{-
     double shift[CPL] = {};  // deflated columns: mean of P's column (see k_cg_shift)
     double v[3][CPL] = {};
     __device__ void row(int i, int q, int c, double pi, double lin, double) {
-        const int64_t at = static_cast<int64_t>(i) * KB + c;
+        const int64_t at = static_cast<int64_t>(i) * LDX + c;
         const T qt = static_cast<T>(pi + lin - shift[q]);
-        Q[at] = qt;
+        // Q and R stream through once: non-temporal, so the L2 keeps the gathered rows of P
+        __builtin_nontemporal_store(qt, Q + at);
         const double qd = static_cast<double>(qt);
         const double mq = static_cast<double>(minv[i]) * qd;
         v[0][q] += pi * qd;
-        v[1][q] += static_cast<double>(R[at]) * mq;
+        v[1][q] += static_cast<double>(__builtin_nontemporal_load(R + at)) * mq;
         v[2][q] += qd * mq;
     }
 };
@@ -463,12 +486,21 @@ struct OpSpmmEpilogue {  // per column: the sums of OpEpilogue; R is written for
 // ------------------------------------------------------------ kernels
 
 // SPLIT: merge-path item split over lane groups (spmm_windows); otherwise one
-// group per row (spmm_rows).
-template <typename V, typename T, int KB, int CPL, bool SPLIT>
+// group per row (spmm_rows). LDX > KB: one column pass over columns
+// [coff, coff + KB) of LDX-wide blocks (rows design only): every pass reads
+// the CSR again, but gathers rows of KB instead of LDX values, which keeps a
+// wide block's gathered part inside the Infinity Cache.
+template <typename V, typename T, int KB, int CPL, bool SPLIT, int LDX = KB>
 __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restrict__ desc, int K,
                                                 const T* __restrict__ P, const T* __restrict__ R,
                                                 const float* __restrict__ minv, T* __restrict__ Q,
-                                                double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+                                                double* __restrict__ part, const Ctrl* __restrict__ ctrl,
+                                                int coff = 0) {
+    static_assert(LDX == KB || !SPLIT, "column passes use the rows design");
+    P += coff;
+    R += coff;
+    Q += coff;
+    if (ctrl != nullptr) ctrl += coff;
     // launches queued past the last column's stop return at once; ctrl null
     // (the autotuner's timing runs): every column, no shift
     __shared__ int live;
@@ -477,7 +509,7 @@ __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restr
     if (ctrl != nullptr && threadIdx.x < KB && ctrl[threadIdx.x].done == RUNNING) live = 1;
     __syncthreads();
     if (!live) return;
-    OpSpmmCg<T, KB, CPL> op{R, minv, Q};
+    OpSpmmCg<T, KB, CPL, LDX> op{R, minv, Q};
     if (ctrl != nullptr) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) op.shift[q] = ctrl[(threadIdx.x % (KB / CPL)) * CPL + q].pbar;
@@ -490,8 +522,8 @@ __global__ void __launch_bounds__(WG) k_spmm_cg(Csr<V> g, const WinDesc* __restr
         store_column_partials<3, KB, CPL>(op.v, reinterpret_cast<double*>(&st), part);
     } else {
         __shared__ double lred[12 * WG];
-        spmm_rows<T, V, AccLin, KB, CPL>(g, desc, K, P, op, lred);
-        store_column_partials<3, KB, CPL>(op.v, lred, part);
+        spmm_rows<T, V, AccLin, KB, CPL, LDX>(g, desc, K, P, op, lred);
+        store_column_partials<3, KB, CPL, 3, LDX>(op.v, lred, part, coff);
     }
 }
 
@@ -542,22 +574,43 @@ __global__ void __launch_bounds__(WG) k_update_batched(int n, T* __restrict__ X,
     double e[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t total = static_cast<int64_t>(n) * KB;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WG;
+    auto est_add = [&](int i, T x) {
+        const double xi = static_cast<double>(x);
+        const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
+        e[0] += xi * xi;
+        e[1] += xi;
+        e[2] += si * xi;
+        e[3] += (si - xi) * (si - xi);
+    };
     if (run) {
-        for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e0 < total; e0 += stride) {
+        int64_t e0 = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x;
+        for (; e0 + stride < total; e0 += 2 * stride) {  // two elements' loads in flight
+            const int64_t e1 = e0 + stride;
+            const int i0 = static_cast<int>(e0 / KB), i1 = static_cast<int>(e1 / KB);
+            T x0 = X[e0], r0 = R[e0], p0 = P[e0], q0 = Q[e0];
+            T x1 = X[e1], r1 = R[e1], p1 = P[e1], q1 = Q[e1];
+            const float m0 = minv[i0], m1 = minv[i1];
+            cg_update_elem(alpha, beta, pbar, x0, r0, p0, q0, m0, v);
+            cg_update_elem(alpha, beta, pbar, x1, r1, p1, q1, m1, v);
+            X[e0] = x0;
+            R[e0] = r0;
+            P[e0] = p0;
+            X[e1] = x1;
+            R[e1] = r1;
+            P[e1] = p1;
+            if (EST && est) {
+                est_add(i0, x0);
+                est_add(i1, x1);
+            }
+        }
+        if (e0 < total) {
             const int i = static_cast<int>(e0 / KB);
             T x = X[e0], r = R[e0], p = P[e0];
             cg_update_elem(alpha, beta, pbar, x, r, p, Q[e0], minv[i], v);
             X[e0] = x;
             R[e0] = r;
             P[e0] = p;
-            if (EST && est) {
-                const double xi = static_cast<double>(x);
-                const double si = c < k ? S[static_cast<int64_t>(i) * lds + c] : 0.0;
-                e[0] += xi * xi;
-                e[1] += xi;
-                e[2] += si * xi;
-                e[3] += (si - xi) * (si - xi);
-            }
+            if (EST && est) est_add(i, x);
         }
     }
     if constexpr (EST) {

@@ -314,7 +314,6 @@ __global__ void __launch_bounds__(WG) k_bcg_precond(int n, const double* __restr
                                                     const Ctrl* __restrict__ ctrl) {
     if (ctrl[0].done != RUNNING) return;
     __shared__ double lred[2 * WG];
-    const int c = threadIdx.x % KB;
     double v[2] = {0.0, 0.0};
     const int64_t total = static_cast<int64_t>(n) * KB;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < total;

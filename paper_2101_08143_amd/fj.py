@@ -123,8 +123,8 @@ def lib():
         L.fj_apply.argtypes = [P(fj_csr), vp, vp, vp, vp]
         L.fj_apriori_delta.argtypes = [i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.fj_apriori_delta.restype = ctypes.c_double
-        L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32)]
-        L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32, i32]
+        L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32), P(i32)]
+        L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32, i32, i32]
         L.fj_gather_bound.argtypes = [P(fj_csr), vp, vp, vp]
         L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
@@ -268,18 +268,20 @@ def fj_apriori_delta(n: int, w_min: float, w_max: float, sbar_norm: float, eps: 
 
 
 def fj_spmm_choice(graph: Graph, kb: int, precision: int = 0):
-    """(columns per lane, grid, split) the SpMM autotuner chose for this graph,
-    block width and precision, or None if nothing is tuned yet."""
-    cpl, grid, split = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    """(columns per lane, grid, split, passes) the SpMM autotuner chose for this
+    graph, block width and precision, or None if nothing is tuned yet."""
+    cpl, grid, split, passes = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     rc = lib().fj_spmm_choice(ctypes.byref(graph.csr), int(kb), int(precision), ctypes.byref(cpl),
-                              ctypes.byref(grid), ctypes.byref(split))
-    return (cpl.value, grid.value, split.value) if rc == FJ_OK else None
+                              ctypes.byref(grid), ctypes.byref(split), ctypes.byref(passes))
+    return (cpl.value, grid.value, split.value, passes.value) if rc == FJ_OK else None
 
 
-def fj_spmm_set_choice(graph: Graph, kb: int, cpl: int, grid: int, precision: int = 0, split: int = 1):
-    """Pin the SpMM launch shape (columns per lane, grid, split) instead of tuning it."""
+def fj_spmm_set_choice(graph: Graph, kb: int, cpl: int, grid: int, precision: int = 0, split: int = 1,
+                       passes: int = 1):
+    """Pin the SpMM launch shape (columns per lane, grid, split, column passes)
+    instead of tuning it."""
     rc = lib().fj_spmm_set_choice(ctypes.byref(graph.csr), int(kb), int(precision), int(cpl), int(grid),
-                                  int(split))
+                                  int(split), int(passes))
     if rc != FJ_OK:
         raise FJError(rc, "fj_spmm_set_choice")
 

@@ -224,3 +224,13 @@ def test_block_cg_argument_errors(lib):
     o = fj.make_opts(flags=fj.FJ_BLOCK_CG)
     assert lib.fj_workspace_bytes(ctypes.byref(csr), 3, ctypes.byref(o)) > \
         lib.fj_workspace_bytes(ctypes.byref(csr), 3, ctypes.byref(fj.make_opts()))
+
+
+def test_spmm_shape_rules(lib):
+    """Column passes only for 32- and 64-column blocks, rows design, cpl <= 2
+    and at least 16 columns per pass (checked before any device work)."""
+    csr = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=None, val_type=fj.FJ_VAL_UNIT)
+    bad = [(16, 1, 0, 2), (32, 1, 0, 4), (64, 1, 1, 2), (64, 4, 0, 2), (64, 1, 0, 3)]
+    for kb, cpl, split, passes in bad:
+        assert lib.fj_spmm_set_choice(ctypes.byref(csr), kb, 0, cpl, 64, split, passes) == fj.FJ_ERR_INVALID_ARG, \
+            (kb, cpl, split, passes)

@@ -394,11 +394,37 @@ def test_batched_every_spmm_shape_matches_oracle(torch_fj, name, k, cpl, split, 
     say(f"spmm shape {name} k={k} cpl={cpl} split={split} {precision}")
     grid = 64 if cpl == 2 else 512
     fj.fj_spmm_set_choice(G, kb, cpl, grid, precision=prec, split=split)
-    assert fj.fj_spmm_choice(G, kb, prec) == (cpl, grid, split)
+    assert fj.fj_spmm_choice(G, kb, prec) == (cpl, grid, split, 1)
     vals, infos, rc = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(eps=EPS, precision=prec),
                                     check=False)
     assert rc == fj.FJ_OK
     for c in range(k):
+        ref, _, _ = O.indices(g, S[:, c])
+        for j, nm in enumerate(NAMES):
+            err = abs(vals[c][nm] - ref[nm]) / abs(ref[nm])
+            assert err <= EPS and err <= infos[c].bound[j] + 1e-12, (c, nm, err)
+
+
+@pytest.mark.parametrize("name", ["cl50k_f32", "star6001", "gnp500_f64"])
+@pytest.mark.parametrize("k,kb,passes", [(20, 32, 2), (64, 64, 2), (40, 64, 4)])
+@pytest.mark.parametrize("cpl", [1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_column_passes_match_oracle(torch_fj, name, k, kb, passes, cpl, precision):
+    """The column-pass SpMM shapes for wide blocks (2 passes of 16 or 32
+    columns, 4 of 16; one lane group per row), pinned on a freshly prepared
+    graph: certified indices within 1e-6 of the oracle (sampled columns)."""
+    torch, fj = torch_fj
+    g = small_graphs()[name]
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=False)
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    S = _block(g.n, k, 700 + k)
+    say(f"spmm passes {name} k={k} passes={passes} cpl={cpl} {precision}")
+    fj.fj_spmm_set_choice(G, kb, cpl, 512, precision=prec, split=0, passes=passes)
+    assert fj.fj_spmm_choice(G, kb, prec) == (cpl, 512, 0, passes)
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(S).to("cuda:0"), fj.make_opts(eps=EPS, precision=prec),
+                                    check=False)
+    assert rc == fj.FJ_OK
+    for c in range(0, k, 5):
         ref, _, _ = O.indices(g, S[:, c])
         for j, nm in enumerate(NAMES):
             err = abs(vals[c][nm] - ref[nm]) / abs(ref[nm])
@@ -418,8 +444,8 @@ def test_batched_autotuner_records_a_shape(torch_fj):
     assert rc0 == fj.FJ_OK and fj.fj_spmm_choice(G, 16, fj.FJ_FP64) is None
     v1, _, rc1 = fj.fj_indices(G, S, fj.make_opts(eps=EPS), check=False)
     assert rc1 == fj.FJ_OK
-    cpl, grid, split = fj.fj_spmm_choice(G, 16, fj.FJ_FP64)
-    assert cpl in (1, 2, 4) and 1 <= grid <= 4096 and split in (0, 1)
+    cpl, grid, split, passes = fj.fj_spmm_choice(G, 16, fj.FJ_FP64)
+    assert cpl in (1, 2, 4) and 1 <= grid <= 4096 and split in (0, 1) and passes == 1
     v2, _, _ = fj.fj_indices(G, S, fj.make_opts(eps=EPS), check=False)
     assert v2 == v1  # the cached choice is reused: bitwise repeatable
     for c in range(16):
