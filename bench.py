@@ -90,6 +90,38 @@ def spmm_bytes(n: int, nnz: int, val_bytes: int, kb: int, elem: int) -> int:
     return nnz * (4 + val_bytes) + 4 * (n + 1) + 3 * n * kb * elem + 4 * n
 
 
+def gather_ladder(fj, torch, G, g, x64):
+    """The bare gather of the SpMV over the same matrix, in CSR order and over
+    eight XCD-aligned streams (fj_gather_bound_sliced: workgroup b on stream
+    b % 8, hub columns [0, H) read by every stream, the rest cut into eight
+    ranges of equal entry count), FP64 and FP32 x. footprint: the x bytes one
+    XCD's streams read (hub range plus its widest tail range)."""
+    out = []
+    x32 = x64.float()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for slices, hub in ((1, 0), (8, 0), (8, 131072), (8, 262144), (8, 524288)):
+        for x in (x64, x32):
+            xb = x.element_size()
+            check = torch.zeros(2, dtype=torch.int32, device=x.device)
+            y, b = fj.fj_gather_bound_sliced(G, x, slices, hub, check=check)
+            torch.cuda.synchronize()
+            ev0.record()
+            for _ in range(10):
+                fj.fj_gather_bound_sliced(G, x, slices, hub, y=y)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / 10
+            hits, wgs = check.cpu().tolist()
+            foot = (g.n if slices == 1 else b[0] + max(b[s + 1] - b[s] for s in range(8))) * xb
+            out.append({"streams": slices, "hub_cols": hub if slices == 8 else None, "x_bytes": xb, "ms": ms,
+                        "footprint_per_xcd_MB": foot / 2**20,
+                        "workgroups_on_xcd_b_mod_8": f"{hits}/{wgs}" if slices == 8 else None})
+            print(f"[bench] gather ladder: {slices} stream(s), hub {hub}, x{8 * xb}: {ms:.3f} ms, "
+                  f"{foot / 2**20:.1f} MB per XCD", file=sys.stderr, flush=True)
+            del y
+    return out
+
+
 def batched_forms(args, fj, W, torch, dev):
     """The 1M-node Chung-Lu graph with k = 64 opinion vectors (21 uniform, 21
     exponential, 22 Pareto, min-max scaled) in one call, FP64 and mixed,
@@ -428,6 +460,8 @@ def main():
                     help="measured requests (after 500 warm-up) of the FP64 server at 0.5x saturation")
     ap.add_argument("--fifo-requests", type=int, default=300,
                     help="measured requests per level of the plain FP64 FIFO baseline (0 = skip it)")
+    ap.add_argument("--gather-ladder", type=int, default=1,
+                    help="time the bare gather over XCD-aligned column slices (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -513,7 +547,9 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     gather_ms = e0.elapsed_time(e1) / 10
-    del xg, yg
+    del yg
+    ladder = gather_ladder(fj, torch, G, g, xg) if args.gather_ladder else None
+    del xg
 
     # a plain 1 GiB device copy: the streaming bandwidth this GPU reaches in practice
     src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -561,6 +597,7 @@ def main():
             "frac_of_gather_ceiling": gather_ms / work_ms if work_ms > 0 else None,
             "gather_ceiling_note": "fj_gather_bound: the same col/val streams and one random x_j gather per "
                                    "entry, nothing else; random gathers, not HBM bytes, bound this kernel",
+            "gather_ladder": ladder,
             "measured_copy_GBs": copy_gbs,
             "frac_of_measured_copy": achieved / copy_gbs if copy_gbs > 0 else None,
         },

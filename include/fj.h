@@ -238,6 +238,33 @@ int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t c
 int fj_gather_bound(const fj_csr *g, const double *x, double *y, void *stream);
 
 /*
+ * Measurement aid (not part of any solve): the gather of fj_gather_bound over
+ * the same entries regrouped into `slices` streams, to see what confining each
+ * XCD's gathers to a slice of x buys. slices = 1: one stream in CSR order (the
+ * same grouping as fj_gather_bound, so y is bitwise equal to its y).
+ * slices = 8: the columns [hub_cols, n) are cut into eight ranges of about
+ * equal entry count and range s is read only by stream s; the entries of the
+ * hub columns [0, hub_cols) are dealt to the eight streams in equal runs in
+ * CSR order (each stream reads the whole hub range). Workgroup b of the launch
+ * works on stream b % 8, which on MI355X keeps a stream on one XCD, so that
+ * XCD's L2 holds the hub range plus one tail range of x.
+ * x: device double[n] (x_bytes 8) or float[n] (x_bytes 4). y: device
+ * double[(nnz + 7) / 8 + 8]; y[t] of stream s's group t sits at off_s / 8 + t.
+ * check: optional device int32[2], added to: [0] the workgroups whose
+ * hardware XCD id equals b % 8, [1] all workgroups. bounds: optional host
+ * int64[9], the range edges (bounds[s] .. bounds[s + 1] is tail range s;
+ * bounds[0] = min(hub_cols, n)).
+ * The streams are built on the host from a device-to-host copy of the CSR on
+ * the first call for a graph (synchronous, seconds for 10^8 entries) and held
+ * in device memory until a call on another graph, stream count or hub width,
+ * or process end; later calls only launch, asynchronously on `stream`.
+ * FJ_ERR_INVALID_ARG for slices other than 1 or 8, x_bytes other than 4 or
+ * 8, negative hub_cols or a null x or y with nnz > 0.
+ */
+int fj_gather_bound_sliced(const fj_csr *g, const void *x, int32_t x_bytes, double *y, int32_t slices,
+                           int32_t hub_cols, int32_t *check, int64_t *bounds, void *stream);
+
+/*
  * The FJ opinion dynamics itself (Section 3.1, Eq. FJmodel): up to `steps`
  * synchronous updates z_i <- (s_i + sum_j w_ij z_j) / (1 + sum_j w_ij) from
  * z0 (NULL: start from s). Stops after the first step whose largest change

@@ -687,6 +687,51 @@ __global__ void __launch_bounds__(WG) k_gather_bound(Csr<V> g, const double* __r
     }
 }
 
+// Measurement aid: the same bare gather over entries regrouped into S
+// streams (the host builds them; see fj_gather_bound_sliced). Stream s holds
+// entries [off[s], off[s] + cnt[s]) padded to a multiple of 8 from off[s]
+// (8-aligned); padding slots point at column 0 with weight 0. Workgroup b
+// works on stream b % S, so with S = 8 a stream stays on one XCD (workgroups
+// are dealt to the XCDs round robin). check (optional, int[2]) counts the
+// workgroups whose hardware XCD id equals b % 8, and all workgroups.
+template <typename V, typename X>
+__global__ void __launch_bounds__(WG) k_gather_sliced(const int* __restrict__ col, const V* __restrict__ val,
+                                                      const X* __restrict__ x, double* __restrict__ y,
+                                                      const int64_t* __restrict__ off, const int64_t* __restrict__ cnt,
+                                                      int S, int* __restrict__ check) {
+    const int s = blockIdx.x % S;
+    const int wb = blockIdx.x / S;
+    const int gs = gridDim.x / S;
+    if (check && threadIdx.x == 0) {
+        unsigned xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        atomicAdd(&check[0], static_cast<int>((xcc & 0xfu) == static_cast<unsigned>(blockIdx.x % 8)));
+        atomicAdd(&check[1], 1);
+    }
+    const int64_t e0 = off[s], real_end = e0 + cnt[s];
+    const int64_t groups = (cnt[s] + 7) / 8;
+    typedef int iv4 __attribute__((ext_vector_type(4)));
+    for (int64_t t = static_cast<int64_t>(wb) * WG + threadIdx.x; t < groups; t += static_cast<int64_t>(gs) * WG) {
+        const int64_t b = e0 + t * 8;
+        const iv4 ja = __builtin_nontemporal_load(reinterpret_cast<const iv4*>(col + b));
+        const iv4 jb = __builtin_nontemporal_load(reinterpret_cast<const iv4*>(col + b + 4));
+        const int j[8] = {ja.x, ja.y, ja.z, ja.w, jb.x, jb.y, jb.z, jb.w};
+        double w[8], v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            double wv = 1.0;
+            if constexpr (!std::is_same<V, Unit>::value) wv = static_cast<double>(stream_load(&val[b + u]));
+            w[u] = b + u < real_end ? wv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = static_cast<double>(x[j[u]]);
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += w[u] * v[u];
+        y[e0 / 8 + t] = acc;
+    }
+}
+
 // One synchronous step of the FJ update rule (Section 3.1, Eq. FJmodel):
 // z'_i = (s_i + sum_j w_ij z_j) / (1 + sum_j w_ij), with the largest change
 // |z'_i - z_i| of the step.

@@ -47,7 +47,7 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
            "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
-           "fj_spmm_set_choice", "fj_gather_bound", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
+           "fj_spmm_set_choice", "fj_gather_bound", "fj_gather_bound_sliced", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
            "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll", "fj_server_cancel")
@@ -126,6 +126,7 @@ def lib():
         L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32), P(i32)]
         L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32, i32, i32]
         L.fj_gather_bound.argtypes = [P(fj_csr), vp, vp, vp]
+        L.fj_gather_bound_sliced.argtypes = [P(fj_csr), vp, i32, vp, i32, i32, vp, P(i64), vp]
         L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
         L.fj_indices.argtypes = [P(fj_csr), vp, i32, vp, i64, P(fj_opts), vp, sz, vp, P(fj_indices_t),
@@ -141,6 +142,7 @@ def lib():
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
         for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
+                     "fj_gather_bound_sliced",
                      "fj_dynamics", "fj_solve", "fj_indices", "fj_indices_noalloc", "fj_server_create",
                      "fj_server_destroy",
                      "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll",
@@ -296,6 +298,22 @@ def fj_gather_bound(graph: Graph, x, y=None, stream=None):
     if rc != FJ_OK:
         raise FJError(rc, "fj_gather_bound")
     return y
+
+
+def fj_gather_bound_sliced(graph: Graph, x, slices: int = 8, hub_cols: int = 0, y=None, check=None, stream=None):
+    """Measurement aid: the gather over XCD-aligned entry streams (see
+    include/fj.h). x is float64 or float32. Returns (y, bounds)."""
+    import torch
+    assert x.dtype in (torch.float64, torch.float32) and x.is_contiguous() and x.numel() == graph.n
+    if y is None:
+        y = torch.empty((graph.csr.nnz + 7) // 8 + 8, dtype=torch.float64, device=x.device)
+    bounds = (ctypes.c_int64 * 9)()
+    rc = lib().fj_gather_bound_sliced(ctypes.byref(graph.csr), _ptr(x), 8 if x.dtype == torch.float64 else 4,
+                                      _ptr(y), int(slices), int(hub_cols), _ptr(check) if check is not None else None,
+                                      bounds, _stream_handle(torch, stream))
+    if rc != FJ_OK:
+        raise FJError(rc, "fj_gather_bound_sliced")
+    return y, list(bounds)
 
 
 def fj_dynamics(graph: Graph, s, steps: int, tol: float = -1.0, z0=None, z=None, ws=None, stream=None):

@@ -83,6 +83,10 @@ def test_argument_errors_are_caught_on_the_host(lib):
     nonodes = fj.fj_csr(n=0, nnz=4, row_ptr=256, col_idx=512, val=None, val_type=0)
     assert lib.fj_prepare(ctypes.byref(nonodes), None, ctypes.c_void_p(256), 1 << 20, None) == \
         fj.FJ_ERR_INVALID_GRAPH
+    # the sliced gather aid: 1 or 8 streams, 4- or 8-byte x, hub_cols >= 0
+    for sl, xb, hub in ((3, 8, 0), (8, 2, 0), (8, 8, -1), (0, 8, 0)):
+        assert lib.fj_gather_bound_sliced(ctypes.byref(csr), ctypes.c_void_p(256), xb, ctypes.c_void_p(256), sl, hub,
+                                          None, None, None) == fj.FJ_ERR_INVALID_ARG
     # misaligned or undersized plan
     assert lib.fj_prepare(ctypes.byref(csr), None, ctypes.c_void_p(257), 1 << 20, None) == fj.FJ_ERR_WORKSPACE
     assert lib.fj_prepare(ctypes.byref(csr), None, ctypes.c_void_p(256), 16, None) == fj.FJ_ERR_WORKSPACE

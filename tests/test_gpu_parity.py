@@ -142,6 +142,51 @@ def test_gather_bound_probe(torch_fj, graphs, name):
     assert np.allclose(y, prod.sum(axis=1), rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("name", ["cl50k_f32", "gnp500_f64", "star6001", "isolated9000"])
+@pytest.mark.parametrize("xbytes", [8, 4])
+def test_gather_bound_sliced(torch_fj, graphs, name, xbytes):
+    """fj_gather_bound_sliced: one stream reproduces fj_gather_bound bitwise;
+    eight streams hold exactly the entries the slicing rule gives them (tail
+    ranges from the returned edges, hub entries dealt in eight equal runs in
+    CSR order), each in CSR order, and every workgroup is counted."""
+    torch, fj = torch_fj
+    g, G = graphs[name]
+    say(f"gather sliced {name} x{8 * xbytes}")
+    x64 = np.random.default_rng(8).random(g.n)
+    x = x64 if xbytes == 8 else x64.astype(np.float32)
+    xd = torch.from_numpy(x).to("cuda:0")
+    xs = x.astype(np.float64)
+    w = g.weights_f64()
+    y1, _ = fj.fj_gather_bound_sliced(G, xd, slices=1)
+    if xbytes == 8:
+        y0 = fj.fj_gather_bound(G, xd).cpu().numpy()
+        assert np.array_equal(y1.cpu().numpy()[:len(y0)], y0)
+    for hub in (0, g.n // 16):
+        check = torch.zeros(2, dtype=torch.int32, device="cuda:0")
+        y8, b = fj.fj_gather_bound_sliced(G, xd, slices=8, hub_cols=hub, check=check)
+        y8 = y8.cpu().numpy()
+        assert b[0] == min(hub, g.n) and b[8] == g.n and all(b[s] <= b[s + 1] for s in range(8))
+        col = g.col.astype(np.int64)
+        is_hub = col < b[0]
+        tail_cnt = np.bincount(np.searchsorted(b[1:8], col[~is_hub], side="right"), minlength=8)
+        if (~is_hub).any():  # ranges balanced up to one column's entries
+            per_col = np.bincount(col, minlength=g.n)
+            assert tail_cnt.max() <= (~is_hub).sum() / 8 + per_col[b[0]:].max() + 1
+        hub_rank = np.cumsum(is_hub) - 1
+        sid = np.where(is_hub, hub_rank * 8 // max(int(is_hub.sum()), 1),
+                       np.searchsorted(b[1:8], col, side="right"))
+        prod = w * xs[col]
+        at = 0
+        for s_ in range(8):
+            ps = prod[sid == s_]
+            ps = np.concatenate([ps, np.zeros((-len(ps)) % 8)]).reshape(-1, 8).sum(axis=1)
+            assert np.allclose(y8[at:at + len(ps)], ps, rtol=1e-13, atol=1e-13), (hub, s_)
+            at += len(ps)
+        hits, wgs = check.cpu().numpy().tolist()
+        assert wgs >= 8 and wgs % 8 == 0 and 0 <= hits <= wgs
+        say(f"  hub {hub}: {hits} of {wgs} workgroups on XCD b % 8")
+
+
 @pytest.mark.parametrize("name", [n for n in small_graphs() if n not in ("path5",)])
 @pytest.mark.parametrize("kind", ["uniform", "exp"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
