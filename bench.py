@@ -26,7 +26,7 @@ METRIC = "FJ index solves/sec at 1e-6 rel err; achieved HBM GB/s; serving p50/p9
 PEAK_HBM_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["paper_2101_08143_amd/csrc/fj_kernels.hpp", "paper_2101_08143_amd/csrc/fj_batched.hpp",
-                  "paper_2101_08143_amd/csrc/fj_blockcg.hpp",
+                  "paper_2101_08143_amd/csrc/fj_blockcg.hpp", "paper_2101_08143_amd/csrc/fj_multilevel.hpp",
                   "paper_2101_08143_amd/csrc/fj_server.hpp", "paper_2101_08143_amd/csrc/fj_api.hip", "include/fj.h"]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_cl4m.json")
 

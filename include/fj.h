@@ -104,6 +104,12 @@ typedef struct fj_csr {
                                   matrix cores. By default (and in the server) every column runs its own CG, so
                                   a column's result does not depend on the others; with this flag it does.
                                   Not with FJ_TWO_SOLVE or FJ_WARM_START */
+#define FJ_MULTILEVEL    512u  /* one opinion vector (k = 1), FJ_FP64: precondition CG with the aggregation
+                                  V-cycle of opts->hierarchy (fj_hierarchy_create) instead of the 2x2 blocks or
+                                  Jacobi; for graphs whose edge weights spread over many orders of magnitude.
+                                  Not with FJ_DIAG_PRECOND, FJ_BLOCK_CG, in the server or fj_indices_noalloc */
+
+typedef struct fj_hierarchy fj_hierarchy;
 
 typedef struct fj_opts {
     double eps;           /* certified relative error of every index, in (0, 1/2) (Algorithm 1 input) */
@@ -112,9 +118,10 @@ typedef struct fj_opts {
     int32_t precision;    /* FJ_FP64 or FJ_MIXED */
     uint32_t flags;       /* FJ_* flags above */
     int32_t reserved;     /* must be 0 */
+    const fj_hierarchy *hierarchy;  /* FJ_MULTILEVEL: the hierarchy of this graph; otherwise ignored */
 } fj_opts;
 
-/* Fill *opts with the defaults: eps = 1e-6, rtol = 0, max_iter = 0, FJ_FP64, no flags. */
+/* Fill *opts with the defaults: eps = 1e-6, rtol = 0, max_iter = 0, FJ_FP64, no flags, no hierarchy. */
 void fj_default_opts(fj_opts *opts);
 
 /* ---- results ------------------------------------------------------------ */
@@ -225,6 +232,43 @@ int fj_spmm_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t *cpl,
  */
 int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t cpl, int32_t grid,
                        int32_t split, int32_t passes);
+
+/*
+ * The multilevel preconditioner of FJ_MULTILEVEL, a stand-in for the Laplacian
+ * solver the method calls (Lemma ST: a nearly-linear-time solver for
+ * Laplacian systems, built there by approximate Gaussian elimination) in the
+ * same class: an aggregation hierarchy of I + L with a V-cycle.
+ *   Level 0 is I + L = diag(a_0) - W_0 (a_0 = 1 + weighted degree). Every node
+ *   points to its heaviest neighbour (ties broken by a hash of the edge); the connected
+ *   groups of these pointers are the aggregates, the nodes of the next level.
+ *   The next level keeps the form diag(a) - W (Galerkin: P^T A P with P the
+ *   0/1 aggregate indicator): W sums the weights between aggregates, the
+ *   identity part becomes the aggregate sizes. Coarsening stops at
+ *   <= coarse_max nodes (0: 1024), after 16 levels, or when a level shrinks by
+ *   less than 10 %; the last level is inverted exactly (dense, FP64) if it has
+ *   at most 4096 nodes and is otherwise smoothed by one Jacobi step.
+ *   One V-cycle: damped Jacobi (weight 0.9) before and after the coarse
+ *   correction on every level; it is a fixed symmetric positive definite
+ *   operator, so CG stays CG.
+ * Built on the host from a device-to-host copy of the CSR (synchronous on
+ * `stream`), then uploaded: the hierarchy holds its own FP64 copy of every
+ * level and the V-cycle's work vectors (about 4 n + 3 nnz doubles in all),
+ * allocated here. Rebuild it if the graph's weights change. A hierarchy
+ * serves one solve at a time (its work vectors are shared): concurrent solves
+ * need one each.
+ * FJ_ERR_INVALID_ARG for a null out or coarse_max < 0; FJ_ERR_HOST_MEMORY or
+ * FJ_ERR_HIP when an allocation fails (nothing is leaked).
+ */
+int fj_hierarchy_create(const fj_csr *g, int32_t coarse_max, fj_hierarchy **out, void *stream);
+
+/* Shape of a hierarchy: *levels (counting level 0 and the last), and, for
+ * level l < min(levels, 16), its nodes n[l] and stored off-diagonal entries
+ * nnz[l] (host arrays of 16, may be NULL). *dense = 1 if the last level is
+ * inverted exactly. */
+int fj_hierarchy_shape(const fj_hierarchy *h, int32_t *levels, int32_t *n, int64_t *nnz, int32_t *dense);
+
+/* Free a hierarchy (waits for the device first). NULL is accepted. */
+int fj_hierarchy_destroy(fj_hierarchy *h);
 
 /*
  * Measurement aid (not part of any solve): the bare gather of an SpMV over

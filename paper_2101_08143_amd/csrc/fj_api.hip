@@ -19,6 +19,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <stdexcept>
@@ -30,8 +31,27 @@
 #include "fj_kernels.hpp"
 #include "fj_batched.hpp"
 #include "fj_blockcg.hpp"
+#include "fj_multilevel.hpp"
 
 using namespace fj;
+
+// The aggregation hierarchy of FJ_MULTILEVEL (see fj_hierarchy_create): levels
+// 0 .. levels-2 each with a coarser level, then the last level.
+struct fj_hierarchy {
+    int dev = 0;
+    int n0 = 0;
+    int64_t nnz0 = 0;
+    int levels = 0;
+    MlLevel lv[ML_MAXL];
+    int n[ML_MAXL] = {};
+    int64_t nnz[ML_MAXL] = {};
+    int nL = 0;                        // the last level: nodes,
+    const double* inv = nullptr;       // its dense inverse (row-major, nL x nL) or null,
+    const double* ainvL = nullptr;     // its 1 / a
+    double* rbuf[ML_MAXL] = {};        // right-hand side of level l >= 1
+    double* xbuf[ML_MAXL] = {};        // V-cycle result of level l >= 1
+    void* mem = nullptr;               // one device allocation holding all of it
+};
 
 namespace {
 
@@ -277,10 +297,30 @@ int check_opts(const fj_opts* o) {
                       "FJ_BLOCK_CG needs FJ_FP64 and neither FJ_TWO_SOLVE nor FJ_WARM_START");
         return FJ_ERR_INVALID_ARG;
     }
+    if ((o->flags & FJ_MULTILEVEL) &&
+        (o->precision != FJ_FP64 || !o->hierarchy || (o->flags & (FJ_DIAG_PRECOND | FJ_BLOCK_CG)))) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "FJ_MULTILEVEL needs FJ_FP64, a hierarchy and neither FJ_DIAG_PRECOND nor FJ_BLOCK_CG");
+        return FJ_ERR_INVALID_ARG;
+    }
     if (!(o->eps > 0.0 && o->eps < 0.5)) return FJ_ERR_INVALID_ARG;
     if (!(o->rtol >= 0.0 && o->rtol < 1.0)) return FJ_ERR_INVALID_ARG;
     if (o->max_iter < 0 || o->reserved != 0) return FJ_ERR_INVALID_ARG;
     if (o->precision != FJ_FP64 && o->precision != FJ_MIXED) return FJ_ERR_INVALID_ARG;
+    return FJ_OK;
+}
+
+// FJ_MULTILEVEL: one vector, and the hierarchy built for this graph on this device.
+int check_ml(const fj_csr* g, int k, const fj_opts* o) {
+    if (!(o->flags & FJ_MULTILEVEL)) return FJ_OK;
+    const fj_hierarchy* h = o->hierarchy;
+    int dev = 0;
+    if (int rc = current_device(&dev)) return rc;
+    if (k != 1 || h->n0 != g->n || h->nnz0 != g->nnz || h->dev != dev) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "FJ_MULTILEVEL needs k = 1 and the hierarchy of this graph on this device");
+        return FJ_ERR_INVALID_ARG;
+    }
     return FJ_OK;
 }
 
@@ -306,6 +346,7 @@ struct CgState {
     T* z = nullptr;                 // with the 2x2 block preconditioner: M^{-1} r, M^{-1} q
     T* mq = nullptr;
     bool pairs = false;
+    const fj_hierarchy* ml = nullptr;  // FJ_MULTILEVEL (FP64): z = V-cycle(r) instead of the 2x2 blocks
 };
 
 // What every launch of a solve needs.
@@ -353,7 +394,51 @@ int cg_init(Ctx& c, CgState<T>& S, const double* s, int64_t lds, int mode, doubl
     return FJ_OK;
 }
 
-// One CG step with the 2x2 block preconditioner (one vector).
+// x = V b: one V-cycle of the hierarchy (see fj_multilevel.hpp). With ctrl,
+// every launch returns at once once the solve has stopped.
+int vcycle(hipStream_t st, const fj_hierarchy* h, const double* b, double* x, const Ctrl* ctrl) {
+    auto rows_grid = [](auto kern, int n, int nlong, int* grid) -> int {
+        const int64_t units = (static_cast<int64_t>(n) * ML_GW + static_cast<int64_t>(nlong) * 64 + WG - 1) / WG;
+        return grid_for(kern, std::max<int64_t>(units, 1), grid);
+    };
+    int grid = 1;
+    const double* bl = b;
+    for (int l = 0; l + 1 < h->levels; ++l) {
+        const MlLevel& L = h->lv[l];
+        if (int rc = rows_grid(k_ml_rows<OpPre>, L.n, L.nlong, &grid)) return rc;
+        k_ml_rows<OpPre><<<grid, WG, 0, st>>>(L.n, L.rp, L.col, L.w, L.longs, L.nlong, OpPre{bl, L.ainv, L.t}, ctrl);
+        HIPCHK(hipGetLastError());
+        if (int rc = rows_grid(k_ml_rows<OpSum>, L.nc, L.nclong, &grid)) return rc;
+        k_ml_rows<OpSum><<<grid, WG, 0, st>>>(L.nc, L.mrp, L.mem, nullptr, L.clongs, L.nclong,
+                                              OpSum{L.t, h->rbuf[l + 1]}, ctrl);
+        HIPCHK(hipGetLastError());
+        bl = h->rbuf[l + 1];
+    }
+    const int last = h->levels - 1;
+    double* xl = last == 0 ? x : h->xbuf[last];
+    if (h->inv) {
+        if (int rc = grid_for(k_ml_coarse, (static_cast<int64_t>(h->nL) * 64 + WG - 1) / WG, &grid)) return rc;
+    } else {
+        if (int rc = grid_for(k_ml_coarse, (static_cast<int64_t>(h->nL) + WG - 1) / WG, &grid)) return rc;
+    }
+    k_ml_coarse<<<grid, WG, 0, st>>>(h->nL, h->inv, h->ainvL, bl, xl, ctrl);
+    HIPCHK(hipGetLastError());
+    for (int l = last - 1; l >= 0; --l) {
+        const MlLevel& L = h->lv[l];
+        const double* b_l = l == 0 ? b : h->rbuf[l];
+        double* out = l == 0 ? x : h->xbuf[l];
+        if (int rc = grid_for(k_ml_prolong, (static_cast<int64_t>(L.n) + WG - 1) / WG, &grid)) return rc;
+        k_ml_prolong<<<grid, WG, 0, st>>>(L.n, b_l, L.ainv, L.agg, h->xbuf[l + 1], L.t, ctrl);
+        HIPCHK(hipGetLastError());
+        if (int rc = rows_grid(k_ml_rows<OpPost>, L.n, L.nlong, &grid)) return rc;
+        k_ml_rows<OpPost><<<grid, WG, 0, st>>>(L.n, L.rp, L.col, L.w, L.longs, L.nlong,
+                                               OpPost{b_l, L.t, L.a, L.ainv, out}, ctrl);
+        HIPCHK(hipGetLastError());
+    }
+    return FJ_OK;
+}
+
+// One CG step with the 2x2 block preconditioner or the V-cycle (one vector).
 template <typename T>
 int cg_iteration_pair(Ctx& c, CgState<T>& S) {
     int grid_win = 1;
@@ -374,7 +459,16 @@ int cg_iteration_pair(Ctx& c, CgState<T>& S) {
     });
     if (rc) return rc;
     const int n = c.g->n;
-    k_pair_dots<T><<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, c.mate(), c.pc(), S.mq, S.part, S.ctrl);
+    if constexpr (std::is_same<T, double>::value) {
+        if (S.ml) {
+            if (int e = vcycle(c.st, S.ml, S.q, S.mq, S.ctrl)) return e;
+            k_ml_dots<<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, S.mq, S.part, S.ctrl);
+        } else {
+            k_pair_dots<T><<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, c.mate(), c.pc(), S.mq, S.part, S.ctrl);
+        }
+    } else {
+        k_pair_dots<T><<<c.grid_vec, WG, 0, c.st>>>(n, S.q, S.z, c.mate(), c.pc(), S.mq, S.part, S.ctrl);
+    }
     HIPCHK(hipGetLastError());
     k_fin_pair<<<1, WG, 0, c.st>>>(grid_win, c.grid_vec, S.part, S.ctrl);
     HIPCHK(hipGetLastError());
@@ -399,7 +493,7 @@ int cg_iteration_pair(Ctx& c, CgState<T>& S) {
 
 template <typename T>
 int cg_iteration(Ctx& c, CgState<T>& S) {
-    if (S.pairs) return cg_iteration_pair(c, S);
+    if (S.pairs || S.ml) return cg_iteration_pair(c, S);
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
@@ -640,10 +734,17 @@ int solve_fp64(Ctx& c, CgState<double>& S, const double* s, int64_t lds, const f
     };
     // 2x2 block preconditioner on the plan's heavy-edge matching (default):
     // z = M^{-1} r and p = z replace the Jacobi start every start leaves
-    S.pairs = S.z != nullptr && !(o.flags & FJ_DIAG_PRECOND) && c.g->n >= PAIR_MIN_N;
+    // or the V-cycle of FJ_MULTILEVEL: z = V r, p = z
+    S.ml = (o.flags & FJ_MULTILEVEL) && S.z != nullptr ? o.hierarchy : nullptr;
+    S.pairs = !S.ml && S.z != nullptr && !(o.flags & FJ_DIAG_PRECOND) && c.g->n >= PAIR_MIN_N;
     auto pair_start = [&](double stop) -> int {
-        if (!S.pairs) return FJ_OK;
-        k_pair_start<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.r, S.z, S.p, c.mate(), c.pc(), S.part);
+        if (!S.pairs && !S.ml) return FJ_OK;
+        if (S.ml) {
+            if (int rc = vcycle(c.st, S.ml, S.r, S.z, nullptr)) return rc;
+            k_ml_start<<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.r, S.z, S.p, S.part);
+        } else {
+            k_pair_start<double><<<c.grid_vec, WG, 0, c.st>>>(c.g->n, S.r, S.z, S.p, c.mate(), c.pc(), S.part);
+        }
         HIPCHK(hipGetLastError());
         k_fin_init<<<1, WG, 0, c.st>>>(c.grid_vec, c.g->n, S.part, 1, rtol * rtol, max_iter, range_check ? 1 : 0,
                                        S.ctrl, stop, deflate);
@@ -2021,6 +2122,341 @@ int fj_gather_bound_sliced(const fj_csr* g, const void* x, int32_t x_bytes, doub
     });
 }
 
+namespace {
+// One level of the hierarchy on the host: W (CSR, no diagonal) and the
+// identity part mass (1 on level 0, the aggregate sizes further down).
+struct HostLevel {
+    int n = 0;
+    std::vector<int> rp, col;
+    std::vector<double> w, mass;
+};
+
+// Tie-break key of the edge {i, j} (SplitMix64 of the ordered pair): among
+// equally heavy edges a node takes the one with the larger key, so that
+// uniform weights do not chain a whole path or cycle into one aggregate.
+uint64_t edge_key(int i, int j) {
+    uint64_t x = (static_cast<uint64_t>(std::min(i, j)) << 32) | static_cast<uint32_t>(std::max(i, j));
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Heaviest-neighbour forest: node i is joined to its heaviest neighbour (ties
+// by edge_key); the connected groups are the aggregates, labelled in the
+// order of their smallest node. Returns the number of aggregates.
+int forest_aggregates(const HostLevel& L, std::vector<int>& agg) {
+    std::vector<int> parent(static_cast<size_t>(L.n));
+    for (int i = 0; i < L.n; ++i) parent[i] = i;
+    auto find = [&](int x) {
+        while (parent[x] != x) {
+            parent[x] = parent[parent[x]];
+            x = parent[x];
+        }
+        return x;
+    };
+    for (int i = 0; i < L.n; ++i) {
+        int best = -1;
+        double bw = -INFINITY;
+        uint64_t bk = 0;
+        for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
+            const uint64_t k = edge_key(i, L.col[e]);
+            if (L.w[e] > bw || (L.w[e] == bw && k > bk)) {
+                bw = L.w[e];
+                bk = k;
+                best = L.col[e];
+            }
+        }
+        if (best >= 0) {
+            const int a = find(i), b = find(best);
+            if (a != b) parent[std::max(a, b)] = std::min(a, b);
+        }
+    }
+    agg.assign(static_cast<size_t>(L.n), -1);
+    std::vector<int> label(static_cast<size_t>(L.n), -1);
+    int nc = 0;
+    for (int i = 0; i < L.n; ++i) {
+        const int r = find(i);
+        if (label[r] < 0) label[r] = nc++;
+        agg[i] = label[r];
+    }
+    return nc;
+}
+
+// Members of each aggregate (CSR, ascending node order) and the next level:
+// W' sums the weights between aggregates in member and entry order, columns
+// ascending per row; mass' sums the members' mass.
+void galerkin(const HostLevel& L, const std::vector<int>& agg, int nc, std::vector<int>& mrp,
+              std::vector<int>& mem, HostLevel& C) {
+    mrp.assign(static_cast<size_t>(nc) + 1, 0);
+    for (int i = 0; i < L.n; ++i) ++mrp[agg[i] + 1];
+    for (int a = 0; a < nc; ++a) mrp[a + 1] += mrp[a];
+    mem.assign(static_cast<size_t>(L.n), 0);
+    std::vector<int> at(mrp.begin(), mrp.end() - 1);
+    for (int i = 0; i < L.n; ++i) mem[at[agg[i]]++] = i;
+    C.n = nc;
+    C.rp.assign(static_cast<size_t>(nc) + 1, 0);
+    C.col.clear();
+    C.w.clear();
+    C.mass.assign(static_cast<size_t>(nc), 0.0);
+    std::vector<int> slot(static_cast<size_t>(nc), -1);
+    std::vector<std::pair<int, double>> row;
+    for (int a = 0; a < nc; ++a) {
+        row.clear();
+        for (int k = mrp[a]; k < mrp[a + 1]; ++k) {
+            const int i = mem[k];
+            C.mass[a] += L.mass[i];
+            for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
+                const int b = agg[L.col[e]];
+                if (b == a) continue;
+                if (slot[b] < 0) {
+                    slot[b] = static_cast<int>(row.size());
+                    row.emplace_back(b, L.w[e]);
+                } else {
+                    row[slot[b]].second += L.w[e];
+                }
+            }
+        }
+        for (const auto& pr : row) slot[pr.first] = -1;
+        std::sort(row.begin(), row.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        for (const auto& pr : row) {
+            C.col.push_back(pr.first);
+            C.w.push_back(pr.second);
+        }
+        C.rp[a + 1] = static_cast<int>(C.col.size());
+    }
+}
+
+// Dense inverse of the SPD matrix diag(a) - W (Cholesky, then L^-T L^-1).
+void dense_inverse(const HostLevel& L, const std::vector<double>& a, std::vector<double>& inv) {
+    const size_t n = static_cast<size_t>(L.n);
+    std::vector<double> A(n * n, 0.0);
+    for (size_t i = 0; i < n; ++i) {
+        A[i * n + i] = a[i];
+        for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) A[i * n + L.col[e]] -= L.w[e];
+    }
+    for (size_t j = 0; j < n; ++j) {  // lower Cholesky factor in place
+        double d = A[j * n + j];
+        for (size_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        d = std::sqrt(d);
+        A[j * n + j] = d;
+        for (size_t i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (size_t k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / d;
+        }
+    }
+    std::vector<double> Li(n * n, 0.0);  // L^-1, lower
+    for (size_t j = 0; j < n; ++j) {
+        Li[j * n + j] = 1.0 / A[j * n + j];
+        for (size_t i = j + 1; i < n; ++i) {
+            double v = 0.0;
+            for (size_t k = j; k < i; ++k) v -= A[i * n + k] * Li[k * n + j];
+            Li[i * n + j] = v / A[i * n + i];
+        }
+    }
+    inv.assign(n * n, 0.0);
+    for (size_t i = 0; i < n; ++i)
+        for (size_t j = 0; j <= i; ++j) {
+            double v = 0.0;
+            for (size_t k = i; k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
+            inv[i * n + j] = v;
+            inv[j * n + i] = v;
+        }
+}
+
+constexpr int ML_DENSE_MAX = 2048;
+
+int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarchy* h) {
+    const int n = g->n;
+    const int64_t nnz = g->nnz;
+    std::vector<HostLevel> lv(1);
+    HostLevel& L0 = lv[0];
+    L0.n = n;
+    L0.rp.resize(static_cast<size_t>(n) + 1, 0);
+    L0.col.resize(static_cast<size_t>(nnz));
+    L0.w.assign(static_cast<size_t>(nnz), 1.0);
+    L0.mass.assign(static_cast<size_t>(n), 1.0);
+    HIPCHK(hipStreamSynchronize(st));
+    if (n > 0) HIPCHK(hipMemcpy(L0.rp.data(), g->row_ptr, L0.rp.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (nnz > 0) {
+        HIPCHK(hipMemcpy(L0.col.data(), g->col_idx, L0.col.size() * sizeof(int), hipMemcpyDeviceToHost));
+        if (g->val_type == FJ_VAL_F64) {
+            HIPCHK(hipMemcpy(L0.w.data(), g->val, L0.w.size() * sizeof(double), hipMemcpyDeviceToHost));
+        } else if (g->val_type == FJ_VAL_F32) {
+            std::vector<float> wf(static_cast<size_t>(nnz));
+            HIPCHK(hipMemcpy(wf.data(), g->val, wf.size() * sizeof(float), hipMemcpyDeviceToHost));
+            for (size_t e = 0; e < wf.size(); ++e) L0.w[e] = wf[e];
+        }
+    }
+    // coarsen
+    std::vector<std::vector<int>> aggs, mrps, mems;
+    while (static_cast<int>(lv.size()) < ML_MAXL && lv.back().n > coarse_max) {
+        std::vector<int> agg, mrp, mem;
+        const int nc = forest_aggregates(lv.back(), agg);
+        if (static_cast<int64_t>(nc) * 10 > static_cast<int64_t>(lv.back().n) * 9) break;  // < 10 % smaller
+        HostLevel C;
+        galerkin(lv.back(), agg, nc, mrp, mem, C);
+        aggs.push_back(std::move(agg));
+        mrps.push_back(std::move(mrp));
+        mems.push_back(std::move(mem));
+        lv.push_back(std::move(C));
+    }
+    const int levels = static_cast<int>(lv.size());
+    std::vector<std::vector<double>> a(levels);
+    std::vector<std::vector<int>> longs(levels), clongs(levels);
+    for (int l = 0; l < levels; ++l) {
+        const HostLevel& L = lv[l];
+        a[l].resize(static_cast<size_t>(L.n));
+        for (int i = 0; i < L.n; ++i) {
+            double d = L.mass[i];
+            for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) d += L.w[e];
+            a[l][i] = d;
+            if (L.rp[i + 1] - L.rp[i] > ML_LONG) longs[l].push_back(i);
+        }
+        if (l + 1 < levels)
+            for (int c = 0; c + 1 < static_cast<int>(mrps[l].size()); ++c)
+                if (mrps[l][c + 1] - mrps[l][c] > ML_LONG) clongs[l].push_back(c);
+    }
+    const HostLevel& last = lv.back();
+    std::vector<double> inv;
+    if (last.n > 0 && last.n <= ML_DENSE_MAX) dense_inverse(last, a.back(), inv);
+    // device layout: per level rp, col, w, longs, a, ainv (+ agg, mrp, mem, clongs, t for levels with a
+    // coarser one), rbuf and xbuf for l >= 1, then the dense inverse
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    struct Off { size_t rp, col, w, longs, a, ainv, agg, mrp, mem, clongs, t, rbuf, xbuf; };
+    std::vector<Off> o(levels);
+    for (int l = 0; l < levels; ++l) {
+        const HostLevel& L = lv[l];
+        const size_t nl = static_cast<size_t>(L.n);
+        o[l].rp = take(sizeof(int) * (nl + 1));
+        o[l].col = take(sizeof(int) * L.col.size());
+        o[l].w = take(sizeof(double) * L.w.size());
+        o[l].longs = take(sizeof(int) * longs[l].size());
+        o[l].a = take(sizeof(double) * nl);
+        o[l].ainv = take(sizeof(double) * nl);
+        if (l + 1 < levels) {
+            o[l].agg = take(sizeof(int) * nl);
+            o[l].mrp = take(sizeof(int) * mrps[l].size());
+            o[l].mem = take(sizeof(int) * nl);
+            o[l].clongs = take(sizeof(int) * clongs[l].size());
+            o[l].t = take(sizeof(double) * nl);
+        }
+        if (l >= 1) {
+            o[l].rbuf = take(sizeof(double) * nl);
+            o[l].xbuf = take(sizeof(double) * nl);
+        }
+    }
+    const size_t inv_off = take(sizeof(double) * inv.size());
+    void* mem = nullptr;
+    HIPCHK(hipMalloc(&mem, off));
+    h->mem = mem;
+    char* base = static_cast<char*>(mem);
+    auto put = [&](size_t at, const void* src, size_t bytes) -> int {
+        if (bytes) HIPCHK(hipMemcpy(base + at, src, bytes, hipMemcpyHostToDevice));
+        return FJ_OK;
+    };
+    h->levels = levels;
+    for (int l = 0; l < levels; ++l) {
+        const HostLevel& L = lv[l];
+        const size_t nl = static_cast<size_t>(L.n);
+        std::vector<double> ainv(nl);
+        for (size_t i = 0; i < nl; ++i) ainv[i] = 1.0 / a[l][i];
+        if (int rc = put(o[l].rp, L.rp.data(), sizeof(int) * (nl + 1))) return rc;
+        if (int rc = put(o[l].col, L.col.data(), sizeof(int) * L.col.size())) return rc;
+        if (int rc = put(o[l].w, L.w.data(), sizeof(double) * L.w.size())) return rc;
+        if (int rc = put(o[l].longs, longs[l].data(), sizeof(int) * longs[l].size())) return rc;
+        if (int rc = put(o[l].a, a[l].data(), sizeof(double) * nl)) return rc;
+        if (int rc = put(o[l].ainv, ainv.data(), sizeof(double) * nl)) return rc;
+        h->n[l] = L.n;
+        h->nnz[l] = static_cast<int64_t>(L.col.size());
+        if (l >= 1) {
+            h->rbuf[l] = reinterpret_cast<double*>(base + o[l].rbuf);
+            h->xbuf[l] = reinterpret_cast<double*>(base + o[l].xbuf);
+        }
+        if (l + 1 < levels) {
+            if (int rc = put(o[l].agg, aggs[l].data(), sizeof(int) * nl)) return rc;
+            if (int rc = put(o[l].mrp, mrps[l].data(), sizeof(int) * mrps[l].size())) return rc;
+            if (int rc = put(o[l].mem, mems[l].data(), sizeof(int) * nl)) return rc;
+            if (int rc = put(o[l].clongs, clongs[l].data(), sizeof(int) * clongs[l].size())) return rc;
+            MlLevel& M = h->lv[l];
+            M.n = L.n;
+            M.nc = lv[l + 1].n;
+            M.nlong = static_cast<int>(longs[l].size());
+            M.nclong = static_cast<int>(clongs[l].size());
+            M.rp = reinterpret_cast<const int*>(base + o[l].rp);
+            M.col = reinterpret_cast<const int*>(base + o[l].col);
+            M.w = reinterpret_cast<const double*>(base + o[l].w);
+            M.longs = reinterpret_cast<const int*>(base + o[l].longs);
+            M.a = reinterpret_cast<const double*>(base + o[l].a);
+            M.ainv = reinterpret_cast<const double*>(base + o[l].ainv);
+            M.agg = reinterpret_cast<const int*>(base + o[l].agg);
+            M.mrp = reinterpret_cast<const int*>(base + o[l].mrp);
+            M.mem = reinterpret_cast<const int*>(base + o[l].mem);
+            M.clongs = reinterpret_cast<const int*>(base + o[l].clongs);
+            M.t = reinterpret_cast<double*>(base + o[l].t);
+        }
+    }
+    h->nL = last.n;
+    h->ainvL = reinterpret_cast<const double*>(base + o[levels - 1].ainv);
+    if (!inv.empty()) {
+        if (int rc = put(inv_off, inv.data(), sizeof(double) * inv.size())) return rc;
+        h->inv = reinterpret_cast<const double*>(base + inv_off);
+    }
+    return FJ_OK;
+}
+}  // namespace
+
+int fj_hierarchy_create(const fj_csr* g, int32_t coarse_max, fj_hierarchy** out, void* stream) {
+    return guarded([&]() -> int {
+        if (!out) return FJ_ERR_INVALID_ARG;
+        *out = nullptr;
+        if (int rc = check_graph_args(g)) return rc;
+        if (coarse_max < 0) return FJ_ERR_INVALID_ARG;
+        std::unique_ptr<fj_hierarchy> h(new fj_hierarchy);
+        if (int rc = current_device(&h->dev)) return rc;
+        h->n0 = g->n;
+        h->nnz0 = g->nnz;
+        int rc = build_hierarchy(g, coarse_max > 0 ? coarse_max : 1024, static_cast<hipStream_t>(stream), h.get());
+        if (rc) {
+            if (h->mem) (void)hipFree(h->mem);
+            return rc;
+        }
+        *out = h.release();
+        return FJ_OK;
+    });
+}
+
+int fj_hierarchy_shape(const fj_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz, int32_t* dense) {
+    return guarded([&]() -> int {
+        if (!h) return FJ_ERR_INVALID_ARG;
+        if (levels) *levels = h->levels;
+        for (int l = 0; l < ML_MAXL; ++l) {
+            if (n) n[l] = l < h->levels ? h->n[l] : 0;
+            if (nnz) nnz[l] = l < h->levels ? h->nnz[l] : 0;
+        }
+        if (dense) *dense = h->inv != nullptr ? 1 : 0;
+        return FJ_OK;
+    });
+}
+
+int fj_hierarchy_destroy(fj_hierarchy* h) {
+    return guarded([&]() -> int {
+        if (!h) return FJ_OK;
+        int rc = FJ_OK;
+        if (h->mem) {
+            if (hipDeviceSynchronize() != hipSuccess || hipFree(h->mem) != hipSuccess) rc = FJ_ERR_HIP;
+        }
+        delete h;
+        return rc;
+    });
+}
+
 int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,
                 int32_t steps, double tol, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
     return guarded([&]() -> int {
@@ -2123,6 +2559,7 @@ int fj_solve(const fj_csr* g, const void* plan, int32_t k, const double* S, int6
         if (int rc = check_opts(opts)) return rc;
         if (k < 1 || lds < k || ldz < k || !S || !Z) return FJ_ERR_INVALID_ARG;
         if ((opts->flags & FJ_BLOCK_CG) && k < 2) return FJ_ERR_INVALID_ARG;
+        if (int rc = check_ml(g, k, opts)) return rc;
         if ((opts->flags & FJ_WARM_START) && (k != 1 || (opts->flags & FJ_TWO_SOLVE))) {
             std::snprintf(g_last_error, sizeof g_last_error, "FJ_WARM_START needs k = 1 without FJ_TWO_SOLVE");
             return FJ_ERR_INVALID_ARG;
@@ -2143,6 +2580,7 @@ int fj_indices(const fj_csr* g, const void* plan, int32_t k, const double* S, in
         if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
         if (g->n == 0) return FJ_ERR_INVALID_ARG;
         if ((opts->flags & FJ_BLOCK_CG) && k < 2) return FJ_ERR_INVALID_ARG;
+        if (int rc = check_ml(g, k, opts)) return rc;
         if (k == 1 && !(opts->flags & FJ_TWO_SOLVE))
             return solve_one(g, plan, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
         return solve_many(g, plan, k, S, lds, nullptr, 0, *opts, ws, ws_bytes, stream, true, out, info);
@@ -2156,6 +2594,10 @@ int fj_indices_noalloc(const fj_csr* g, const void* plan, int32_t k, const doubl
         if (int rc = check_opts(opts)) return rc;
         if (k < 1 || lds < k || !S || !out) return FJ_ERR_INVALID_ARG;
         if (g->n == 0) return FJ_ERR_INVALID_ARG;
+        if (opts->flags & FJ_MULTILEVEL) {  // a hierarchy's work vectors are shared, not scratch
+            std::snprintf(g_last_error, sizeof g_last_error, "fj_indices_noalloc: FJ_MULTILEVEL is not available");
+            return FJ_ERR_INVALID_ARG;
+        }
         if (opts->flags & FJ_PROFILE) {  // profiling creates events
             std::snprintf(g_last_error, sizeof g_last_error, "fj_indices_noalloc: FJ_PROFILE is not available");
             return FJ_ERR_INVALID_ARG;

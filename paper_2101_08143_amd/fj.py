@@ -41,13 +41,15 @@ FJ_TWO_SOLVE, FJ_NO_RANGE_CHECK, FJ_VALIDATE_GRAPH, FJ_PROFILE, FJ_NO_TUNE, FJ_W
     1, 2, 4, 8, 16, 32, 64
 FJ_DIAG_PRECOND = 128
 FJ_BLOCK_CG = 256
+FJ_MULTILEVEL = 512
 
 INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
            "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
-           "fj_spmm_set_choice", "fj_gather_bound", "fj_gather_bound_sliced", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
+           "fj_spmm_set_choice", "fj_hierarchy_create", "fj_hierarchy_shape", "fj_hierarchy_destroy",
+           "fj_gather_bound", "fj_gather_bound_sliced", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
            "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
            "fj_server_step", "fj_server_poll", "fj_server_cancel")
@@ -60,7 +62,8 @@ class fj_csr(ctypes.Structure):
 
 class fj_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("hierarchy", ctypes.c_void_p)]
 
 
 class fj_indices_t(ctypes.Structure):
@@ -126,6 +129,9 @@ def lib():
         L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32), P(i32)]
         L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32, i32, i32]
         L.fj_gather_bound.argtypes = [P(fj_csr), vp, vp, vp]
+        L.fj_hierarchy_create.argtypes = [P(fj_csr), i32, P(vp), vp]
+        L.fj_hierarchy_shape.argtypes = [vp, P(i32), P(i32), P(i64), P(i32)]
+        L.fj_hierarchy_destroy.argtypes = [vp]
         L.fj_gather_bound_sliced.argtypes = [P(fj_csr), vp, i32, vp, i32, i32, vp, P(i64), vp]
         L.fj_dynamics.argtypes = [P(fj_csr), vp, vp, vp, vp, i32, ctypes.c_double, vp, sz, vp, P(fj_info)]
         L.fj_solve.argtypes = [P(fj_csr), vp, i32, vp, i64, vp, i64, P(fj_opts), vp, sz, vp, P(fj_info)]
@@ -142,7 +148,7 @@ def lib():
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
         for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
-                     "fj_gather_bound_sliced",
+                     "fj_gather_bound_sliced", "fj_hierarchy_create", "fj_hierarchy_shape", "fj_hierarchy_destroy",
                      "fj_dynamics", "fj_solve", "fj_indices", "fj_indices_noalloc", "fj_server_create",
                      "fj_server_destroy",
                      "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll",
@@ -166,9 +172,13 @@ def fj_default_opts() -> fj_opts:
     return o
 
 
-def make_opts(eps=1e-6, rtol=0.0, max_iter=0, precision=FJ_FP64, flags=0) -> fj_opts:
+def make_opts(eps=1e-6, rtol=0.0, max_iter=0, precision=FJ_FP64, flags=0, hierarchy=None) -> fj_opts:
+    """Solve options. hierarchy: a Hierarchy; passing one sets FJ_MULTILEVEL."""
     o = fj_default_opts()
     o.eps, o.rtol, o.max_iter, o.precision, o.flags = eps, rtol, max_iter, precision, flags
+    if hierarchy is not None:
+        o.flags |= FJ_MULTILEVEL
+        o.hierarchy = hierarchy.handle
     return o
 
 
@@ -286,6 +296,44 @@ def fj_spmm_set_choice(graph: Graph, kb: int, cpl: int, grid: int, precision: in
                                   int(split), int(passes))
     if rc != FJ_OK:
         raise FJError(rc, "fj_spmm_set_choice")
+
+
+class Hierarchy:
+    """The aggregation hierarchy of FJ_MULTILEVEL for one graph (see
+    include/fj.h, fj_hierarchy_create). It keeps the graph alive; pass it to
+    make_opts(hierarchy=...). One solve at a time per hierarchy."""
+
+    def __init__(self, graph: "Graph", coarse_max: int = 0, stream=None):
+        import torch
+        self.graph = graph
+        self.handle = None
+        h = ctypes.c_void_p()
+        rc = lib().fj_hierarchy_create(ctypes.byref(graph.csr), int(coarse_max), ctypes.byref(h),
+                                       _stream_handle(torch, stream))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_hierarchy_create")
+        self.handle = h.value
+
+    def shape(self):
+        """(levels, [n per level], [stored entries per level], dense last level)"""
+        lv, dense = ctypes.c_int32(0), ctypes.c_int32(0)
+        n, nnz = (ctypes.c_int32 * 16)(), (ctypes.c_int64 * 16)()
+        rc = lib().fj_hierarchy_shape(self.handle, ctypes.byref(lv), n, nnz, ctypes.byref(dense))
+        if rc != FJ_OK:
+            raise FJError(rc, "fj_hierarchy_shape")
+        k = lv.value
+        return k, list(n[:k]), list(nnz[:k]), bool(dense.value)
+
+    def close(self):
+        if self.handle is not None:
+            lib().fj_hierarchy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fj_gather_bound(graph: Graph, x, y=None, stream=None):

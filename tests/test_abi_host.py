@@ -238,3 +238,39 @@ def test_spmm_shape_rules(lib):
     for kb, cpl, split, passes in bad:
         assert lib.fj_spmm_set_choice(ctypes.byref(csr), kb, 0, cpl, 64, split, passes) == fj.FJ_ERR_INVALID_ARG, \
             (kb, cpl, split, passes)
+
+
+def test_opts_layout_matches_header():
+    """fj_opts in the binding has the header's fields in the header's order."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct fj_opts \{(.*?)\} fj_opts;", src, flags=re.S).group(1)
+    fields = re.findall(r"\*?(\w+);", body)
+    assert fields == [f[0] for f in fj.fj_opts._fields_]
+    assert ctypes.sizeof(fj.fj_opts) == 40
+
+
+def test_multilevel_argument_errors(lib):
+    """FJ_MULTILEVEL needs FP64 and a hierarchy, excludes FJ_DIAG_PRECOND and
+    FJ_BLOCK_CG and fj_indices_noalloc; the hierarchy calls check their
+    arguments (all before any device work)."""
+    csr = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=None, val_type=fj.FJ_VAL_UNIT)
+    out = (fj.fj_indices_t * 4)()
+    fake = 4096  # never dereferenced: every case fails before the hierarchy is read
+    for prec, flags, h, k in ((fj.FJ_FP64, fj.FJ_MULTILEVEL, None, 1), (fj.FJ_MIXED, fj.FJ_MULTILEVEL, fake, 1),
+                              (fj.FJ_FP64, fj.FJ_MULTILEVEL | fj.FJ_DIAG_PRECOND, fake, 1),
+                              (fj.FJ_FP64, fj.FJ_MULTILEVEL | fj.FJ_BLOCK_CG, fake, 4)):
+        o = fj.make_opts(precision=prec, flags=flags)
+        o.hierarchy = h
+        rc = lib.fj_indices(ctypes.byref(csr), ctypes.c_void_p(256), k, ctypes.c_void_p(256), k,
+                            ctypes.byref(o), ctypes.c_void_p(256), 1 << 30, None, out, None)
+        assert rc == fj.FJ_ERR_INVALID_ARG, (prec, flags, h, k)
+    o = fj.make_opts(flags=fj.FJ_MULTILEVEL)
+    o.hierarchy = fake
+    assert lib.fj_indices_noalloc(ctypes.byref(csr), ctypes.c_void_p(256), 1, ctypes.c_void_p(256), 1,
+                                  ctypes.byref(o), None, out, None) == fj.FJ_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert lib.fj_hierarchy_create(ctypes.byref(csr), 0, None, None) == fj.FJ_ERR_INVALID_ARG
+    assert lib.fj_hierarchy_create(ctypes.byref(csr), -1, ctypes.byref(h), None) == fj.FJ_ERR_INVALID_ARG
+    assert lib.fj_hierarchy_destroy(None) == fj.FJ_OK
+    lv = ctypes.c_int32(0)
+    assert lib.fj_hierarchy_shape(None, ctypes.byref(lv), None, None, None) == fj.FJ_ERR_INVALID_ARG
