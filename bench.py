@@ -285,6 +285,51 @@ def small_configs_form(args, fj, W, torch, dev):
     return out
 
 
+def multilevel_form(args, fj, W, torch, dev):
+    """The 100K-node Chung-Lu graph with weights log-uniform over a factor 1e6:
+    microseconds per certified solve with the 2x2 blocks (default), Jacobi and
+    the aggregation V-cycle of FJ_MULTILEVEL, against the oracle per index."""
+    g, s, spec = W.workload("wide100k")
+    G = fj.Graph.from_csr(g, device=dev, validate=False)
+    sd = torch.from_numpy(s).to(dev)
+    t0 = time.perf_counter()
+    H = fj.Hierarchy(G)
+    t_build = time.perf_counter() - t0
+    levels, ns, nnzs, dense = H.shape()
+    ref = None
+    if args.cpu_solves > 0:
+        from oracle import sparse as O
+        ref, _, _ = O.indices(g, s)
+    form = {"graph": spec["desc"], "nnz": g.nnz,
+            "hierarchy": {"build_s": t_build, "levels": levels, "nodes": ns, "entries": nnzs,
+                          "dense_last_level": dense}}
+    for name, o in (("pairs", fj.make_opts(eps=args.eps)),
+                    ("jacobi", fj.make_opts(eps=args.eps, flags=fj.FJ_DIAG_PRECOND)),
+                    ("multilevel", fj.make_opts(eps=args.eps, hierarchy=H))):
+        ws = G.workspace(1, o)
+        for _ in range(3):
+            fj.fj_indices(G, sd, o, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 20
+        for _ in range(steps):
+            vals, infos, rc = fj.fj_indices(G, sd, o, ws=ws, check=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        entry = {"us_per_solve": 1e6 * el, "iters": infos[0].iters, "certified": bool(rc == fj.FJ_OK)}
+        if ref is not None:
+            entry["rel_err_vs_oracle"] = {k: abs(vals[0][k] - ref[k]) / abs(ref[k]) for k in fj.INDEX_NAMES}
+        form[name] = entry
+    form["multilevel_speedup_vs_pairs"] = form["pairs"]["us_per_solve"] / form["multilevel"]["us_per_solve"]
+    print(f"[bench] wide100k: pairs {form['pairs']['us_per_solve']:.0f} us ({form['pairs']['iters']} it), "
+          f"multilevel {form['multilevel']['us_per_solve']:.0f} us ({form['multilevel']['iters']} it)",
+          file=sys.stderr, flush=True)
+    H.close()
+    del G, sd
+    torch.cuda.empty_cache()
+    return form
+
+
 def fifo_baseline(args, fj, W, torch, graphs, pools, server_sat_rps):
     """The same kind of request stream served the plain way: one FP64
     single-vector fj_indices call per opinion vector, requests in arrival
@@ -674,6 +719,7 @@ def main():
         del z_dyn, ws
     if args.small_configs:
         result["forms"].update(small_configs_form(args, fj, W, torch, dev))
+        result["forms"]["wide100k_multilevel"] = multilevel_form(args, fj, W, torch, dev)
     if args.batched_steps > 0:
         result["forms"].update(batched_forms(args, fj, W, torch, dev))
     if args.serve_requests > 0:

@@ -238,9 +238,10 @@ int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t c
  * solver the method calls (Lemma ST: a nearly-linear-time solver for
  * Laplacian systems, built there by approximate Gaussian elimination) in the
  * same class: an aggregation hierarchy of I + L with a V-cycle.
- *   Level 0 is I + L = diag(a_0) - W_0 (a_0 = 1 + weighted degree). Every node
- *   points to its heaviest neighbour (ties broken by a hash of the edge); the connected
- *   groups of these pointers are the aggregates, the nodes of the next level.
+ *   Level 0 is I + L = diag(a_0) - W_0 (a_0 = 1 + weighted degree). Node by
+ *   node in index order, each joins the group of its heaviest neighbour (ties
+ *   broken by a hash of the edge) unless the union would exceed 64 nodes; the
+ *   groups are the aggregates, the nodes of the next level.
  *   The next level keeps the form diag(a) - W (Galerkin: P^T A P with P the
  *   0/1 aggregate indicator): W sums the weights between aggregates, the
  *   identity part becomes the aggregate sizes. Coarsening stops at
@@ -251,8 +252,9 @@ int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t c
  *   correction on every level; it is a fixed symmetric positive definite
  *   operator, so CG stays CG.
  * Built on the host from a device-to-host copy of the CSR (synchronous on
- * `stream`), then uploaded: the hierarchy holds its own FP64 copy of every
- * level and the V-cycle's work vectors (about 4 n + 3 nnz doubles in all),
+ * `stream`), then uploaded: the hierarchy holds its own copy of every level
+ * (12 bytes per stored entry: int column, FP64 weight) and the V-cycle's work
+ * vectors (up to seven doubles per node of each level),
  * allocated here. Rebuild it if the graph's weights change. A hierarchy
  * serves one solve at a time (its work vectors are shared): concurrent solves
  * need one each.

@@ -50,6 +50,8 @@ struct fj_hierarchy {
     const double* ainvL = nullptr;     // its 1 / a
     double* rbuf[ML_MAXL] = {};        // right-hand side of level l >= 1
     double* xbuf[ML_MAXL] = {};        // V-cycle result of level l >= 1
+    double* ybuf[ML_MAXL] = {};        // D^-1 times the right-hand side, every level
+    const double* ainvs[ML_MAXL] = {}; // 1 / a, every level
     void* mem = nullptr;               // one device allocation holding all of it
 };
 
@@ -403,14 +405,20 @@ int vcycle(hipStream_t st, const fj_hierarchy* h, const double* b, double* x, co
     };
     int grid = 1;
     const double* bl = b;
+    if (h->levels > 1) {
+        if (int rc = grid_for(k_ml_scale, (static_cast<int64_t>(h->n0) + WG - 1) / WG, &grid)) return rc;
+        k_ml_scale<<<grid, WG, 0, st>>>(h->n0, b, h->ainvs[0], h->ybuf[0], ctrl);
+        HIPCHK(hipGetLastError());
+    }
     for (int l = 0; l + 1 < h->levels; ++l) {
         const MlLevel& L = h->lv[l];
         if (int rc = rows_grid(k_ml_rows<OpPre>, L.n, L.nlong, &grid)) return rc;
-        k_ml_rows<OpPre><<<grid, WG, 0, st>>>(L.n, L.rp, L.col, L.w, L.longs, L.nlong, OpPre{bl, L.ainv, L.t}, ctrl);
+        k_ml_rows<OpPre><<<grid, WG, 0, st>>>(L.n, L.rp, L.col, L.w, L.longs, L.nlong,
+                                              OpPre{bl, h->ybuf[l], L.t}, ctrl);
         HIPCHK(hipGetLastError());
         if (int rc = rows_grid(k_ml_rows<OpSum>, L.nc, L.nclong, &grid)) return rc;
         k_ml_rows<OpSum><<<grid, WG, 0, st>>>(L.nc, L.mrp, L.mem, nullptr, L.clongs, L.nclong,
-                                              OpSum{L.t, h->rbuf[l + 1]}, ctrl);
+                                              OpSum{L.t, h->ainvs[l + 1], h->rbuf[l + 1], h->ybuf[l + 1]}, ctrl);
         HIPCHK(hipGetLastError());
         bl = h->rbuf[l + 1];
     }
@@ -428,7 +436,7 @@ int vcycle(hipStream_t st, const fj_hierarchy* h, const double* b, double* x, co
         const double* b_l = l == 0 ? b : h->rbuf[l];
         double* out = l == 0 ? x : h->xbuf[l];
         if (int rc = grid_for(k_ml_prolong, (static_cast<int64_t>(L.n) + WG - 1) / WG, &grid)) return rc;
-        k_ml_prolong<<<grid, WG, 0, st>>>(L.n, b_l, L.ainv, L.agg, h->xbuf[l + 1], L.t, ctrl);
+        k_ml_prolong<<<grid, WG, 0, st>>>(L.n, h->ybuf[l], L.agg, h->xbuf[l + 1], L.t, ctrl);
         HIPCHK(hipGetLastError());
         if (int rc = rows_grid(k_ml_rows<OpPost>, L.n, L.nlong, &grid)) return rc;
         k_ml_rows<OpPost><<<grid, WG, 0, st>>>(L.n, L.rp, L.col, L.w, L.longs, L.nlong,
@@ -2142,11 +2150,14 @@ uint64_t edge_key(int i, int j) {
     return x ^ (x >> 31);
 }
 
-// Heaviest-neighbour forest: node i is joined to its heaviest neighbour (ties
-// by edge_key); the connected groups are the aggregates, labelled in the
-// order of their smallest node. Returns the number of aggregates.
+// Heaviest-neighbour forest: node i, in index order, is joined to its
+// heaviest neighbour (ties by edge_key) unless the merged group would exceed
+// ML_LONG nodes; the groups are the aggregates, labelled in the order of their
+// smallest node. The cap keeps a hub from gathering most of a power-law graph
+// into one aggregate (one member list, and one coarse row, as long as the
+// graph). Returns the number of aggregates.
 int forest_aggregates(const HostLevel& L, std::vector<int>& agg) {
-    std::vector<int> parent(static_cast<size_t>(L.n));
+    std::vector<int> parent(static_cast<size_t>(L.n)), size(static_cast<size_t>(L.n), 1);
     for (int i = 0; i < L.n; ++i) parent[i] = i;
     auto find = [&](int x) {
         while (parent[x] != x) {
@@ -2169,7 +2180,10 @@ int forest_aggregates(const HostLevel& L, std::vector<int>& agg) {
         }
         if (best >= 0) {
             const int a = find(i), b = find(best);
-            if (a != b) parent[std::max(a, b)] = std::min(a, b);
+            if (a != b && size[a] + size[b] <= ML_LONG) {
+                parent[std::max(a, b)] = std::min(a, b);
+                size[std::min(a, b)] += size[std::max(a, b)];
+            }
         }
     }
     agg.assign(static_cast<size_t>(L.n), -1);
@@ -2329,7 +2343,7 @@ int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarch
         off = align_up(off + std::max<size_t>(bytes, 1));
         return o;
     };
-    struct Off { size_t rp, col, w, longs, a, ainv, agg, mrp, mem, clongs, t, rbuf, xbuf; };
+    struct Off { size_t rp, col, w, longs, a, ainv, agg, mrp, mem, clongs, t, y, rbuf, xbuf; };
     std::vector<Off> o(levels);
     for (int l = 0; l < levels; ++l) {
         const HostLevel& L = lv[l];
@@ -2340,6 +2354,7 @@ int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarch
         o[l].longs = take(sizeof(int) * longs[l].size());
         o[l].a = take(sizeof(double) * nl);
         o[l].ainv = take(sizeof(double) * nl);
+        o[l].y = take(sizeof(double) * nl);
         if (l + 1 < levels) {
             o[l].agg = take(sizeof(int) * nl);
             o[l].mrp = take(sizeof(int) * mrps[l].size());
@@ -2375,6 +2390,8 @@ int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarch
         if (int rc = put(o[l].ainv, ainv.data(), sizeof(double) * nl)) return rc;
         h->n[l] = L.n;
         h->nnz[l] = static_cast<int64_t>(L.col.size());
+        h->ybuf[l] = reinterpret_cast<double*>(base + o[l].y);
+        h->ainvs[l] = reinterpret_cast<const double*>(base + o[l].ainv);
         if (l >= 1) {
             h->rbuf[l] = reinterpret_cast<double*>(base + o[l].rbuf);
             h->xbuf[l] = reinterpret_cast<double*>(base + o[l].xbuf);
@@ -2400,6 +2417,7 @@ int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarch
             M.mem = reinterpret_cast<const int*>(base + o[l].mem);
             M.clongs = reinterpret_cast<const int*>(base + o[l].clongs);
             M.t = reinterpret_cast<double*>(base + o[l].t);
+            M.y = h->ybuf[l];
         }
     }
     h->nL = last.n;

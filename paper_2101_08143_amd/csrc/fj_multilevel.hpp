@@ -11,11 +11,12 @@
 // P_l the 0/1 indicator of level l's aggregates (the nodes of level l + 1).
 //
 // One V-cycle on level l, right-hand side b (all FP64):
-//   u = w D^-1 b                      pre-smoothing from 0 (Jacobi, weight w)
-//   t = b - A u                       k_ml_rows<OpPre>: (1-w) b + w W (D^-1 b)
+//   y = D^-1 b                        k_ml_scale on level 0, else with b by OpSum
+//   u = w y                           pre-smoothing from 0 (Jacobi, weight w)
+//   t = b - A u                       k_ml_rows<OpPre>: (1-w) b + w W y
 //   b' = P^T t                        k_ml_rows<OpSum> over the member lists
 //   x' = V-cycle on level l + 1 (the last level: exact dense solve or Jacobi)
-//   u = w D^-1 b + P x'               k_ml_prolong
+//   u = w y + P x'                    k_ml_prolong
 //   x = u + w D^-1 (b - A u)          k_ml_rows<OpPost>
 // Each row of the sparse passes is summed by a group of 8 lanes (entries
 // strided over the lanes, then a fixed shuffle tree); rows with more than 64
@@ -47,6 +48,7 @@ struct MlLevel {
     const int* mem = nullptr;
     const int* clongs = nullptr;  // the long aggregates
     double* t = nullptr;          // work: n
+    double* y = nullptr;          // work: n, D^-1 b
 };
 
 // Row sums of a CSR (weights optional) against op.src, epilogue op.row.
@@ -81,22 +83,35 @@ __global__ void __launch_bounds__(WG) k_ml_rows(int n, const int* __restrict__ r
     }
 }
 
-// t = b - A (w D^-1 b) = (1 - w) b + w W (D^-1 b)
+// t = b - A (w D^-1 b) = (1 - w) b + w W y, y = D^-1 b
 struct OpPre {
     const double* __restrict__ b;
-    const double* __restrict__ ainv;
+    const double* __restrict__ y;
     double* __restrict__ t;
-    __device__ double src(int j) const { return b[j] * ainv[j]; }
+    __device__ double src(int j) const { return y[j]; }
     __device__ void row(int i, double acc) const { t[i] = (1.0 - ML_OMEGA) * b[i] + ML_OMEGA * acc; }
 };
 
-// restriction: b'[A] = sum over the members i of A of t[i]
+// restriction: b'[A] = sum over the members i of A of t[i], and y' = b' / a'
 struct OpSum {
     const double* __restrict__ t;
+    const double* __restrict__ ainv_next;
     double* __restrict__ out;
+    double* __restrict__ y_next;
     __device__ double src(int j) const { return t[j]; }
-    __device__ void row(int i, double acc) const { out[i] = acc; }
+    __device__ void row(int i, double acc) const {
+        out[i] = acc;
+        y_next[i] = acc * ainv_next[i];
+    }
 };
+
+// y = D^-1 b on level 0 (the finer levels get it from OpSum)
+__global__ void __launch_bounds__(WG) k_ml_scale(int n, const double* __restrict__ b,
+                                                 const double* __restrict__ ainv, double* __restrict__ y,
+                                                 const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done != RUNNING) return;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) y[i] = b[i] * ainv[i];
+}
 
 // x = u + w D^-1 (b - a u + W u)
 struct OpPost {
@@ -112,14 +127,12 @@ struct OpPost {
     }
 };
 
-// u = w D^-1 b + P x'
-__global__ void __launch_bounds__(WG) k_ml_prolong(int n, const double* __restrict__ b,
-                                                   const double* __restrict__ ainv, const int* __restrict__ agg,
+// u = w D^-1 b + P x' = w y + P x'
+__global__ void __launch_bounds__(WG) k_ml_prolong(int n, const double* __restrict__ y, const int* __restrict__ agg,
                                                    const double* __restrict__ xc, double* __restrict__ u,
                                                    const Ctrl* __restrict__ ctrl) {
     if (ctrl && ctrl->done != RUNNING) return;
-    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG)
-        u[i] = ML_OMEGA * ainv[i] * b[i] + xc[agg[i]];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) u[i] = ML_OMEGA * y[i] + xc[agg[i]];
 }
 
 // The last level. dense: x = A^-1 b with the stored inverse (one wave per row,

@@ -353,6 +353,21 @@ def opinion_block(n: int, kinds: Sequence[str], seed: int) -> np.ndarray:
     return np.ascontiguousarray(np.stack(cols, axis=1))
 
 
+def log_uniform_weights(g: CSRGraph, span: float, seed: int) -> CSRGraph:
+    """The same graph with FP64 weights log-uniform over a factor `span`
+    (geometric mean 1, so in [span^-1/2, span^1/2]), equal in both stored
+    directions of an edge: u = a 53-bit hash of the edge key, w = span^(u - 1/2)."""
+    import dataclasses
+    rows = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr))
+    lo = np.minimum(rows, g.col.astype(np.uint64))
+    hi = np.maximum(rows, g.col.astype(np.uint64))
+    with np.errstate(over="ignore"):
+        h = (lo * np.uint64(g.n) + hi + np.uint64(seed)) * np.uint64(0x9E3779B97F4A7C15)
+    u = (h >> np.uint64(11)).astype(np.float64) / 2.0 ** 53
+    w = np.exp(np.log(1.0 / np.sqrt(span)) + u * np.log(span))
+    return dataclasses.replace(g, val=w.astype(np.float64))
+
+
 # ---------------------------------------------------------------- named workloads
 
 WORKLOADS = {
@@ -365,6 +380,10 @@ WORKLOADS = {
                  s=("exp", 2003), rtol=0.0,
                  desc="Chung-Lu n=4,000,000, gamma=2.2, mean degree 30, weights float32(U[0.5,2]); "
                       "s~Exp(1) min-max scaled"),
+    "wide100k": dict(graph=lambda: log_uniform_weights(chung_lu(100_000, 2.5, 10.0, 31), 1e6, 7),
+                     s=("uniform", 32), rtol=0.0,
+                     desc="Chung-Lu n=100,000, gamma=2.5, mean degree 10, FP64 weights log-uniform over a "
+                          "factor 1e6; s~U[0,1]"),
 }
 
 def serving_graph_params(count: int = 32, seed0: int = 1100):

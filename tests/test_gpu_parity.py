@@ -738,14 +738,7 @@ def test_restart_passes_certify(torch_fj, graphs, k, zero_start, name):
 def _skewed_weights(g, span, seed):
     """The same graph with weights log-uniform over a factor `span`, equal in
     both directions of every edge (a hash of the edge's end points)."""
-    import dataclasses
-    rows = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr))
-    lo = np.minimum(rows, g.col.astype(np.uint64))
-    hi = np.maximum(rows, g.col.astype(np.uint64))
-    h = (lo * np.uint64(g.n) + hi + np.uint64(seed)) * np.uint64(0x9E3779B97F4A7C15)
-    u = (h >> np.uint64(11)).astype(np.float64) / 2.0 ** 53
-    w = np.exp(np.log(1.0 / np.sqrt(span)) + u * np.log(span))
-    return dataclasses.replace(g, val=w.astype(np.float64))
+    return W.log_uniform_weights(g, span, seed)
 
 
 @pytest.mark.parametrize("span", [4.0, 1e4])
