@@ -56,6 +56,108 @@ def recorded_traffic(kernel: str):
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["bytes_per_launch"]
 
+# How the committed counter summary is made (from the repository root, one
+# command per rocprofv3 run; $P is the output directory, then
+# `python bench.py --summarize-profiles $P`).
+PROFILE_COMMANDS = [
+    "rocprofv3 --kernel-trace --stats -d $P/stats -o run --output-format csv -- python3 bench.py --steps 10 "
+    "--warmup 2 --cpu-solves 0 --dynamics-steps 300 --serve-requests 0 --fifo-requests 0 --batched-steps 3 "
+    "--two-solve-steps 1 --small-configs 1 --gather-ladder 2",
+    "rocprofv3 --pmc FETCH_SIZE -d $P/fetch -o run --output-format csv -- python3 bench.py --steps 2 --warmup 0 "
+    "--cpu-solves 0 --dynamics-steps 20 --serve-requests 0 --fifo-requests 0 --batched-steps 1 --two-solve-steps 0 "
+    "--small-configs 0 --gather-ladder 2",
+    "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 bench.py --steps 2 --warmup 0 "
+    "--cpu-solves 0 --dynamics-steps 20 --serve-requests 0 --fifo-requests 0 --batched-steps 1 --two-solve-steps 0 "
+    "--small-configs 0 --gather-ladder 2",
+    "rocprofv3 --pmc FETCH_SIZE -d $P/cfetch -o run --output-format csv -- python3 bench.py --copy-calibration 1024",
+    "rocprofv3 --pmc WRITE_SIZE -d $P/cwrite -o run --output-format csv -- python3 bench.py --copy-calibration 1024",
+]
+
+
+def short_kernel_name(name: str) -> str:
+    """'void fj::k_x<fj::Unit, double>(args...)' -> 'k_x<Unit, double>'."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):  # the argument list starts at the first '(' outside <...>
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return name[:cut].replace("fj::", "")
+
+
+def summarize_profiles(d: str) -> None:
+    """rocprofv3 CSVs under d -> profiles/counters_cl4m.json (mean FETCH_SIZE and
+    WRITE_SIZE per working dispatch, scaled by a plain copy of known size) and a
+    markdown table of the stats run on stdout. A dispatch counts as working when
+    its value (or duration) is above 30 % of that kernel's largest."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def table(sub, pattern):
+        f = sorted(glob.glob(os.path.join(d, sub, "**", pattern), recursive=True))
+        if not f:
+            raise SystemExit(f"no {pattern} under {os.path.join(d, sub)}")
+        with open(f[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    def working_mean(vals):
+        top = max(vals)
+        w = [v for v in vals if v > 0.3 * top] or vals
+        return sum(w) / len(w), len(w)
+
+    def counter(sub, name):
+        per = defaultdict(list)
+        for r in table(sub, "*counter_collection.csv"):
+            if r["Counter_Name"] == name:
+                per[short_kernel_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return {k: (*working_mean(v), len(v)) for k, v in per.items()}
+
+    copy = "__amd_rocclr_copyBuffer"
+    cf, cw = counter("cfetch", "FETCH_SIZE"), counter("cwrite", "WRITE_SIZE")
+    copy_bytes = 1024 << 20
+    fscale = copy_bytes / (cf[copy][0] * 1024)
+    wscale = copy_bytes / (cw[copy][0] * 1024)
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        fk, nw, nd = fetch[k]
+        wk = write[k][0]
+        kernels[k] = {"fetch_kib": fk, "write_kib": wk, "working_dispatches": nw, "dispatches": nd,
+                      "bytes_per_launch": int(round(fk * 1024 * fscale + wk * 1024 * wscale))}
+    rec = {"source_sha256": kernel_source_hash(), "sources": KERNEL_SOURCES,
+           "workload": "cl4m (and cl1m for the batched kernels)",
+           "commands": PROFILE_COMMANDS,
+           "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf[copy][0], "write_kib": cw[copy][0],
+                                "fetch_scale": fscale, "write_scale": wscale},
+           "kernels": kernels}
+    with open(COUNTERS, "w") as f:
+        json.dump(rec, f, indent=1)
+    dur = defaultdict(list)
+    for r in table("stats", "*kernel_trace.csv"):
+        dur[short_kernel_name(r["Kernel_Name"])].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in dur.values())
+    print("| Kernel | Calls | Average us | Working launches | Their average us | Share | FETCH_SIZE KiB | "
+          "WRITE_SIZE KiB | HBM GB per launch (scaled) |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
+    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:18]:
+        wavg, nw = working_mean(v)
+        c = kernels.get(k)
+        cols = (f"{c['fetch_kib']:,.0f} | {c['write_kib']:,.0f} | {c['bytes_per_launch'] / 1e9:.3f}" if c
+                else "- | - | -")
+        print(f"| {k} | {len(v)} | {sum(v) / len(v):.1f} | {nw} | {wavg:.1f} | {100 * sum(v) / total:.1f} % | "
+              f"{cols} |")
+    print(f"\ncopy calibration: fetch scale {fscale:.3f}, write scale {wscale:.3f}; "
+          f"sources {rec['source_sha256'][:16]}...")
+
+
 WORKLOAD_META = {
     "ba10k": dict(graph="Barabasi-Albert", n=10_000, m_per_node=3, weights="unit", opinions="U[0,1]"),
     "cl1m": dict(graph="Chung-Lu", n=1_000_000, gamma=2.5, mean_degree=10, weights="unit", opinions="U[0,1]"),
@@ -90,7 +192,7 @@ def spmm_bytes(n: int, nnz: int, val_bytes: int, kb: int, elem: int) -> int:
     return nnz * (4 + val_bytes) + 4 * (n + 1) + 3 * n * kb * elem + 4 * n
 
 
-def gather_ladder(fj, torch, G, g, x64):
+def gather_ladder(fj, torch, G, g, x64, full=True):
     """The bare gather of the SpMV over the same matrix, in CSR order and over
     eight XCD-aligned streams (fj_gather_bound_sliced: workgroup b on stream
     b % 8, hub columns [0, H) read by every stream, the rest cut into eight
@@ -99,8 +201,9 @@ def gather_ladder(fj, torch, G, g, x64):
     out = []
     x32 = x64.float()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for slices, hub in ((1, 0), (8, 0), (8, 131072), (8, 262144), (8, 524288)):
-        for x in (x64, x32):
+    configs = ((1, 0), (8, 0), (8, 131072), (8, 262144), (8, 524288)) if full else ((1, 0), (8, 131072))
+    for slices, hub in configs:
+        for x in ((x64, x32) if full else (x64,)):
             xb = x.element_size()
             check = torch.zeros(2, dtype=torch.int32, device=x.device)
             y, b = fj.fj_gather_bound_sliced(G, x, slices, hub, check=check)
@@ -156,6 +259,16 @@ def batched_forms(args, fj, W, torch, dev):
         elem = 4 if prec == fj.FJ_MIXED else 8
         b = spmm_bytes(g.n, g.nnz, 0, 64, elem)
         avg = ms / max(working, 1)
+        # the same solve with the 64 columns run as 2 x 32 and 4 x 16 column
+        # passes over the CSR (rows design, the tuned grid), then the tuned shape again
+        passes_ms = {}
+        if shape:
+            for npass in (1, 2, 4):
+                cpl = min(shape[0], 2)
+                fj.fj_spmm_set_choice(G, 64, cpl, shape[1], prec, 0, npass)
+                _, pinfos, _ = fj.fj_indices(G, Sd, po, ws=ws)
+                passes_ms[str(npass)] = pinfos[0].ms_spmv / max(max(i.iters for i in pinfos), 1)
+            fj.fj_spmm_set_choice(G, 64, shape[0], shape[1], prec, shape[2], shape[3])
         out[name] = {
             "description": f"k=64 opinion vectors of the 1M-node Chung-Lu graph per call, "
                            f"{'FP32 inner / FP64 refined' if prec == fj.FJ_MIXED else 'FP64'}",
@@ -173,6 +286,7 @@ def batched_forms(args, fj, W, torch, dev):
                                  "column_passes": shape[3]}
             if shape else None,
             "spmm_default_shape_avg_launch_ms": untuned,
+            "spmm_ms_per_working_launch_by_column_passes": passes_ms,
         }
         print(f"[bench] {name}: {1e3 * el:.1f} ms per call", file=sys.stderr, flush=True)
     # O'Leary's block CG on the same 64 vectors (one shared Krylov space)
@@ -509,7 +623,14 @@ def main():
                     help="time the bare gather over XCD-aligned column slices (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="no GPU work: turn the rocprofv3 CSV output under DIR (stats/, fetch/, write/, cfetch/, "
+                         "cwrite/; see PROFILE_COMMANDS) into profiles/counters_cl4m.json and print the kernel "
+                         "table as markdown")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
               "described in DESIGN.md and is not built", file=sys.stderr)
@@ -593,7 +714,9 @@ def main():
     torch.cuda.synchronize()
     gather_ms = e0.elapsed_time(e1) / 10
     del yg
-    ladder = gather_ladder(fj, torch, G, g, xg) if args.gather_ladder else None
+    # --gather-ladder 2: only CSR order and 8 slices with 128K hub columns, FP64 x (one
+    # configuration per kernel name, for the counter runs)
+    ladder = gather_ladder(fj, torch, G, g, xg, full=args.gather_ladder == 1) if args.gather_ladder else None
     del xg
 
     # a plain 1 GiB device copy: the streaming bandwidth this GPU reaches in practice

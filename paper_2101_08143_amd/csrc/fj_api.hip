@@ -2120,12 +2120,15 @@ int fj_gather_bound_sliced(const fj_csr* g, const void* x, int32_t x_bytes, doub
             auto launch = [&](auto kern, auto xp) -> int {
                 if (int rc = grid_for(kern, (g->nnz / 8 + WG) / WG + slices, &grid)) return rc;
                 grid = std::max(slices, grid / slices * slices);
-                kern<<<grid, WG, 0, st>>>(g_slice.col, val, xp, y, g_slice.off, g_slice.cnt, slices, check);
+                kern<<<grid, WG, 0, st>>>(g_slice.col, val, xp, y, g_slice.off, g_slice.cnt, check);
                 HIPCHK(hipGetLastError());
                 return FJ_OK;
             };
-            if (x_bytes == 8) return launch(k_gather_sliced<Vc, double>, static_cast<const double*>(x));
-            return launch(k_gather_sliced<Vc, float>, static_cast<const float*>(x));
+            const double* x8 = static_cast<const double*>(x);
+            const float* x4 = static_cast<const float*>(x);
+            if (slices == 8)
+                return x_bytes == 8 ? launch(k_gather_sliced<Vc, double, 8>, x8) : launch(k_gather_sliced<Vc, float, 8>, x4);
+            return x_bytes == 8 ? launch(k_gather_sliced<Vc, double, 1>, x8) : launch(k_gather_sliced<Vc, float, 1>, x4);
         });
     });
 }

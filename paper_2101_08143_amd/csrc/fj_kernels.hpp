@@ -694,11 +694,11 @@ __global__ void __launch_bounds__(WG) k_gather_bound(Csr<V> g, const double* __r
 // works on stream b % S, so with S = 8 a stream stays on one XCD (workgroups
 // are dealt to the XCDs round robin). check (optional, int[2]) counts the
 // workgroups whose hardware XCD id equals b % 8, and all workgroups.
-template <typename V, typename X>
+template <typename V, typename X, int S>
 __global__ void __launch_bounds__(WG) k_gather_sliced(const int* __restrict__ col, const V* __restrict__ val,
                                                       const X* __restrict__ x, double* __restrict__ y,
                                                       const int64_t* __restrict__ off, const int64_t* __restrict__ cnt,
-                                                      int S, int* __restrict__ check) {
+                                                      int* __restrict__ check) {
     const int s = blockIdx.x % S;
     const int wb = blockIdx.x / S;
     const int gs = gridDim.x / S;
