@@ -182,6 +182,24 @@ def spmv_pq_bytes(n: int, nnz: int, val_bytes: int) -> int:
     return nnz * (4 + val_bytes) + 4 * (n + 1) + 8 * n + 8 * n
 
 
+def solve_bytes(n: int, nnz: int, val_bytes: int, iters: int, pairs: bool) -> dict:
+    """Algorithmic bytes of one certified FP64 solve in units of the survey's
+    per-iteration model B_it = nnz (4 + s_v) + 4 (n + 1) + c_v n 8: c_v counts
+    the n-vectors of doubles each iteration moves (an ideal gather reads p
+    once). Pair path: SpMV p, q (2); k_pair_dots q, z, mq (3), the partner
+    map int32 (0.5) and coefficients float2 (1), the partners' q (at most 1);
+    k_cg_update_pair x, r, z, p read and written, q, mq read (10). Jacobi
+    path: SpMV p, r, q and the FP32 diagonal (3.5); k_cg_update x, r, p read
+    and written, q read, diagonal (7.5). The epilogue reads z, s, writes r
+    and the diagonal (3.5)."""
+    c_v = 2 + 3 + 0.5 + 1 + 1 + 10 if pairs else 3.5 + 7.5
+    csr = nnz * (4 + val_bytes) + 4 * (n + 1)
+    b_it = csr + c_v * n * 8
+    b_epi = csr + 3.5 * n * 8
+    return {"c_v": c_v, "bytes_per_iteration": int(b_it), "bytes_epilogue": int(b_epi),
+            "bytes_per_solve": int(iters * b_it + b_epi)}
+
+
 # One-vector FP64 solves use the 2x2 block preconditioner from this many
 # nodes on (include/fj.h, FJ_DIAG_PRECOND), so their SpMV is k_cg_spmv_pq.
 PAIR_MIN_N = 65536
@@ -735,6 +753,7 @@ def main():
     del src, dst
 
     vals, info = fp64["vals"], fp64["info"]
+    sb = solve_bytes(g.n, g.nnz, val_bytes, info.iters, pairs)
     result = {
         "metric": METRIC,
         "value": args.steps / fp64["elapsed"],
@@ -772,6 +791,8 @@ def main():
             "frac_of_measured_copy": achieved / copy_gbs if copy_gbs > 0 else None,
         },
         "detail": {
+            "solve_model": {**sb, "achieved_GBs_whole_solve": sb["bytes_per_solve"] / (
+                fp64["elapsed"] / args.steps) / 1e9},
             "iters_per_solve": info.iters,
             "passes": info.passes,
             "rel_residual": info.rel_residual,

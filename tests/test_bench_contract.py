@@ -46,3 +46,61 @@ def test_recorded_traffic_lookup():
     t = bench.recorded_traffic("k_cg_spmv<float, double>")
     # present only while the committed counters describe these sources
     assert t is None or t > bench.spmv_bytes(4_000_000, 119_311_046, 4)
+
+
+def test_solve_byte_model():
+    """Per-iteration vector streams of the survey's model: 17.5 n-vectors for
+    the pair path, 11 for Jacobi; a solve is iterations plus the epilogue."""
+    n, nnz = 4_000_000, 119_311_046
+    m = bench.solve_bytes(n, nnz, 4, 11, True)
+    csr = nnz * 8 + 4 * (n + 1)
+    assert m["c_v"] == 17.5 and m["bytes_per_iteration"] == int(csr + 17.5 * n * 8)
+    assert m["bytes_per_solve"] == int(11 * (csr + 17.5 * n * 8) + csr + 3.5 * n * 8)
+    assert bench.solve_bytes(n, nnz, 4, 14, False)["c_v"] == 11
+
+
+def test_short_kernel_names():
+    """rocprofv3's demangled names reduce to the keys of the counter record."""
+    f = bench.short_kernel_name
+    assert f("void fj::k_spmm_cg<fj::Unit, double, 64, 2, false, 64>(fj::Csr<fj::Unit>, int)") == \
+        "k_spmm_cg<Unit, double, 64, 2, false, 64>"
+    assert f("fj::k_fin_pair(int, int, double const*, fj::Ctrl*)") == "k_fin_pair"
+    assert f("void fj::k_ml_rows<fj::OpPre>(int, fj::OpPre, fj::Ctrl const*)") == "k_ml_rows<OpPre>"
+    assert f("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
+
+
+def test_profile_summary_from_synthetic_csvs(tmp_path, monkeypatch):
+    """--summarize-profiles: working-dispatch means (above 30 % of the largest),
+    the copy calibration scale, and the bytes per launch it records."""
+    import csv
+    import json
+
+    def counters(sub, name, rows):
+        d = tmp_path / sub
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+            for k, v in rows:
+                w.writerow([k, name, v])
+
+    copy = "__amd_rocclr_copyBuffer"
+    kern = "void fj::k_x<double>(int)"
+    counters("cfetch", "FETCH_SIZE", [(copy, 512 * 1024)])  # half of 1 GiB: scale 2
+    counters("cwrite", "WRITE_SIZE", [(copy, 1024 * 1024)])
+    counters("fetch", "FETCH_SIZE", [(kern, 100.0), (kern, 100.0), (kern, 1.0)])  # the 1.0 is an empty launch
+    counters("write", "WRITE_SIZE", [(kern, 50.0), (kern, 50.0), (kern, 50.0)])
+    (tmp_path / "stats").mkdir()
+    with open(tmp_path / "stats" / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writerow([kern, 0, 2000])
+        w.writerow([kern, 5000, 9000])
+    out = tmp_path / "counters.json"
+    monkeypatch.setattr(bench, "COUNTERS", str(out))
+    bench.summarize_profiles(str(tmp_path))
+    rec = json.loads(out.read_text())
+    k = rec["kernels"]["k_x<double>"]
+    assert k["working_dispatches"] == 2 and k["dispatches"] == 3 and k["fetch_kib"] == 100.0
+    assert k["bytes_per_launch"] == int(round(100.0 * 1024 * 2.0 + 50.0 * 1024 * 1.0))
+    assert rec["copy_calibration"]["fetch_scale"] == 2.0 and rec["source_sha256"] == bench.kernel_source_hash()
