@@ -107,7 +107,8 @@ typedef struct fj_csr {
 #define FJ_MULTILEVEL    512u  /* one opinion vector (k = 1), FJ_FP64: precondition CG with the aggregation
                                   V-cycle of opts->hierarchy (fj_hierarchy_create) instead of the 2x2 blocks or
                                   Jacobi; for graphs whose edge weights spread over many orders of magnitude.
-                                  Not with FJ_DIAG_PRECOND, FJ_BLOCK_CG, in the server or fj_indices_noalloc */
+                                  Not with FJ_DIAG_PRECOND, FJ_BLOCK_CG, FJ_TWO_SOLVE (a 2-column batched
+                                  solve), in the server or fj_indices_noalloc */
 
 typedef struct fj_hierarchy fj_hierarchy;
 

@@ -300,9 +300,10 @@ int check_opts(const fj_opts* o) {
         return FJ_ERR_INVALID_ARG;
     }
     if ((o->flags & FJ_MULTILEVEL) &&
-        (o->precision != FJ_FP64 || !o->hierarchy || (o->flags & (FJ_DIAG_PRECOND | FJ_BLOCK_CG)))) {
+        (o->precision != FJ_FP64 || !o->hierarchy || (o->flags & (FJ_DIAG_PRECOND | FJ_BLOCK_CG | FJ_TWO_SOLVE)))) {
         std::snprintf(g_last_error, sizeof g_last_error,
-                      "FJ_MULTILEVEL needs FJ_FP64, a hierarchy and neither FJ_DIAG_PRECOND nor FJ_BLOCK_CG");
+                      "FJ_MULTILEVEL needs FJ_FP64, a hierarchy and none of FJ_DIAG_PRECOND, FJ_BLOCK_CG, "
+                      "FJ_TWO_SOLVE");
         return FJ_ERR_INVALID_ARG;
     }
     if (!(o->eps > 0.0 && o->eps < 0.5)) return FJ_ERR_INVALID_ARG;

@@ -258,7 +258,8 @@ def test_multilevel_argument_errors(lib):
     fake = 4096  # never dereferenced: every case fails before the hierarchy is read
     for prec, flags, h, k in ((fj.FJ_FP64, fj.FJ_MULTILEVEL, None, 1), (fj.FJ_MIXED, fj.FJ_MULTILEVEL, fake, 1),
                               (fj.FJ_FP64, fj.FJ_MULTILEVEL | fj.FJ_DIAG_PRECOND, fake, 1),
-                              (fj.FJ_FP64, fj.FJ_MULTILEVEL | fj.FJ_BLOCK_CG, fake, 4)):
+                              (fj.FJ_FP64, fj.FJ_MULTILEVEL | fj.FJ_BLOCK_CG, fake, 4),
+                              (fj.FJ_FP64, fj.FJ_MULTILEVEL | fj.FJ_TWO_SOLVE, fake, 1)):
         o = fj.make_opts(precision=prec, flags=flags)
         o.hierarchy = h
         rc = lib.fj_indices(ctypes.byref(csr), ctypes.c_void_p(256), k, ctypes.c_void_p(256), k,

@@ -106,9 +106,10 @@ def test_indices_match_oracle(torch_fj, name, kind):
     H.close()
 
 
-def test_two_solve_warm_start_and_determinism(torch_fj):
-    """FJ_TWO_SOLVE and FJ_WARM_START run with the V-cycle too, and two solves
-    give the same z bit for bit."""
+def test_warm_start_and_determinism(torch_fj):
+    """FJ_WARM_START runs with the V-cycle, two solves give the same z bit for
+    bit, and FJ_TWO_SOLVE (a 2-column batched solve, which has no V-cycle) is
+    refused."""
     torch, fj = torch_fj
     g = skewed(W.chung_lu(20_000, 2.5, 10.0, 5), 1e6, 9)
     G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
@@ -117,9 +118,11 @@ def test_two_solve_warm_start_and_determinism(torch_fj):
     sd = torch.from_numpy(s).to("cuda:0")
     ref, _, _ = O.indices(g, s)
     zref, _ = O.solve(g, s, rtol=1e-14)
-    vals, infos, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, flags=fj.FJ_TWO_SOLVE, hierarchy=H))
+    _, _, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, flags=fj.FJ_TWO_SOLVE, hierarchy=H), check=False)
+    assert rc == fj.FJ_ERR_INVALID_ARG
+    vals, infos, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, hierarchy=H))
     assert rc == fj.FJ_OK
-    check_indices(vals, infos, ref, "two_solve")
+    check_indices(vals, infos, ref, "multilevel")
     z1, _, rc1 = fj.fj_solve(G, sd, fj.make_opts(rtol=1e-10, hierarchy=H))
     z2, _, rc2 = fj.fj_solve(G, sd, fj.make_opts(rtol=1e-10, hierarchy=H))
     assert rc1 == rc2 == fj.FJ_OK
