@@ -390,7 +390,9 @@ typedef struct fj_server_opts {
                                    behind a large graph's replay */
     int32_t large_iters_per_replay;  /* CG iterations per replay for large graphs (shorter replays let requests
                                         join sooner); 0 = max(1, iters_per_replay / 4) */
-    int32_t reserved;                /* must be 0 */
+    int32_t large_blocks;            /* blocks per large graph, 1..4; 0 = 1. With more than one, a request goes
+                                        whole to the block of that graph with the fewest columns waiting or
+                                        running, and the blocks replay on different large lanes */
     int64_t large_entries;      /* a graph with n + nnz >= this is large; 0 = 2^22 */
 } fj_server_opts;
 

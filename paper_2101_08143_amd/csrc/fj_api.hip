@@ -2663,9 +2663,10 @@ int fj_server_create(const fj_server_opts* opts, fj_server** out) {
         if (!opts->arena || !aligned(opts->arena) || opts->arena_bytes == 0) return FJ_ERR_WORKSPACE;
         if (opts->large_lanes < 0 || opts->large_lanes > 8 || opts->large_entries < 0) return FJ_ERR_INVALID_ARG;
         if (opts->large_iters_per_replay < 0 || opts->large_iters_per_replay > 256) return FJ_ERR_INVALID_ARG;
-        if (opts->reserved != 0) return FJ_ERR_INVALID_ARG;
+        if (opts->large_blocks < 0 || opts->large_blocks > 4) return FJ_ERR_INVALID_ARG;
         Server* s = new Server();
         s->o = *opts;
+        if (s->o.large_blocks == 0) s->o.large_blocks = 1;
         if (s->o.large_lanes == 0) s->o.large_lanes = 2;
         if (s->o.large_entries == 0) s->o.large_entries = int64_t(1) << 22;
         if (s->o.large_iters_per_replay == 0) s->o.large_iters_per_replay = std::max(1, s->o.iters_per_replay / 4);
@@ -2723,26 +2724,45 @@ int fj_server_add_graph(fj_server* srv, const fj_csr* g, const void* plan, int32
         if (g->n < 1) return FJ_ERR_INVALID_ARG;
         if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
         Server* s = reinterpret_cast<Server*>(srv);
-        s->graphs.reserve(s->graphs.size() + 1);  // may throw: nothing created yet
-        ServerGraph G;
-        G.g = *g;
-        G.plan = plan;
-        G.pl = plan_layout(g);
-        // a large graph shares one of the large lanes (in turn), any other the last lane
+        const bool large = static_cast<int64_t>(g->n) + g->nnz >= s->o.large_entries;
+        const int nb = large ? s->o.large_blocks : 1;
+        // may throw: nothing created yet
+        s->graphs.reserve(s->graphs.size() + nb);
+        s->entries.reserve(s->entries.size() + 1);
+        std::vector<int> mine;
+        mine.reserve(nb);
+        std::vector<ServerGraph> made;
+        made.reserve(nb);
         const int nl = s->o.large_lanes;
-        G.large = static_cast<int64_t>(g->n) + g->nnz >= s->o.large_entries;
-        G.st = G.large ? s->lanes[(s->n_large++) % nl] : s->lanes[nl];
-        hipError_t e = hipEventCreateWithFlags(&G.dep, hipEventDisableTiming);
-        // the graph's work waits for the caller's work so far (fj_prepare of this plan)
-        if (e == hipSuccess) e = hipEventRecord(G.dep, static_cast<hipStream_t>(stream));
-        if (e == hipSuccess) e = hipStreamWaitEvent(G.st, G.dep, 0);
-        if (e != hipSuccess) {
-            set_error("fj_server_add_graph: event", e);
-            if (G.dep) (void)hipEventDestroy(G.dep);
-            return FJ_ERR_HIP;
+        for (int b = 0; b < nb; ++b) {
+            ServerGraph G;
+            G.g = *g;
+            G.plan = plan;
+            G.pl = plan_layout(g);
+            // a large graph's blocks take the large lanes in turn, any other graph the last lane
+            G.large = large;
+            G.st = large ? s->lanes[(s->n_large + b) % nl] : s->lanes[nl];
+            hipError_t e = hipEventCreateWithFlags(&G.dep, hipEventDisableTiming);
+            // the block's work waits for the caller's work so far (fj_prepare of this plan)
+            if (e == hipSuccess) e = hipEventRecord(G.dep, static_cast<hipStream_t>(stream));
+            if (e == hipSuccess) e = hipStreamWaitEvent(G.st, G.dep, 0);
+            if (e != hipSuccess) {
+                set_error("fj_server_add_graph: event", e);
+                if (G.dep) (void)hipEventDestroy(G.dep);
+                for (ServerGraph& M : made) (void)hipEventDestroy(M.dep);
+                return FJ_ERR_HIP;
+            }
+            made.push_back(std::move(G));  // capacity reserved: does not throw
         }
-        s->graphs.push_back(std::move(G));  // capacity reserved: does not throw
-        *graph_id = static_cast<int32_t>(s->graphs.size() - 1);
+        if (large) s->n_large += nb;
+        // capacities are reserved; moving a ServerGraph may still allocate (its deque), and a
+        // failure here leaves unused entries behind but returns no graph id
+        for (ServerGraph& G : made) {
+            mine.push_back(static_cast<int>(s->graphs.size()));
+            s->graphs.push_back(std::move(G));
+        }
+        s->entries.push_back(std::move(mine));
+        *graph_id = static_cast<int32_t>(s->entries.size() - 1);
         return FJ_OK;
     });
 }
@@ -2752,14 +2772,32 @@ int fj_server_submit(fj_server* srv, int32_t graph_id, int32_t k, const double* 
     return guarded([&]() -> int {
         if (!srv || !S || !out || !request_id) return FJ_ERR_INVALID_ARG;
         Server* s = reinterpret_cast<Server*>(srv);
-        if (graph_id < 0 || graph_id >= static_cast<int32_t>(s->graphs.size())) return FJ_ERR_INVALID_ARG;
+        if (graph_id < 0 || graph_id >= static_cast<int32_t>(s->entries.size())) return FJ_ERR_INVALID_ARG;
         if (k < 1 || k > s->o.block_columns || lds < k) return FJ_ERR_INVALID_ARG;
-        ServerGraph& G = s->graphs[graph_id];
+        // the graph's block with the fewest columns waiting or running (the first on ties)
+        int pick = -1;
+        int64_t best = 0;
+        for (int e : s->entries[graph_id]) {
+            const ServerGraph& H = s->graphs[e];
+            int64_t load = 0;
+            for (uint64_t q : H.queue) {
+                const auto it = s->requests.find(q);
+                if (it != s->requests.end()) load += it->second.k - it->second.admitted;
+            }
+            if (H.blk)
+                for (int c = 0; c < s->o.block_columns; ++c) load += H.blk->slot_req[c] >= 0;
+            if (pick < 0 || load < best) {
+                pick = e;
+                best = load;
+            }
+        }
+        ServerGraph& G = s->graphs[pick];
         if (block_bytes(G.g.n, s->o.block_columns, s->o.precision == FJ_MIXED) > s->o.arena_bytes)
             return FJ_ERR_WORKSPACE;  // could never run
         ServerRequest r;
         r.id = s->next_id;
-        r.gid = graph_id;
+        r.gid = pick;
+        r.user_gid = graph_id;
         r.k = k;
         r.S = S;
         r.lds = lds;
@@ -2807,7 +2845,7 @@ int fj_server_poll(fj_server* srv, fj_server_done* done, int32_t max, int32_t* c
             if (it == s->requests.end()) continue;
             const ServerRequest& r = it->second;
             done[n].request_id = rid;
-            done[n].graph_id = r.gid;
+            done[n].graph_id = r.user_gid;
             done[n].status = r.status;
             done[n].latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
             s->requests.erase(it);

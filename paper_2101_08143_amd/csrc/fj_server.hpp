@@ -18,7 +18,9 @@
 // large graph's long one sharing its queue; the lanes keep short and long
 // work on different queues, and blocks on different lanes overlap. Large
 // graphs also replay fewer iterations at a time (large_iters_per_replay), so
-// that requests join their blocks sooner. After each replay the host reads the control
+// that requests join their blocks sooner, and may hold several blocks
+// (large_blocks, each an entry of its own in `graphs`; a request goes whole
+// to the block with the least work). After each replay the host reads the control
 // blocks; columns whose CG stopped are finished by the batched epilogue
 // (after the FP64 correction z += ||r|| d for FJ_MIXED), then retired
 // (certified, or final) or restarted from their true residual with a
@@ -31,7 +33,8 @@
 
 struct ServerRequest {
     uint64_t id = 0;
-    int gid = 0;
+    int gid = 0;        // the internal graph entry (block) serving it
+    int user_gid = 0;   // the caller's graph id
     int k = 0;
     const double* S = nullptr;
     int64_t lds = 0;
@@ -85,7 +88,8 @@ struct Server {
     fj_server_opts o{};
     char* arena = nullptr;
     std::map<size_t, size_t> free_list;  // offset -> bytes
-    std::vector<ServerGraph> graphs;
+    std::vector<ServerGraph> graphs;           // one entry per block: a large graph may have several
+    std::vector<std::vector<int>> entries;     // caller's graph id -> its entries in graphs
     std::unordered_map<uint64_t, ServerRequest> requests;
     std::deque<uint64_t> completed;
     std::vector<hipStream_t> lanes;  // large_lanes streams for large graphs, then one for the others

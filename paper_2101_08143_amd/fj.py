@@ -82,7 +82,7 @@ class fj_server_opts(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("block_columns", ctypes.c_int32),
                 ("iters_per_replay", ctypes.c_int32), ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("large_lanes", ctypes.c_int32),
-                ("large_iters_per_replay", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("large_iters_per_replay", ctypes.c_int32), ("large_blocks", ctypes.c_int32),
                 ("large_entries", ctypes.c_int64)]
 
 
@@ -450,13 +450,14 @@ class Server:
     until they complete."""
 
     def __init__(self, arena_bytes, block_columns=16, iters_per_replay=8, eps=1e-6, max_iter=0, device="cuda",
-                 precision=FJ_FP64, large_lanes=0, large_entries=0, large_iters_per_replay=0):
+                 precision=FJ_FP64, large_lanes=0, large_entries=0, large_iters_per_replay=0, large_blocks=0):
         import torch
         self.arena = _aligned_empty(torch, arena_bytes, device)
         self.opts = fj_server_opts(arena=self.arena.data_ptr(), arena_bytes=int(arena_bytes),
                                    block_columns=block_columns, iters_per_replay=iters_per_replay, eps=eps,
                                    max_iter=max_iter, precision=precision, large_lanes=large_lanes,
-                                   large_iters_per_replay=large_iters_per_replay, large_entries=large_entries)
+                                   large_iters_per_replay=large_iters_per_replay, large_entries=large_entries,
+                                   large_blocks=large_blocks)
         self.handle = ctypes.c_void_p()
         rc = lib().fj_server_create(ctypes.byref(self.opts), ctypes.byref(self.handle))
         if rc != FJ_OK:

@@ -275,3 +275,14 @@ def test_multilevel_argument_errors(lib):
     assert lib.fj_hierarchy_destroy(None) == fj.FJ_OK
     lv = ctypes.c_int32(0)
     assert lib.fj_hierarchy_shape(None, ctypes.byref(lv), None, None, None) == fj.FJ_ERR_INVALID_ARG
+
+
+def test_server_option_errors(lib):
+    """fj_server_create checks its options before any device work."""
+    base = dict(arena=4096, arena_bytes=1 << 20, block_columns=16, iters_per_replay=8, eps=1e-6, max_iter=0,
+                precision=fj.FJ_FP64, large_lanes=0, large_iters_per_replay=0, large_blocks=0, large_entries=0)
+    h = ctypes.c_void_p()
+    for field, bad in (("large_blocks", 5), ("large_blocks", -1), ("large_lanes", 9), ("block_columns", 32),
+                       ("iters_per_replay", 0), ("large_entries", -1)):
+        o = fj.fj_server_opts(**{**base, field: bad})
+        assert lib.fj_server_create(ctypes.byref(o), ctypes.byref(h)) == fj.FJ_ERR_INVALID_ARG, field

@@ -46,8 +46,9 @@ def _prec(fj, precision):
     return fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
 
 
-def _run(fj, torch, G, reqs, arena_bytes, block_columns=16, precision="fp64"):
-    srv = fj.Server(arena_bytes, block_columns=block_columns, iters_per_replay=6, precision=_prec(fj, precision))
+def _run(fj, torch, G, reqs, arena_bytes, block_columns=16, precision="fp64", **server_kw):
+    srv = fj.Server(arena_bytes, block_columns=block_columns, iters_per_replay=6, precision=_prec(fj, precision),
+                    **server_kw)
     gids = [srv.add_graph(g) for g in G]
     ids = [srv.submit(gids[gi], torch.from_numpy(S).to("cuda:0")) for gi, S in reqs]
     res = {r["id"]: r for r in srv.drain(timeout_s=240)}
@@ -83,6 +84,21 @@ def test_server_result_same_alone_and_in_mix(env, precision):
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
+def test_server_several_blocks_per_large_graph(env, precision):
+    """Every graph large (large_entries = 1) with 3 blocks each: requests spread
+    over a graph's blocks, report the caller's graph id, and give bitwise the
+    results of the one-block server (a column's arithmetic never depends on
+    its block)."""
+    torch, fj, graphs, G, reqs = env
+    say(f"three blocks per graph {precision}")
+    ref = env_cache.get(precision) or _run(fj, torch, G, reqs, 1 << 30, precision=precision)
+    res = _run(fj, torch, G, reqs, 4 << 30, precision=precision, large_entries=1, large_blocks=3)
+    for (gi, _), a, b in zip(reqs, res, ref):
+        assert a["status"] == fj.FJ_OK and a["graph"] == gi
+        assert a["values"] == b["values"]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
 def test_server_admission_by_footprint(env, precision):
     """An arena that holds only one block at a time: requests on other graphs
     wait until an idle block can be released, and all still complete certified."""
@@ -112,6 +128,9 @@ def test_server_errors(env):
     srv.close()
     with pytest.raises(fj.FJError) as e:
         fj.Server(1 << 20, block_columns=16, precision=7)
+    assert e.value.status == fj.FJ_ERR_INVALID_ARG
+    with pytest.raises(fj.FJError) as e:
+        fj.Server(1 << 20, block_columns=16, large_blocks=5)
     assert e.value.status == fj.FJ_ERR_INVALID_ARG
     assert fj.Server.block_bytes(1000, 16, 7) == 0
 
