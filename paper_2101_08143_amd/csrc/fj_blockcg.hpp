@@ -44,7 +44,8 @@ __device__ __forceinline__ dv4 mfma16(double a, double b, dv4 c) {
 // GCH nodes: the chunk's rows are staged in LDS with coalesced loads, then
 // wave w multiplies the 16 x 16 tiles t with t % NWAVE == w from LDS.
 // Workgroup b writes its NG partials to part[(b * NG + g) * KB * KB ...]
-// (row-major).
+// (row-major). The next chunk's loads are issued before the current chunk's
+// products.
 constexpr int GCH = 16;
 template <int KB, int NG>
 __global__ void __launch_bounds__(WG) k_gram(int n, const double* __restrict__ A, const double* __restrict__ B0,
@@ -68,16 +69,20 @@ __global__ void __launch_bounds__(WG) k_gram(int n, const double* __restrict__ A
     for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int p = 0; p < PER; ++p) acc[g][p] = dv4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t c0 = i_begin; c0 < i_end; c0 += GCH) {
-        double va[PT], vb[NG][PT];
+    double va[PT], vb[NG][PT];
+    // the chunk at c0 into registers (element e of a chunk: node e / KB, column e % KB)
+    auto fetch = [&](int64_t c0) {
 #pragma unroll
         for (int u = 0; u < PT; ++u) {
-            const int e = threadIdx.x + u * WG;  // element e of the chunk: node e / KB, column e % KB
+            const int e = threadIdx.x + u * WG;
             const bool ok = c0 + e / KB < i_end;
             va[u] = ok ? A[c0 * KB + e] : 0.0;
 #pragma unroll
             for (int g = 0; g < NG; ++g) vb[g][u] = ok ? Bp[g][c0 * KB + e] : 0.0;
         }
+    };
+    if (i_begin < i_end) fetch(i_begin);
+    for (int64_t c0 = i_begin; c0 < i_end; c0 += GCH) {
 #pragma unroll
         for (int u = 0; u < PT; ++u) {
             const int e = threadIdx.x + u * WG;
@@ -86,6 +91,7 @@ __global__ void __launch_bounds__(WG) k_gram(int n, const double* __restrict__ A
             for (int g = 0; g < NG; ++g) Bs[g][(e / KB) * LD + e % KB] = vb[g][u];
         }
         __syncthreads();
+        if (c0 + GCH < i_end) fetch(c0 + GCH);  // the next chunk's loads fly during these products
 #pragma unroll
         for (int s = 0; s < GCH / 4; ++s) {
 #pragma unroll
@@ -282,10 +288,13 @@ __global__ void __launch_bounds__(WG) k_block_mul(int n, const double* IN, const
         if (IN != nullptr) {
             const int64_t ia = i0 + sub;  // A operand: node i0 + sub, inner column k0 + kk
             const bool oka = ia < n;
-            for (int k0 = 0; k0 < KB; k0 += 4) {
-                const double a = oka ? IN[ia * KB + k0 + kk] : 0.0;
+            double a[KB / 4];  // the band's whole row block in flight before the first product
 #pragma unroll
-                for (int t = 0; t < TT; ++t) acc[t] = mfma16(a, C[(k0 + kk) * KB + 16 * t + sub], acc[t]);
+            for (int q = 0; q < KB / 4; ++q) a[q] = oka ? IN[ia * KB + 4 * q + kk] : 0.0;
+#pragma unroll
+            for (int q = 0; q < KB / 4; ++q) {
+#pragma unroll
+                for (int t = 0; t < TT; ++t) acc[t] = mfma16(a[q], C[(4 * q + kk) * KB + 16 * t + sub], acc[t]);
             }
         }
 #pragma unroll
