@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # scheduler and the header's declarations do not change what a dispatch reads).
 KERNEL_SOURCES = ["paper_2101_08143_amd/csrc/fj_kernels.hpp", "paper_2101_08143_amd/csrc/fj_batched.hpp",
                   "paper_2101_08143_amd/csrc/fj_blockcg.hpp", "paper_2101_08143_amd/csrc/fj_multilevel.hpp",
-                  "paper_2101_08143_amd/csrc/fj_api.hip"]
+                  "paper_2101_08143_amd/csrc/fj_aids.hpp", "paper_2101_08143_amd/csrc/fj_api.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_cl4m.json")
 
 

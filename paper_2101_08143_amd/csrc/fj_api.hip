@@ -1971,513 +1971,9 @@ int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t c
     });
 }
 
-int fj_gather_bound(const fj_csr* g, const double* x, double* y, void* stream) {
-    return guarded([&]() -> int {
-        if (int rc = check_graph_args(g)) return rc;
-        if (g->nnz == 0) return FJ_OK;
-        if (!x || !y) return FJ_ERR_INVALID_ARG;
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        return with_graph(g, [&](auto G) -> int {
-            using Vc = typename decltype(G)::value_type;
-            int grid = 1;
-            if (int rc = grid_for(k_gather_bound<Vc>, (g->nnz / 8 + WG) / WG, &grid)) return rc;
-            k_gather_bound<Vc><<<grid, WG, 0, st>>>(G, x, y);
-            HIPCHK(hipGetLastError());
-            return FJ_OK;
-        });
-    });
-}
+#include "fj_aids.hpp"
 
-namespace {
-// The regrouped entry streams of fj_gather_bound_sliced, for the last graph
-// it was called on (rebuilt when the graph, stream count or hub width changes).
-struct SliceKey {
-    int dev = -1, vt = 0, n = 0, slices = 0, hub = 0;
-    int64_t nnz = 0;
-    const void *rp = nullptr, *col = nullptr, *val = nullptr;
-    bool operator==(const SliceKey& o) const {
-        return dev == o.dev && vt == o.vt && n == o.n && slices == o.slices && hub == o.hub && nnz == o.nnz &&
-               rp == o.rp && col == o.col && val == o.val;
-    }
-};
-struct SlicedStreams {
-    SliceKey key;
-    void* mem = nullptr;  // col | val | off | cnt
-    int* col = nullptr;
-    void* val = nullptr;
-    int64_t* off = nullptr;
-    int64_t* cnt = nullptr;
-    int64_t bounds[9] = {};
-};
-std::mutex g_slice_mu;
-SlicedStreams g_slice;
-
-// Stream s of S = 8: the tail columns [hub, n) are cut into eight ranges of
-// about equal entry count, range s read by stream s only; the entries of the
-// hub columns [0, hub) are dealt to the streams in CSR order in eight equal
-// runs. Every stream keeps CSR order. S = 1: all entries in CSR order.
-int build_slices(const fj_csr* g, const SliceKey& key, hipStream_t st, SlicedStreams* out) {
-    const int n = g->n;
-    const int64_t nnz = g->nnz;
-    const int S = key.slices, H = key.hub;
-    const size_t vb = g->val_type == FJ_VAL_F64 ? 8 : g->val_type == FJ_VAL_F32 ? 4 : 0;
-    std::vector<int> rp(static_cast<size_t>(n) + 1), col(static_cast<size_t>(nnz));
-    std::vector<unsigned char> val(static_cast<size_t>(nnz) * vb);
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipMemcpy(rp.data(), g->row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(col.data(), g->col_idx, col.size() * sizeof(int), hipMemcpyDeviceToHost));
-    if (vb) HIPCHK(hipMemcpy(val.data(), g->val, val.size(), hipMemcpyDeviceToHost));
-    std::vector<int64_t> bounds(9, n);
-    bounds[0] = std::min(H, n);
-    std::vector<int> sid(static_cast<size_t>(nnz), 0);
-    if (S == 8) {
-        std::vector<int64_t> per_col(static_cast<size_t>(n) + 1, 0);
-        int64_t tail = 0, hub_total = 0;
-        for (int64_t e = 0; e < nnz; ++e) {
-            if (col[e] >= H) { ++per_col[col[e]]; ++tail; }
-            else ++hub_total;
-        }
-        int64_t cum = 0;
-        int next = 1;
-        for (int c = bounds[0]; c < n && next < 8; ++c) {
-            cum += per_col[c];
-            while (next < 8 && cum * 8 >= tail * next) bounds[next++] = c + 1;
-        }
-        int64_t hub_seen = 0;
-        for (int64_t e = 0; e < nnz; ++e) {
-            const int c = col[e];
-            if (c < H) {
-                sid[e] = static_cast<int>(hub_seen * 8 / std::max<int64_t>(hub_total, 1));
-                ++hub_seen;
-            } else {
-                sid[e] = static_cast<int>(std::upper_bound(bounds.begin() + 1, bounds.begin() + 8, c) -
-                                          (bounds.begin() + 1));
-            }
-        }
-    }
-    int64_t cnt[8] = {}, off[9] = {};
-    for (int64_t e = 0; e < nnz; ++e) ++cnt[sid[e]];
-    for (int s = 0; s < S; ++s) off[s + 1] = off[s] + (cnt[s] + 7) / 8 * 8;
-    const int64_t total = off[S];
-    std::vector<int> hcol(static_cast<size_t>(total), 0);
-    std::vector<unsigned char> hval(static_cast<size_t>(total) * vb, 0);
-    int64_t at[8];
-    std::copy(off, off + 8, at);
-    for (int64_t e = 0; e < nnz; ++e) {
-        const int64_t d = at[sid[e]]++;
-        hcol[d] = col[e];
-        if (vb) std::memcpy(&hval[d * vb], &val[e * vb], vb);
-    }
-    const size_t col_b = align_up(static_cast<size_t>(total) * 4), val_b = align_up(static_cast<size_t>(total) * vb);
-    void* mem = nullptr;
-    HIPCHK(hipMalloc(&mem, col_b + val_b + 2 * 256));
-    unsigned char* base = static_cast<unsigned char*>(mem);
-    out->mem = mem;
-    out->col = reinterpret_cast<int*>(base);
-    out->val = vb ? base + col_b : nullptr;
-    out->off = reinterpret_cast<int64_t*>(base + col_b + val_b);
-    out->cnt = reinterpret_cast<int64_t*>(base + col_b + val_b + 256);
-    HIPCHK(hipMemcpy(out->col, hcol.data(), hcol.size() * 4, hipMemcpyHostToDevice));
-    if (vb) HIPCHK(hipMemcpy(out->val, hval.data(), hval.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(out->off, off, sizeof(off), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(out->cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice));
-    std::copy(bounds.begin(), bounds.end(), out->bounds);
-    out->key = key;
-    return FJ_OK;
-}
-}  // namespace
-
-int fj_gather_bound_sliced(const fj_csr* g, const void* x, int32_t x_bytes, double* y, int32_t slices,
-                           int32_t hub_cols, int32_t* check, int64_t* bounds, void* stream) {
-    return guarded([&]() -> int {
-        if (int rc = check_graph_args(g)) return rc;
-        if ((slices != 1 && slices != 8) || (x_bytes != 4 && x_bytes != 8) || hub_cols < 0)
-            return FJ_ERR_INVALID_ARG;
-        if (g->nnz == 0) return FJ_OK;
-        if (!x || !y) return FJ_ERR_INVALID_ARG;
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        int dev = 0;
-        if (int rc = current_device(&dev)) return rc;
-        const SliceKey key{dev, g->val_type, g->n, slices, slices == 8 ? hub_cols : 0, g->nnz,
-                           g->row_ptr, g->col_idx, g->val};
-        std::lock_guard<std::mutex> lock(g_slice_mu);
-        if (!(g_slice.key == key)) {
-            if (g_slice.mem) {
-                HIPCHK(hipDeviceSynchronize());
-                HIPCHK(hipFree(g_slice.mem));
-            }
-            g_slice = SlicedStreams{};
-            if (int rc = build_slices(g, key, st, &g_slice)) {
-                if (g_slice.mem) (void)hipFree(g_slice.mem);
-                g_slice = SlicedStreams{};
-                return rc;
-            }
-        }
-        if (bounds) std::copy(g_slice.bounds, g_slice.bounds + 9, bounds);
-        return with_graph(g, [&](auto G) -> int {
-            using Vc = typename decltype(G)::value_type;
-            const Vc* val = static_cast<const Vc*>(g_slice.val);
-            int grid = 1;
-            auto launch = [&](auto kern, auto xp) -> int {
-                if (int rc = grid_for(kern, (g->nnz / 8 + WG) / WG + slices, &grid)) return rc;
-                grid = std::max(slices, grid / slices * slices);
-                kern<<<grid, WG, 0, st>>>(g_slice.col, val, xp, y, g_slice.off, g_slice.cnt, check);
-                HIPCHK(hipGetLastError());
-                return FJ_OK;
-            };
-            const double* x8 = static_cast<const double*>(x);
-            const float* x4 = static_cast<const float*>(x);
-            if (slices == 8)
-                return x_bytes == 8 ? launch(k_gather_sliced<Vc, double, 8>, x8) : launch(k_gather_sliced<Vc, float, 8>, x4);
-            return x_bytes == 8 ? launch(k_gather_sliced<Vc, double, 1>, x8) : launch(k_gather_sliced<Vc, float, 1>, x4);
-        });
-    });
-}
-
-namespace {
-// One level of the hierarchy on the host: W (CSR, no diagonal) and the
-// identity part mass (1 on level 0, the aggregate sizes further down).
-struct HostLevel {
-    int n = 0;
-    std::vector<int> rp, col;
-    std::vector<double> w, mass;
-};
-
-// Tie-break key of the edge {i, j} (SplitMix64 of the ordered pair): among
-// equally heavy edges a node takes the one with the larger key, so that
-// uniform weights do not chain a whole path or cycle into one aggregate.
-uint64_t edge_key(int i, int j) {
-    uint64_t x = (static_cast<uint64_t>(std::min(i, j)) << 32) | static_cast<uint32_t>(std::max(i, j));
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    return x ^ (x >> 31);
-}
-
-// Heaviest-neighbour forest: node i, in index order, is joined to its
-// heaviest neighbour (ties by edge_key) unless the merged group would exceed
-// ML_LONG nodes; the groups are the aggregates, labelled in the order of their
-// smallest node. The cap keeps a hub from gathering most of a power-law graph
-// into one aggregate (one member list, and one coarse row, as long as the
-// graph). Returns the number of aggregates.
-int forest_aggregates(const HostLevel& L, std::vector<int>& agg) {
-    std::vector<int> parent(static_cast<size_t>(L.n)), size(static_cast<size_t>(L.n), 1);
-    for (int i = 0; i < L.n; ++i) parent[i] = i;
-    auto find = [&](int x) {
-        while (parent[x] != x) {
-            parent[x] = parent[parent[x]];
-            x = parent[x];
-        }
-        return x;
-    };
-    for (int i = 0; i < L.n; ++i) {
-        int best = -1;
-        double bw = -INFINITY;
-        uint64_t bk = 0;
-        for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
-            const uint64_t k = edge_key(i, L.col[e]);
-            if (L.w[e] > bw || (L.w[e] == bw && k > bk)) {
-                bw = L.w[e];
-                bk = k;
-                best = L.col[e];
-            }
-        }
-        if (best >= 0) {
-            const int a = find(i), b = find(best);
-            if (a != b && size[a] + size[b] <= ML_LONG) {
-                parent[std::max(a, b)] = std::min(a, b);
-                size[std::min(a, b)] += size[std::max(a, b)];
-            }
-        }
-    }
-    agg.assign(static_cast<size_t>(L.n), -1);
-    std::vector<int> label(static_cast<size_t>(L.n), -1);
-    int nc = 0;
-    for (int i = 0; i < L.n; ++i) {
-        const int r = find(i);
-        if (label[r] < 0) label[r] = nc++;
-        agg[i] = label[r];
-    }
-    return nc;
-}
-
-// Members of each aggregate (CSR, ascending node order) and the next level:
-// W' sums the weights between aggregates in member and entry order, columns
-// ascending per row; mass' sums the members' mass.
-void galerkin(const HostLevel& L, const std::vector<int>& agg, int nc, std::vector<int>& mrp,
-              std::vector<int>& mem, HostLevel& C) {
-    mrp.assign(static_cast<size_t>(nc) + 1, 0);
-    for (int i = 0; i < L.n; ++i) ++mrp[agg[i] + 1];
-    for (int a = 0; a < nc; ++a) mrp[a + 1] += mrp[a];
-    mem.assign(static_cast<size_t>(L.n), 0);
-    std::vector<int> at(mrp.begin(), mrp.end() - 1);
-    for (int i = 0; i < L.n; ++i) mem[at[agg[i]]++] = i;
-    C.n = nc;
-    C.rp.assign(static_cast<size_t>(nc) + 1, 0);
-    C.col.clear();
-    C.w.clear();
-    C.mass.assign(static_cast<size_t>(nc), 0.0);
-    std::vector<int> slot(static_cast<size_t>(nc), -1);
-    std::vector<std::pair<int, double>> row;
-    for (int a = 0; a < nc; ++a) {
-        row.clear();
-        for (int k = mrp[a]; k < mrp[a + 1]; ++k) {
-            const int i = mem[k];
-            C.mass[a] += L.mass[i];
-            for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) {
-                const int b = agg[L.col[e]];
-                if (b == a) continue;
-                if (slot[b] < 0) {
-                    slot[b] = static_cast<int>(row.size());
-                    row.emplace_back(b, L.w[e]);
-                } else {
-                    row[slot[b]].second += L.w[e];
-                }
-            }
-        }
-        for (const auto& pr : row) slot[pr.first] = -1;
-        std::sort(row.begin(), row.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-        for (const auto& pr : row) {
-            C.col.push_back(pr.first);
-            C.w.push_back(pr.second);
-        }
-        C.rp[a + 1] = static_cast<int>(C.col.size());
-    }
-}
-
-// Dense inverse of the SPD matrix diag(a) - W (Cholesky, then L^-T L^-1).
-void dense_inverse(const HostLevel& L, const std::vector<double>& a, std::vector<double>& inv) {
-    const size_t n = static_cast<size_t>(L.n);
-    std::vector<double> A(n * n, 0.0);
-    for (size_t i = 0; i < n; ++i) {
-        A[i * n + i] = a[i];
-        for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) A[i * n + L.col[e]] -= L.w[e];
-    }
-    for (size_t j = 0; j < n; ++j) {  // lower Cholesky factor in place
-        double d = A[j * n + j];
-        for (size_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
-        d = std::sqrt(d);
-        A[j * n + j] = d;
-        for (size_t i = j + 1; i < n; ++i) {
-            double v = A[i * n + j];
-            for (size_t k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
-            A[i * n + j] = v / d;
-        }
-    }
-    std::vector<double> Li(n * n, 0.0);  // L^-1, lower
-    for (size_t j = 0; j < n; ++j) {
-        Li[j * n + j] = 1.0 / A[j * n + j];
-        for (size_t i = j + 1; i < n; ++i) {
-            double v = 0.0;
-            for (size_t k = j; k < i; ++k) v -= A[i * n + k] * Li[k * n + j];
-            Li[i * n + j] = v / A[i * n + i];
-        }
-    }
-    inv.assign(n * n, 0.0);
-    for (size_t i = 0; i < n; ++i)
-        for (size_t j = 0; j <= i; ++j) {
-            double v = 0.0;
-            for (size_t k = i; k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
-            inv[i * n + j] = v;
-            inv[j * n + i] = v;
-        }
-}
-
-constexpr int ML_DENSE_MAX = 2048;
-
-int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarchy* h) {
-    const int n = g->n;
-    const int64_t nnz = g->nnz;
-    std::vector<HostLevel> lv(1);
-    HostLevel& L0 = lv[0];
-    L0.n = n;
-    L0.rp.resize(static_cast<size_t>(n) + 1, 0);
-    L0.col.resize(static_cast<size_t>(nnz));
-    L0.w.assign(static_cast<size_t>(nnz), 1.0);
-    L0.mass.assign(static_cast<size_t>(n), 1.0);
-    HIPCHK(hipStreamSynchronize(st));
-    if (n > 0) HIPCHK(hipMemcpy(L0.rp.data(), g->row_ptr, L0.rp.size() * sizeof(int), hipMemcpyDeviceToHost));
-    if (nnz > 0) {
-        HIPCHK(hipMemcpy(L0.col.data(), g->col_idx, L0.col.size() * sizeof(int), hipMemcpyDeviceToHost));
-        if (g->val_type == FJ_VAL_F64) {
-            HIPCHK(hipMemcpy(L0.w.data(), g->val, L0.w.size() * sizeof(double), hipMemcpyDeviceToHost));
-        } else if (g->val_type == FJ_VAL_F32) {
-            std::vector<float> wf(static_cast<size_t>(nnz));
-            HIPCHK(hipMemcpy(wf.data(), g->val, wf.size() * sizeof(float), hipMemcpyDeviceToHost));
-            for (size_t e = 0; e < wf.size(); ++e) L0.w[e] = wf[e];
-        }
-    }
-    // coarsen
-    std::vector<std::vector<int>> aggs, mrps, mems;
-    while (static_cast<int>(lv.size()) < ML_MAXL && lv.back().n > coarse_max) {
-        std::vector<int> agg, mrp, mem;
-        const int nc = forest_aggregates(lv.back(), agg);
-        if (static_cast<int64_t>(nc) * 10 > static_cast<int64_t>(lv.back().n) * 9) break;  // < 10 % smaller
-        HostLevel C;
-        galerkin(lv.back(), agg, nc, mrp, mem, C);
-        aggs.push_back(std::move(agg));
-        mrps.push_back(std::move(mrp));
-        mems.push_back(std::move(mem));
-        lv.push_back(std::move(C));
-    }
-    const int levels = static_cast<int>(lv.size());
-    std::vector<std::vector<double>> a(levels);
-    std::vector<std::vector<int>> longs(levels), clongs(levels);
-    for (int l = 0; l < levels; ++l) {
-        const HostLevel& L = lv[l];
-        a[l].resize(static_cast<size_t>(L.n));
-        for (int i = 0; i < L.n; ++i) {
-            double d = L.mass[i];
-            for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) d += L.w[e];
-            a[l][i] = d;
-            if (L.rp[i + 1] - L.rp[i] > ML_LONG) longs[l].push_back(i);
-        }
-        if (l + 1 < levels)
-            for (int c = 0; c + 1 < static_cast<int>(mrps[l].size()); ++c)
-                if (mrps[l][c + 1] - mrps[l][c] > ML_LONG) clongs[l].push_back(c);
-    }
-    const HostLevel& last = lv.back();
-    std::vector<double> inv;
-    if (last.n > 0 && last.n <= ML_DENSE_MAX) dense_inverse(last, a.back(), inv);
-    // device layout: per level rp, col, w, longs, a, ainv (+ agg, mrp, mem, clongs, t for levels with a
-    // coarser one), rbuf and xbuf for l >= 1, then the dense inverse
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        const size_t o = off;
-        off = align_up(off + std::max<size_t>(bytes, 1));
-        return o;
-    };
-    struct Off { size_t rp, col, w, longs, a, ainv, agg, mrp, mem, clongs, t, y, rbuf, xbuf; };
-    std::vector<Off> o(levels);
-    for (int l = 0; l < levels; ++l) {
-        const HostLevel& L = lv[l];
-        const size_t nl = static_cast<size_t>(L.n);
-        o[l].rp = take(sizeof(int) * (nl + 1));
-        o[l].col = take(sizeof(int) * L.col.size());
-        o[l].w = take(sizeof(double) * L.w.size());
-        o[l].longs = take(sizeof(int) * longs[l].size());
-        o[l].a = take(sizeof(double) * nl);
-        o[l].ainv = take(sizeof(double) * nl);
-        o[l].y = take(sizeof(double) * nl);
-        if (l + 1 < levels) {
-            o[l].agg = take(sizeof(int) * nl);
-            o[l].mrp = take(sizeof(int) * mrps[l].size());
-            o[l].mem = take(sizeof(int) * nl);
-            o[l].clongs = take(sizeof(int) * clongs[l].size());
-            o[l].t = take(sizeof(double) * nl);
-        }
-        if (l >= 1) {
-            o[l].rbuf = take(sizeof(double) * nl);
-            o[l].xbuf = take(sizeof(double) * nl);
-        }
-    }
-    const size_t inv_off = take(sizeof(double) * inv.size());
-    void* mem = nullptr;
-    HIPCHK(hipMalloc(&mem, off));
-    h->mem = mem;
-    char* base = static_cast<char*>(mem);
-    auto put = [&](size_t at, const void* src, size_t bytes) -> int {
-        if (bytes) HIPCHK(hipMemcpy(base + at, src, bytes, hipMemcpyHostToDevice));
-        return FJ_OK;
-    };
-    h->levels = levels;
-    for (int l = 0; l < levels; ++l) {
-        const HostLevel& L = lv[l];
-        const size_t nl = static_cast<size_t>(L.n);
-        std::vector<double> ainv(nl);
-        for (size_t i = 0; i < nl; ++i) ainv[i] = 1.0 / a[l][i];
-        if (int rc = put(o[l].rp, L.rp.data(), sizeof(int) * (nl + 1))) return rc;
-        if (int rc = put(o[l].col, L.col.data(), sizeof(int) * L.col.size())) return rc;
-        if (int rc = put(o[l].w, L.w.data(), sizeof(double) * L.w.size())) return rc;
-        if (int rc = put(o[l].longs, longs[l].data(), sizeof(int) * longs[l].size())) return rc;
-        if (int rc = put(o[l].a, a[l].data(), sizeof(double) * nl)) return rc;
-        if (int rc = put(o[l].ainv, ainv.data(), sizeof(double) * nl)) return rc;
-        h->n[l] = L.n;
-        h->nnz[l] = static_cast<int64_t>(L.col.size());
-        h->ybuf[l] = reinterpret_cast<double*>(base + o[l].y);
-        h->ainvs[l] = reinterpret_cast<const double*>(base + o[l].ainv);
-        if (l >= 1) {
-            h->rbuf[l] = reinterpret_cast<double*>(base + o[l].rbuf);
-            h->xbuf[l] = reinterpret_cast<double*>(base + o[l].xbuf);
-        }
-        if (l + 1 < levels) {
-            if (int rc = put(o[l].agg, aggs[l].data(), sizeof(int) * nl)) return rc;
-            if (int rc = put(o[l].mrp, mrps[l].data(), sizeof(int) * mrps[l].size())) return rc;
-            if (int rc = put(o[l].mem, mems[l].data(), sizeof(int) * nl)) return rc;
-            if (int rc = put(o[l].clongs, clongs[l].data(), sizeof(int) * clongs[l].size())) return rc;
-            MlLevel& M = h->lv[l];
-            M.n = L.n;
-            M.nc = lv[l + 1].n;
-            M.nlong = static_cast<int>(longs[l].size());
-            M.nclong = static_cast<int>(clongs[l].size());
-            M.rp = reinterpret_cast<const int*>(base + o[l].rp);
-            M.col = reinterpret_cast<const int*>(base + o[l].col);
-            M.w = reinterpret_cast<const double*>(base + o[l].w);
-            M.longs = reinterpret_cast<const int*>(base + o[l].longs);
-            M.a = reinterpret_cast<const double*>(base + o[l].a);
-            M.ainv = reinterpret_cast<const double*>(base + o[l].ainv);
-            M.agg = reinterpret_cast<const int*>(base + o[l].agg);
-            M.mrp = reinterpret_cast<const int*>(base + o[l].mrp);
-            M.mem = reinterpret_cast<const int*>(base + o[l].mem);
-            M.clongs = reinterpret_cast<const int*>(base + o[l].clongs);
-            M.t = reinterpret_cast<double*>(base + o[l].t);
-            M.y = h->ybuf[l];
-        }
-    }
-    h->nL = last.n;
-    h->ainvL = reinterpret_cast<const double*>(base + o[levels - 1].ainv);
-    if (!inv.empty()) {
-        if (int rc = put(inv_off, inv.data(), sizeof(double) * inv.size())) return rc;
-        h->inv = reinterpret_cast<const double*>(base + inv_off);
-    }
-    return FJ_OK;
-}
-}  // namespace
-
-int fj_hierarchy_create(const fj_csr* g, int32_t coarse_max, fj_hierarchy** out, void* stream) {
-    return guarded([&]() -> int {
-        if (!out) return FJ_ERR_INVALID_ARG;
-        *out = nullptr;
-        if (int rc = check_graph_args(g)) return rc;
-        if (coarse_max < 0) return FJ_ERR_INVALID_ARG;
-        std::unique_ptr<fj_hierarchy> h(new fj_hierarchy);
-        if (int rc = current_device(&h->dev)) return rc;
-        h->n0 = g->n;
-        h->nnz0 = g->nnz;
-        int rc = build_hierarchy(g, coarse_max > 0 ? coarse_max : 1024, static_cast<hipStream_t>(stream), h.get());
-        if (rc) {
-            if (h->mem) (void)hipFree(h->mem);
-            return rc;
-        }
-        *out = h.release();
-        return FJ_OK;
-    });
-}
-
-int fj_hierarchy_shape(const fj_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz, int32_t* dense) {
-    return guarded([&]() -> int {
-        if (!h) return FJ_ERR_INVALID_ARG;
-        if (levels) *levels = h->levels;
-        for (int l = 0; l < ML_MAXL; ++l) {
-            if (n) n[l] = l < h->levels ? h->n[l] : 0;
-            if (nnz) nnz[l] = l < h->levels ? h->nnz[l] : 0;
-        }
-        if (dense) *dense = h->inv != nullptr ? 1 : 0;
-        return FJ_OK;
-    });
-}
-
-int fj_hierarchy_destroy(fj_hierarchy* h) {
-    return guarded([&]() -> int {
-        if (!h) return FJ_OK;
-        int rc = FJ_OK;
-        if (h->mem) {
-            if (hipDeviceSynchronize() != hipSuccess || hipFree(h->mem) != hipSuccess) rc = FJ_ERR_HIP;
-        }
-        delete h;
-        return rc;
-    });
-}
+#include "fj_hierarchy.hpp"
 
 int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,
                 int32_t steps, double tol, void* ws, size_t ws_bytes, void* stream, fj_info* info) {

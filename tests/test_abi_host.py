@@ -162,10 +162,15 @@ def test_every_status_entry_point_is_guarded():
     guarded() (no C++ exception crosses the ABI)."""
     src = open(API).read()
     body = src.split('extern "C" {', 1)[1]
+    csrc = os.path.dirname(API)
+    for inc in re.findall(r'^#include "(fj_\w+\.hpp)"', body, flags=re.M):  # entry points kept in headers
+        body += open(os.path.join(csrc, inc)).read()
     sigs = re.findall(r"^int (fj_\w+)\([^{]*\{\n([^\n]*)\n", body, flags=re.M)
-    assert len(sigs) >= 15
     for name, first in sigs:
         assert first.strip() == "return guarded([&]() -> int {", name
+    header = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    declared = set(re.findall(r"^int (fj_\w+)\(", header, flags=re.M))
+    assert declared and declared <= {name for name, _ in sigs}, declared - {name for name, _ in sigs}
 
 
 def test_guard_maps_exceptions_to_status(tmp_path):
