@@ -292,7 +292,6 @@ int build_hierarchy(const fj_csr* g, int coarse_max, hipStream_t st, fj_hierarch
             M.mem = reinterpret_cast<const int*>(base + o[l].mem);
             M.clongs = reinterpret_cast<const int*>(base + o[l].clongs);
             M.t = reinterpret_cast<double*>(base + o[l].t);
-            M.y = h->ybuf[l];
         }
     }
     h->nL = last.n;

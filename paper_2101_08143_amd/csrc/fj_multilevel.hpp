@@ -47,8 +47,7 @@ struct MlLevel {
     const int* mrp = nullptr;     // members of each aggregate (CSR over level l + 1)
     const int* mem = nullptr;
     const int* clongs = nullptr;  // the long aggregates
-    double* t = nullptr;          // work: n
-    double* y = nullptr;          // work: n, D^-1 b
+    double* t = nullptr;          // work: n (D^-1 b of every level lives in fj_hierarchy::ybuf)
 };
 
 // Row sums of a CSR (weights optional) against op.src, epilogue op.row.
