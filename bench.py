@@ -242,7 +242,47 @@ def gather_ladder(fj, torch, G, g, x64, full=True):
             print(f"[bench] gather ladder: {slices} stream(s), hub {hub}, x{8 * xb}: {ms:.3f} ms, "
                   f"{foot / 2**20:.1f} MB per XCD", file=sys.stderr, flush=True)
             del y
-    return out
+    if not full:
+        return {"slices": out}
+
+    def timed_gather(n, row_ptr, col, val, val_type):
+        """fj_gather_bound over a CSR given as device tensors (no plan needed)."""
+        csr = fj.fj_csr(n=n, nnz=int(col.numel()), row_ptr=row_ptr.data_ptr(), col_idx=col.data_ptr(),
+                        val=val.data_ptr() if val is not None else None, val_type=val_type)
+        G2 = fj.Graph(n=n, nnz=int(col.numel()), row_ptr=row_ptr, col=col, val=val, val_type=val_type, plan=None,
+                      csr=csr, device=col.device)
+        x = torch.rand(n, dtype=torch.float64, device=col.device)
+        y = fj.fj_gather_bound(G2, x)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(10):
+            fj.fj_gather_bound(G2, x, y)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 10
+
+    # uniform random 8-byte gathers (64M of them) by the size of the gathered vector
+    dev = x64.device
+    m = 1 << 26
+    footprint = []
+    for mb in (2, 4, 32, 512):
+        n = (mb << 20) // 8
+        col = torch.randint(0, n, (m,), dtype=torch.int32, device=dev, generator=None)
+        rp = torch.full((n + 1,), m, dtype=torch.int32, device=dev)
+        rp[0] = 0
+        ms = timed_gather(n, rp, col, None, fj.FJ_VAL_UNIT)
+        footprint.append({"footprint_MB": mb, "ms": ms, "G_gathers_per_s": m / ms / 1e6})
+        print(f"[bench] gather ladder: uniform random over {mb} MB: {m / ms / 1e6:.0f} G gathers/s",
+              file=sys.stderr, flush=True)
+        del col, rp
+    # the same matrix with its nodes randomly relabelled (no hub-first order)
+    perm = torch.randperm(g.n, device=dev).to(torch.int32)
+    col = perm[G.col.long()]
+    relabelled = timed_gather(g.n, G.row_ptr, col, G.val, G.val_type)
+    print(f"[bench] gather ladder: CSR order after a random relabelling: {relabelled:.3f} ms", file=sys.stderr,
+          flush=True)
+    del perm, col
+    return {"slices": out, "uniform_random_by_footprint": footprint, "csr_order_relabelled_ms": relabelled}
 
 
 def batched_forms(args, fj, W, torch, dev):
