@@ -462,7 +462,8 @@ def small_configs_form(args, fj, W, torch, dev):
 def multilevel_form(args, fj, W, torch, dev):
     """The 100K-node Chung-Lu graph with weights log-uniform over a factor 1e6:
     microseconds per certified solve with the 2x2 blocks (default), Jacobi and
-    the aggregation V-cycle of FJ_MULTILEVEL, against the oracle per index."""
+    the aggregation V-cycle of FJ_MULTILEVEL, against the oracle per index;
+    then the 2x2 blocks against the V-cycle on the 1M- and 4M-node graphs."""
     g, s, spec = W.workload("wide100k")
     G = fj.Graph.from_csr(g, device=dev, validate=False)
     sd = torch.from_numpy(s).to(dev)
@@ -500,6 +501,32 @@ def multilevel_form(args, fj, W, torch, dev):
           file=sys.stderr, flush=True)
     H.close()
     del G, sd
+    # the same comparison on the benchmark graphs, whose weights lie within a factor 4
+    form["benchmark_graphs"] = {}
+    for name in ("cl1m", "cl4m"):
+        g2, s2, _ = W.workload(name)
+        G2 = fj.Graph.from_csr(g2, device=dev, validate=False)
+        sd2 = torch.from_numpy(s2).to(dev)
+        t0 = time.perf_counter()
+        H2 = fj.Hierarchy(G2)
+        entry = {"hierarchy_build_s": time.perf_counter() - t0, "hierarchy_nodes": H2.shape()[1],
+                 "hierarchy_entries": H2.shape()[2]}
+        for tag, o in (("pairs", fj.make_opts(eps=args.eps)), ("multilevel", fj.make_opts(eps=args.eps, hierarchy=H2))):
+            ws = G2.workspace(1, o)
+            fj.fj_indices(G2, sd2, o, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                _, infos, rc = fj.fj_indices(G2, sd2, o, ws=ws, check=False)
+            torch.cuda.synchronize()
+            entry[tag] = {"us_per_solve": 1e6 * (time.perf_counter() - t0) / 5, "iters": infos[0].iters,
+                          "certified": bool(rc == fj.FJ_OK)}
+        form["benchmark_graphs"][name] = entry
+        print(f"[bench] {name}: pairs {entry['pairs']['us_per_solve']:.0f} us, multilevel "
+              f"{entry['multilevel']['us_per_solve']:.0f} us ({entry['multilevel']['iters']} it)", file=sys.stderr,
+              flush=True)
+        H2.close()
+        del G2, sd2
     torch.cuda.empty_cache()
     return form
 
