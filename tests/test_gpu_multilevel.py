@@ -152,3 +152,45 @@ def test_hierarchy_must_fit_the_call(torch_fj):
     assert rc == fj.FJ_ERR_INVALID_ARG
     H1.close()
     H2.close()
+
+
+DEGENERATE = {
+    "edgeless7": (lambda: W.csr_from_edges(7, []), 0),
+    "single_edge": (lambda: W.csr_from_edges(2, [(0, 1)], [3.5]), 0),
+    "K50": (lambda: W.complete_graph(50, 0.7), 1),
+    "path300_deep": (lambda: W.path_graph(300, 2.0), 1),   # coarse_max 1: as many levels as the cap allows
+    "two_stars": (lambda: W.csr_from_edges(203, [(0, j) for j in range(2, 102)] + [(1, j) for j in range(102, 203)]), 4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_degenerate_graphs_match_dense_oracle(torch_fj, name):
+    """Edgeless, a single edge, a complete graph (one aggregate), a path
+    coarsened down to the level cap, and two stars: the V-cycle solve gives
+    the dense oracle's z, and the certified indices match the dense
+    definitions wherever they are certifiable."""
+    from oracle import dense as D
+    torch, fj = torch_fj
+    build, coarse = DEGENERATE[name]
+    g = build()
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    H = fj.Hierarchy(G, coarse_max=coarse)
+    levels, ns, _, dense = H.shape()
+    say(f"degenerate {name}: {levels} levels {ns}")
+    assert 1 <= levels <= 16 and ns[0] == g.n and all(ns[l + 1] < ns[l] for l in range(levels - 1))
+    s = W.opinions("uniform", g.n, 5)
+    sd = torch.from_numpy(s).to("cuda:0")
+    M = np.eye(g.n) + D.laplacian_dense(g)
+    zref = np.linalg.solve(M, s)
+    z, info, rc = fj.fj_solve(G, sd, fj.make_opts(rtol=1e-12, hierarchy=H))
+    assert rc == fj.FJ_OK
+    assert np.abs(z.cpu().numpy() - zref).max() <= 1e-10 * max(1.0, np.abs(zref).max())
+    ref = D.indices(g, s)
+    vals, infos, rc = fj.fj_indices(G, sd, fj.make_opts(eps=EPS, hierarchy=H), check=False)
+    assert rc in (fj.FJ_OK, fj.FJ_ERR_UNCERTIFIABLE)
+    for j, nm in enumerate(NAMES):
+        diff = abs(vals[0][nm] - ref[nm])
+        assert diff <= infos[0].abs_bound[j] + 1e-12, (nm, diff, infos[0].abs_bound[j])
+        if np.isfinite(infos[0].bound[j]):
+            assert diff <= EPS * abs(ref[nm]), (nm, diff)
+    H.close()
