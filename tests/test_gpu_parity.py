@@ -142,7 +142,7 @@ def test_gather_bound_probe(torch_fj, graphs, name):
     assert np.allclose(y, prod.sum(axis=1), rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("name", ["cl50k_f32", "gnp500_f64", "star6001", "isolated9000"])
+@pytest.mark.parametrize("name", ["cl50k_f32", "gnp500_f64", "star6001", "isolated9000", "path5", "gnp400_f32"])
 @pytest.mark.parametrize("xbytes", [8, 4])
 def test_gather_bound_sliced(torch_fj, graphs, name, xbytes):
     """fj_gather_bound_sliced: one stream reproduces fj_gather_bound bitwise;
