@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # scheduler and the header's declarations do not change what a dispatch reads).
 KERNEL_SOURCES = ["paper_2101_08143_amd/csrc/fj_kernels.hpp", "paper_2101_08143_amd/csrc/fj_batched.hpp",
                   "paper_2101_08143_amd/csrc/fj_blockcg.hpp", "paper_2101_08143_amd/csrc/fj_multilevel.hpp",
-                  "paper_2101_08143_amd/csrc/fj_aids.hpp", "paper_2101_08143_amd/csrc/fj_api.hip"]
+                  "paper_2101_08143_amd/csrc/fj_aids.hpp", "paper_2101_08143_amd/csrc/fj_reorder.hpp",
+                  "paper_2101_08143_amd/csrc/fj_api.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_cl4m.json")
 
 
@@ -531,6 +532,56 @@ def multilevel_form(args, fj, W, torch, dev):
     return form
 
 
+def reorder_form(args, fj, W, torch, dev, G, g, s):
+    """The 4M-node graph with its nodes randomly relabelled (as an arbitrary
+    input labelling would be), solved as given and after fj_reorder_by_degree:
+    milliseconds per certified FP64 solve, and the indices of both against
+    those of the generated labelling."""
+    n = g.n
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    lab = torch.randperm(n, device=dev, generator=gen)  # old node o becomes lab[o]
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), torch.diff(G.row_ptr.long()))
+    key = lab[rows] * n + lab[G.col.long()]
+    key, order = torch.sort(key)
+    del rows
+    col_r = (key % n).to(torch.int32)
+    counts = torch.bincount(key // n, minlength=n)
+    rp_r = torch.zeros(n + 1, dtype=torch.int32, device=dev)
+    rp_r[1:] = torch.cumsum(counts, 0).to(torch.int32)
+    val_r = G.val[order] if G.val is not None else None
+    del key, order, counts
+    Gr = fj.Graph.from_tensors(n, rp_r, col_r, val_r, G.val_type, validate=False)
+    sd = torch.from_numpy(s).to(dev)
+    sr = torch.empty_like(sd)
+    sr[lab] = sd
+    t0 = time.perf_counter()
+    G2, perm = fj.reorder_by_degree(Gr, validate=False)
+    t_reorder = time.perf_counter() - t0
+    s2 = fj.permute(perm, sr)
+    out = {"description": "the 4M-node graph randomly relabelled, then relabelled by degree (fj_reorder_by_degree)",
+           "reorder_s": t_reorder}
+    base, _, _ = fj.fj_indices(G, sd, fj.make_opts(eps=args.eps))
+    for name, GG, ss in (("random_labels", Gr, sr), ("reordered", G2, s2)):
+        o = fj.make_opts(eps=args.eps)
+        ws = GG.workspace(1, o)
+        fj.fj_indices(GG, ss, o, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            vals, infos, rc = fj.fj_indices(GG, ss, o, ws=ws, check=False)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_solve": 1e3 * (time.perf_counter() - t0) / 5, "iters": infos[0].iters,
+                     "certified": bool(rc == fj.FJ_OK),
+                     "max_rel_diff_vs_generated_labels": max(abs(vals[0][k] - base[0][k]) / abs(base[0][k])
+                                                             for k in fj.INDEX_NAMES)}
+        print(f"[bench] {name}: {out[name]['ms_per_solve']:.1f} ms per certified solve", file=sys.stderr,
+              flush=True)
+    del Gr, G2, sr, s2, lab, rp_r, col_r, val_r, perm
+    torch.cuda.empty_cache()
+    return out
+
+
 def fifo_baseline(args, fj, W, torch, graphs, pools, server_sat_rps):
     """The same kind of request stream served the plain way: one FP64
     single-vector fj_indices call per opinion vector, requests in arrival
@@ -708,6 +759,8 @@ def main():
                     help="measured requests per level of the plain FP64 FIFO baseline (0 = skip it)")
     ap.add_argument("--gather-ladder", type=int, default=1,
                     help="time the bare gather over XCD-aligned column slices (0 to skip)")
+    ap.add_argument("--reorder-form", type=int, default=1,
+                    help="solve the 4M-node graph randomly relabelled and reordered by degree (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
@@ -930,6 +983,8 @@ def main():
         }
         print(f"[bench] dynamics: {dinfo['iters']} steps in {t_dyn:.3f}s", file=sys.stderr, flush=True)
         del z_dyn, ws
+    if args.reorder_form and args.workload == "cl4m":
+        result["forms"]["cl4m_relabelled"] = reorder_form(args, fj, W, torch, dev, G, g, s)
     if args.small_configs:
         result["forms"].update(small_configs_form(args, fj, W, torch, dev))
         result["forms"]["wide100k_multilevel"] = multilevel_form(args, fj, W, torch, dev)

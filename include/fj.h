@@ -235,6 +235,35 @@ int fj_spmm_set_choice(const fj_csr *g, int32_t kb, int32_t precision, int32_t c
                        int32_t split, int32_t passes);
 
 /*
+ * Optional operator set-up (the relabelling step of the operator's setup):
+ * relabel the nodes by non-increasing degree (number of stored entries, ties
+ * in the old order). Every CG step gathers a node's value once per
+ * neighbour, so this puts the most gathered values side by side at the front
+ * of every vector, where they share cache lines and stay in L2 (on the 4M-node
+ * workload the bare gather takes 1.61 ms randomly labelled, 1.21 ms hub-first).
+ * Writes the relabelled CSR (device, caller-allocated, g's sizes: row_ptr_out
+ * int32[n + 1], col_out int32[nnz] with each row's columns sorted, val_out of
+ * g's value type or NULL for unit weights) and perm (device int32[n]): new
+ * node i is old node perm[i]. Runs on the host from a device-to-host copy of
+ * the CSR (synchronous on `stream`). The five indices of Section 3.2 are sums
+ * over nodes and edges and do not change under a relabelling: solve the new
+ * graph with fj_permute(perm, s) and bring z back with the inverse
+ * permutation. FJ_ERR_INVALID_ARG for a null output that the graph needs.
+ */
+int fj_reorder_by_degree(const fj_csr *g, int32_t *perm, int32_t *row_ptr_out, int32_t *col_out, void *val_out,
+                         void *stream);
+
+/*
+ * Move a node-major block between labellings: y[i * ldy + c] =
+ * x[perm[i] * ldx + c] (inverse = 0: old labels to new) or y[perm[i] * ldy + c]
+ * = x[i * ldx + c] (inverse = 1: new to old), c < k. perm must be a
+ * permutation of 0..n-1 (entries outside that range are skipped). x, y:
+ * distinct device arrays. Asynchronous on `stream`.
+ */
+int fj_permute(int32_t n, int32_t k, const int32_t *perm, const double *x, int64_t ldx, double *y, int64_t ldy,
+               int32_t inverse, void *stream);
+
+/*
  * The multilevel preconditioner of FJ_MULTILEVEL, a stand-in for the Laplacian
  * solver the method calls (Lemma ST: a nearly-linear-time solver for
  * Laplacian systems, built there by approximate Gaussian elimination) in the

@@ -1975,6 +1975,8 @@ int fj_spmm_set_choice(const fj_csr* g, int32_t kb, int32_t precision, int32_t c
 
 #include "fj_hierarchy.hpp"
 
+#include "fj_reorder.hpp"
+
 int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double* z0, double* z,
                 int32_t steps, double tol, void* ws, size_t ws_bytes, void* stream, fj_info* info) {
     return guarded([&]() -> int {

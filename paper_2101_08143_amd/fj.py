@@ -48,7 +48,8 @@ INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
            "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
-           "fj_spmm_set_choice", "fj_hierarchy_create", "fj_hierarchy_shape", "fj_hierarchy_destroy",
+           "fj_spmm_set_choice", "fj_reorder_by_degree", "fj_permute", "fj_hierarchy_create", "fj_hierarchy_shape",
+           "fj_hierarchy_destroy",
            "fj_gather_bound", "fj_gather_bound_sliced", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
            "fj_server_block_bytes",
            "fj_server_create", "fj_server_destroy", "fj_server_add_graph", "fj_server_submit",
@@ -129,6 +130,8 @@ def lib():
         L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32), P(i32)]
         L.fj_spmm_set_choice.argtypes = [P(fj_csr), i32, i32, i32, i32, i32, i32]
         L.fj_gather_bound.argtypes = [P(fj_csr), vp, vp, vp]
+        L.fj_reorder_by_degree.argtypes = [P(fj_csr), vp, vp, vp, vp, vp]
+        L.fj_permute.argtypes = [i32, i32, vp, vp, i64, vp, i64, i32, vp]
         L.fj_hierarchy_create.argtypes = [P(fj_csr), i32, P(vp), vp]
         L.fj_hierarchy_shape.argtypes = [vp, P(i32), P(i32), P(i64), P(i32)]
         L.fj_hierarchy_destroy.argtypes = [vp]
@@ -149,6 +152,7 @@ def lib():
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
         for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
                      "fj_gather_bound_sliced", "fj_hierarchy_create", "fj_hierarchy_shape", "fj_hierarchy_destroy",
+                     "fj_reorder_by_degree", "fj_permute",
                      "fj_dynamics", "fj_solve", "fj_indices", "fj_indices_noalloc", "fj_server_create",
                      "fj_server_destroy",
                      "fj_server_add_graph", "fj_server_submit", "fj_server_step", "fj_server_poll",
@@ -296,6 +300,37 @@ def fj_spmm_set_choice(graph: Graph, kb: int, cpl: int, grid: int, precision: in
                                   int(split), int(passes))
     if rc != FJ_OK:
         raise FJError(rc, "fj_spmm_set_choice")
+
+
+def reorder_by_degree(graph: "Graph", validate=True, stream=None):
+    """fj_reorder_by_degree: the graph relabelled by non-increasing degree,
+    prepared, and perm (device int32[n], new node i = old node perm[i])."""
+    import torch
+    dev = graph.device
+    perm = torch.empty(graph.n, dtype=torch.int32, device=dev)
+    rp = torch.empty(graph.n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(graph.nnz, dtype=torch.int32, device=dev)
+    val = None if graph.val is None else torch.empty_like(graph.val)
+    rc = lib().fj_reorder_by_degree(ctypes.byref(graph.csr), _ptr(perm), _ptr(rp), _ptr(col) if graph.nnz else None,
+                                    _ptr(val), _stream_handle(torch, stream))
+    if rc != FJ_OK:
+        raise FJError(rc, "fj_reorder_by_degree")
+    return Graph.from_tensors(graph.n, rp, col, val, graph.val_type, validate=validate), perm
+
+
+def permute(perm, x, inverse=False, stream=None):
+    """fj_permute: x (float64, n or n x k, device) from the old labels to the
+    new ones (or back with inverse=True) for perm[new] = old."""
+    import torch
+    assert x.dtype == torch.float64 and x.is_contiguous()
+    n = x.shape[0]
+    k = 1 if x.dim() == 1 else x.shape[1]
+    y = torch.empty_like(x)
+    rc = lib().fj_permute(int(n), int(k), _ptr(perm), _ptr(x), k, _ptr(y), k, 1 if inverse else 0,
+                          _stream_handle(torch, stream))
+    if rc != FJ_OK:
+        raise FJError(rc, "fj_permute")
+    return y
 
 
 class Hierarchy:

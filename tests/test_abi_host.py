@@ -291,3 +291,17 @@ def test_server_option_errors(lib):
                        ("iters_per_replay", 0), ("large_entries", -1)):
         o = fj.fj_server_opts(**{**base, field: bad})
         assert lib.fj_server_create(ctypes.byref(o), ctypes.byref(h)) == fj.FJ_ERR_INVALID_ARG, field
+
+
+def test_reorder_and_permute_argument_errors(lib):
+    """fj_reorder_by_degree needs its outputs; fj_permute needs k >= 1,
+    strides >= k, inverse 0 or 1 and distinct arrays (all before device work)."""
+    csr = fj.fj_csr(n=10, nnz=20, row_ptr=256, col_idx=512, val=1024, val_type=fj.FJ_VAL_F32)
+    p = ctypes.c_void_p(4096)
+    assert lib.fj_reorder_by_degree(ctypes.byref(csr), None, p, p, p, None) == fj.FJ_ERR_INVALID_ARG
+    assert lib.fj_reorder_by_degree(ctypes.byref(csr), p, p, p, None, None) == fj.FJ_ERR_INVALID_ARG
+    x, y = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    for n, k, ldx, ldy, inv, xx, yy in ((10, 0, 1, 1, 0, x, y), (10, 2, 1, 2, 0, x, y), (10, 1, 1, 1, 2, x, y),
+                                        (10, 1, 1, 1, 0, x, x), (-1, 1, 1, 1, 0, x, y)):
+        assert lib.fj_permute(n, k, p, xx, ldx, yy, ldy, inv, None) == fj.FJ_ERR_INVALID_ARG
+    assert lib.fj_permute(0, 1, None, None, 1, None, 1, 0, None) == fj.FJ_OK

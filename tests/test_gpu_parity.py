@@ -771,3 +771,49 @@ def test_pair_preconditioner(torch_fj, span):
         assert its[0] <= 0.75 * its[fj.FJ_DIAG_PRECOND], its
     else:
         assert its[0] <= its[fj.FJ_DIAG_PRECOND], its
+
+
+@pytest.mark.parametrize("name", ["ba3000", "cl50k_f32", "gnp500_f64", "isolated9000", "path5"])
+def test_reorder_by_degree_keeps_indices(torch_fj, graphs, name):
+    """A randomly relabelled graph, reordered by degree: a valid CSR (checked
+    by fj_prepare's validation) with non-increasing degrees, whose certified
+    indices with the permuted opinions match the oracle's for the original
+    labels, and whose z comes back to those labels through the inverse
+    permutation."""
+    import dataclasses
+    torch, fj = torch_fj
+    g, _ = graphs[name]
+    rng = np.random.default_rng(17)
+    lab = rng.permutation(g.n)  # old node o becomes node lab[o]
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    keep = rows < g.col  # each undirected edge once
+    w = None if g.val is None else g.val[keep]
+    edges = np.stack([lab[rows[keep]], lab[g.col[keep]]], axis=1)
+    gr = W.csr_from_edges(g.n, edges.tolist(), None if w is None else w.tolist(),
+                          val_dtype=np.float64 if g.val is None else g.val.dtype)
+    if g.val is None:
+        gr = dataclasses.replace(gr, val=None)
+    say(f"reorder {name} n={g.n}")
+    Gr = fj.Graph.from_csr(gr, device="cuda:0", validate=True)
+    G2, perm = fj.reorder_by_degree(Gr, validate=True)
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(g.n))
+    deg2 = np.diff(G2.row_ptr.cpu().numpy())
+    assert np.all(deg2[:-1] >= deg2[1:])
+    s = W.opinions("uniform", g.n, 23)
+    sr = np.empty_like(s)
+    sr[lab] = s  # the opinions in the random labels
+    ref, _, _ = O.indices(g, s)
+    s2 = fj.permute(perm, torch.from_numpy(sr).to("cuda:0"))
+    vals, infos, rc = fj.fj_indices(G2, s2, fj.make_opts(eps=EPS), check=False)
+    assert rc in (fj.FJ_OK, fj.FJ_ERR_UNCERTIFIABLE)
+    for j, nm in enumerate(NAMES):
+        diff = abs(vals[0][nm] - ref[nm])
+        assert diff <= infos[0].abs_bound[j] + 1e-12, (nm, diff)
+        if np.isfinite(infos[0].bound[j]):
+            assert diff <= EPS * abs(ref[nm]), (nm, diff)
+    z2, _, rc = fj.fj_solve(G2, s2, fj.make_opts(rtol=1e-12))
+    assert rc == fj.FJ_OK
+    zr = fj.permute(perm, z2, inverse=True).cpu().numpy()  # random labels
+    zref, _ = O.solve(g, s, rtol=1e-14)
+    assert np.abs(zr[lab] - zref).max() <= 1e-10
