@@ -65,13 +65,13 @@ def recorded_traffic(kernel: str):
 PROFILE_COMMANDS = [
     "rocprofv3 --kernel-trace --stats -d $P/stats -o run --output-format csv -- python3 bench.py --steps 10 "
     "--warmup 2 --cpu-solves 0 --dynamics-steps 300 --serve-requests 0 --fifo-requests 0 --batched-steps 3 "
-    "--two-solve-steps 1 --small-configs 1 --gather-ladder 2",
+    "--two-solve-steps 1 --small-configs 1 --gather-ladder 2 --reorder-form 0",
     "rocprofv3 --pmc FETCH_SIZE -d $P/fetch -o run --output-format csv -- python3 bench.py --steps 2 --warmup 0 "
     "--cpu-solves 0 --dynamics-steps 20 --serve-requests 0 --fifo-requests 0 --batched-steps 1 --two-solve-steps 0 "
-    "--small-configs 0 --gather-ladder 2",
+    "--small-configs 0 --gather-ladder 2 --reorder-form 0",
     "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 bench.py --steps 2 --warmup 0 "
     "--cpu-solves 0 --dynamics-steps 20 --serve-requests 0 --fifo-requests 0 --batched-steps 1 --two-solve-steps 0 "
-    "--small-configs 0 --gather-ladder 2",
+    "--small-configs 0 --gather-ladder 2 --reorder-form 0",
     "rocprofv3 --pmc FETCH_SIZE -d $P/cfetch -o run --output-format csv -- python3 bench.py --copy-calibration 1024",
     "rocprofv3 --pmc WRITE_SIZE -d $P/cwrite -o run --output-format csv -- python3 bench.py --copy-calibration 1024",
 ]
