@@ -109,6 +109,11 @@ typedef struct fj_csr {
                                   Jacobi; for graphs whose edge weights spread over many orders of magnitude.
                                   Not with FJ_DIAG_PRECOND, FJ_BLOCK_CG, FJ_TWO_SOLVE (a 2-column batched
                                   solve), in the server or fj_indices_noalloc */
+#define FJ_WINDOW_SPMV  1024u  /* one-vector solves with the 2x2 blocks or the V-cycle: run the CG SpMV on the
+                                  row windows (CSR order) even on graphs of >= 524288 nodes, where by default it
+                                  runs on the time-phased layout of the plan (see fj_prepare) */
+#define FJ_PHASED_SPMV  2048u  /* the same solves: run the CG SpMV on the time-phased layout on any graph (by
+                                  default only from 524288 nodes on). Not with FJ_WINDOW_SPMV */
 
 typedef struct fj_hierarchy fj_hierarchy;
 
@@ -169,10 +174,18 @@ size_t fj_plan_bytes(const fj_csr *g);
 /*
  * One-time set-up of the operator I + L for graph g (Section 2.1): the
  * Jacobi preconditioner diag(I + D)^{-1}, the heavy-edge matching and the
- * coefficients of the 2x2 block preconditioner (see FJ_DIAG_PRECOND), and the
- * row-window partition that balances the sparse passes. Writes `plan`
- * (device, >= fj_plan_bytes, 256-byte aligned). Asynchronous on `stream` unless opts->flags has FJ_VALIDATE_GRAPH,
- * which also checks the CSR contract and synchronises. opts may be NULL.
+ * coefficients of the 2x2 block preconditioner (see FJ_DIAG_PRECOND), the
+ * row-window partition that balances the sparse passes, and the time-phased
+ * layout of the entries: the rows dealt to wave-sized chunks of about equal
+ * entries, each chunk's entries ordered by column range of 131072 nodes
+ * ("phase") and by row, so that the whole GPU gathers from one column range
+ * at a time and each XCD's L2 holds it. The layout is built on the host:
+ * fj_prepare copies the CSR to the host and the layout back, which
+ * synchronises `stream` (about a second per 10^8 entries); a graph whose
+ * layout would need 2^31 entry slots or more has none. Writes `plan`
+ * (device, >= fj_plan_bytes, 256-byte aligned; the layout takes about
+ * 4 + value bytes + 2 bytes per entry, plus 16 bytes per node).
+ * FJ_VALIDATE_GRAPH also checks the CSR contract first. opts may be NULL.
  */
 int fj_prepare(const fj_csr *g, const fj_opts *opts, void *plan, size_t plan_bytes, void *stream);
 
@@ -184,6 +197,15 @@ size_t fj_workspace_bytes(const fj_csr *g, int32_t k, const fj_opts *opts);
  * distinct. Asynchronous on `stream`.
  */
 int fj_apply(const fj_csr *g, const void *plan, const double *x, double *y, void *stream);
+
+/*
+ * y = (I + L) x as fj_apply, on the time-phased layout of the plan (the pass
+ * that one-vector CG steps run on large graphs): row sums
+ * ((I + L) x)_i = x_i + d_i x_i - sum_j w_ij x_j with the weighted degree d_i,
+ * added in a fixed order. x, y: device double[n], distinct. Asynchronous on
+ * `stream`. FJ_ERR_INVALID_ARG when the graph has no such layout (see fj_prepare).
+ */
+int fj_apply_phased(const fj_csr *g, const void *plan, const double *x, double *y, void *stream);
 
 /*
  * Z ~= (I + L)^{-1} S (Eq. FJmodel02) for k columns. S and Z are node-major:

@@ -15,7 +15,7 @@ SOURCES = [os.path.join(CSRC, "fj_api.hip")]
 HEADERS = [os.path.join(CSRC, "fj_guard.hpp"), os.path.join(CSRC, "fj_kernels.hpp"), os.path.join(CSRC, "fj_batched.hpp"),
            os.path.join(CSRC, "fj_blockcg.hpp"), os.path.join(CSRC, "fj_multilevel.hpp"),
            os.path.join(CSRC, "fj_aids.hpp"), os.path.join(CSRC, "fj_hierarchy.hpp"),
-           os.path.join(CSRC, "fj_reorder.hpp"),
+           os.path.join(CSRC, "fj_reorder.hpp"), os.path.join(CSRC, "fj_phased.hpp"),
            os.path.join(CSRC, "fj_server.hpp"), os.path.join(os.path.dirname(HERE), "include", "fj.h")]
 
 HIPCC_FLAGS = [

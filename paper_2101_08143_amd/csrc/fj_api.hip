@@ -32,6 +32,7 @@
 #include "fj_batched.hpp"
 #include "fj_blockcg.hpp"
 #include "fj_multilevel.hpp"
+#include "fj_phased.hpp"
 
 using namespace fj;
 
@@ -89,6 +90,7 @@ struct PlanLayout {
     size_t prop;      // int[n], float[n]: matching scratch (proposals, their weights)
     size_t pw;
     size_t flags;     // int[64] scratch for validation
+    PhasedPlan ph;    // the time-phased entry layout (fj_phased.hpp), when ph.s.ok
     size_t total;
 };
 
@@ -113,6 +115,25 @@ PlanLayout plan_layout(const fj_csr* g) {
     off = align_up(off + sizeof(float) * static_cast<size_t>(g->n));
     L.flags = off;
     off = align_up(off + sizeof(int) * 64);
+    L.ph.s = phased_shape(g->n, g->nnz);
+    if (L.ph.s.ok) {
+        const PhasedShape& S = L.ph.s;
+        const size_t vb = g->val_type == FJ_VAL_F64 ? 8 : g->val_type == FJ_VAL_F32 ? 4 : 0;
+        L.ph.ps = off;
+        off = align_up(off + sizeof(int) * static_cast<size_t>(S.W) * (S.P + 1));
+        L.ph.rs = off;
+        off = align_up(off + sizeof(int) * (static_cast<size_t>(S.W) + 1));
+        L.ph.row = off;
+        off = align_up(off + sizeof(int) * static_cast<size_t>(g->n));
+        L.ph.deg = off;
+        off = align_up(off + sizeof(double) * static_cast<size_t>(g->n));
+        L.ph.key = off;
+        off = align_up(off + sizeof(unsigned short) * static_cast<size_t>(S.nnzp));
+        L.ph.col = off;
+        off = align_up(off + sizeof(int) * static_cast<size_t>(S.nnzp));
+        L.ph.val = off;
+        off = align_up(off + vb * static_cast<size_t>(S.nnzp));
+    }
     L.total = off;
     return L;
 }
@@ -306,6 +327,10 @@ int check_opts(const fj_opts* o) {
                       "FJ_TWO_SOLVE");
         return FJ_ERR_INVALID_ARG;
     }
+    if ((o->flags & FJ_WINDOW_SPMV) && (o->flags & FJ_PHASED_SPMV)) {
+        std::snprintf(g_last_error, sizeof g_last_error, "FJ_WINDOW_SPMV and FJ_PHASED_SPMV exclude each other");
+        return FJ_ERR_INVALID_ARG;
+    }
     if (!(o->eps > 0.0 && o->eps < 0.5)) return FJ_ERR_INVALID_ARG;
     if (!(o->rtol >= 0.0 && o->rtol < 1.0)) return FJ_ERR_INVALID_ARG;
     if (o->max_iter < 0 || o->reserved != 0) return FJ_ERR_INVALID_ARG;
@@ -360,6 +385,7 @@ struct Ctx {
     hipStream_t st;
     HostSlots* hs;
     bool profile;
+    bool use_ph = false;  // the one-vector SpMV runs on the time-phased layout
     size_t n_prof = 0;  // FJ_PROFILE event pairs used
     int grid_vec = 1;
     const WinDesc* desc() const { return reinterpret_cast<const WinDesc*>(plan + pl.desc); }
@@ -453,12 +479,20 @@ int cg_iteration_pair(Ctx& c, CgState<T>& S) {
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
-        if (int e = grid_for(k_cg_spmv_pq<Vc, T>, c.pl.K, &grid_win)) return e;
+        if (c.use_ph) {
+            if (int e = grid_for(k_cg_spmv_pq_ph<Vc, T>, (c.pl.ph.s.W + NWAVE - 1) / NWAVE, &grid_win)) return e;
+        } else {
+            if (int e = grid_for(k_cg_spmv_pq<Vc, T>, c.pl.K, &grid_win)) return e;
+        }
         if (c.profile) {
             if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
         }
-        k_cg_spmv_pq<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.q, S.part, S.ctrl);
+        if (c.use_ph)
+            k_cg_spmv_pq_ph<Vc, T><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p, S.q, S.part,
+                                                              S.ctrl);
+        else
+            k_cg_spmv_pq<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.q, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
         if (c.profile) {
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
@@ -921,6 +955,8 @@ int make_ctx(const fj_csr* g, const void* plan, void* ws, size_t ws_bytes, int k
     if (ws_bytes < wl->total) return FJ_ERR_WORKSPACE;
     c->st = static_cast<hipStream_t>(stream);
     c->profile = (o->flags & FJ_PROFILE) != 0;
+    c->use_ph = c->pl.ph.s.ok && ((o->flags & FJ_PHASED_SPMV) ||
+                                  (g->n >= PH_MIN_N && !(o->flags & FJ_WINDOW_SPMV)));
     if (slots) c->hs = slots;
     else if (int rc = host_slots(&c->hs)) return rc;
     return grid_for(k_cg_update<double, true>, (static_cast<int64_t>(g->n) + 2 * WG - 1) / (2 * WG), &c->grid_vec);
@@ -1902,6 +1938,8 @@ int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_byt
             }
             k_pair_coef<<<gv, WG, 0, st>>>(g->n, mate, pw, minv, pc);
             HIPCHK(hipGetLastError());
+            // the time-phased layout, built on the host (synchronises the stream)
+            if (pl.ph.s.ok) return build_phased(g, P, pl.ph, st);
             return FJ_OK;
         });
     });
@@ -1921,6 +1959,29 @@ int fj_apply(const fj_csr* g, const void* plan, const double* x, double* y, void
             int grid = 1;
             if (int rc = grid_for(k_apply<Vc>, pl.K, &grid)) return rc;
             k_apply<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, x, y);
+            HIPCHK(hipGetLastError());
+            return FJ_OK;
+        });
+    });
+}
+
+int fj_apply_phased(const fj_csr* g, const void* plan, const double* x, double* y, void* stream) {
+    return guarded([&]() -> int {
+        if (int rc = check_graph_args(g)) return rc;
+        if (!plan || !aligned(plan)) return FJ_ERR_WORKSPACE;
+        if (g->n == 0) return FJ_OK;
+        if (!x || !y || x == y) return FJ_ERR_INVALID_ARG;
+        const PlanLayout pl = plan_layout(g);
+        if (!pl.ph.s.ok) {
+            std::snprintf(g_last_error, sizeof g_last_error, "no time-phased layout for this graph");
+            return FJ_ERR_INVALID_ARG;
+        }
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        return with_graph(g, [&](auto G) -> int {
+            using Vc = typename decltype(G)::value_type;
+            int grid = 1;
+            if (int rc = grid_for(k_apply_ph<Vc>, (pl.ph.s.W + NWAVE - 1) / NWAVE, &grid)) return rc;
+            k_apply_ph<Vc><<<grid, WG, 0, st>>>(phased_view<Vc>(static_cast<const char*>(plan), pl.ph), x, y);
             HIPCHK(hipGetLastError());
             return FJ_OK;
         });

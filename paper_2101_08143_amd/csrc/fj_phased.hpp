@@ -1,0 +1,466 @@
+// fj_phased.hpp -- the time-phased entry layout of I + L and its SpMV (HIP,
+// gfx950). Part of fj_api.hip's translation unit (included once).
+//
+// On a graph without locality (Chung-Lu, expander-like) every CSR-order row
+// gathers x_j from all over the vector, and a vector larger than one XCD's
+// 4 MB L2 misses on about half of those gathers: the window pass runs at the
+// rate of L2 line fills from the Infinity Cache, not at HBM bandwidth. This
+// layout orders the gathers in time instead:
+//
+//   * The rows are dealt to W wave-chunks (longest-processing-time first over
+//     16-row blocks, so that every chunk holds about nnz / W entries and at
+//     most PH_RMAX rows). A chunk belongs to one wave, which keeps the
+//     chunk's row sums in LDS.
+//   * The columns are cut into P phases of PH_PHASE_NODES nodes (1 MB of an
+//     FP64 vector). A chunk's entries are stored phase by phase, each phase's
+//     entries by local row, and each (chunk, phase) group is padded to a
+//     multiple of 8 entries (padding: column 0, weight 0, key PH_SENT).
+//   * Every wave walks its chunk phase by phase. All chunks are resident at
+//     once and hold about the same entries per phase, so the whole chip
+//     moves through the phases together and each XCD's L2 holds the current
+//     phase of x: the gathers hit L2.
+//
+// Within a phase a wave takes 512 entries at a time, 8 consecutive entries
+// per lane. A lane sums the runs of equal local row in its 8 entries, adds
+// the runs that start and end inside them to LDS, and keeps its first and
+// last run; one segmented scan over the 64 lanes joins the runs that cross
+// lanes, and every row's run is added to LDS exactly once, by one lane, in a
+// fixed order. The result is deterministic. The row sum is the raw
+// sum_j w_ij x_j; with the weighted degree d_i of the row,
+// ((I + L) x)_i = x_i + d_i x_i - sum_j w_ij x_j.
+#pragma once
+
+#include <algorithm>
+#include <cstring>
+#include <exception>
+#include <queue>
+#include <thread>
+#include <vector>
+
+#include "fj_guard.hpp"
+#include "fj_kernels.hpp"
+
+namespace fj {
+
+#define PH_HIPCHK(call)                                                                           \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", #call, hipGetErrorString(e_)); \
+            return FJ_ERR_HIP;                                                                    \
+        }                                                                                         \
+    } while (0)
+
+constexpr int PH_RMAX = 1280;            // rows per wave-chunk (their sums live in LDS)
+constexpr int PH_PHASE_NODES = 131072;   // columns per phase
+constexpr int PH_MIN_N = 524288;         // one-vector solves use the layout from this many nodes on
+constexpr int PH_BLOCK = 16;             // rows dealt together
+constexpr int PH_SINGLE_ABOVE = 2048;    // a 16-row block with more entries is dealt row by row
+constexpr unsigned PH_SENT = 0xFFFFu;    // key of a padding entry
+
+struct PhasedShape {
+    int W = 0;          // wave-chunks (a multiple of 4)
+    int P = 0;          // phases
+    int width = 1;      // columns per phase
+    int64_t nnzp = 0;   // entry slots reserved: nnz + 7 W P (the most padding can take)
+    bool ok = false;    // the layout exists for this graph
+};
+
+inline PhasedShape phased_shape(int n, int64_t nnz) {
+    PhasedShape s;
+    if (n < 1) return s;
+    s.P = static_cast<int>((static_cast<int64_t>(n) + PH_PHASE_NODES - 1) / PH_PHASE_NODES);
+    s.width = static_cast<int>((static_cast<int64_t>(n) + s.P - 1) / s.P);
+    int64_t W = n <= 4096 * 1024 ? std::min<int64_t>(4096, (static_cast<int64_t>(n) + 255) / 256)
+                                 : (static_cast<int64_t>(n) + 1023) / 1024;
+    W = std::max<int64_t>(4, (W + 3) / 4 * 4);
+    s.W = static_cast<int>(W);
+    s.nnzp = nnz + 7 * W * s.P;
+    s.ok = s.nnzp < INT32_MAX && W * (s.P + 1) < INT32_MAX;
+    return s;
+}
+
+template <typename V>
+struct PhasedCsr {
+    int W, P;
+    const int* __restrict__ ps;              // entry offset of (chunk c, phase k) at c (P + 1) + k
+    const int* __restrict__ col;
+    const V* __restrict__ val;
+    const unsigned short* __restrict__ key;  // local row of each entry, PH_SENT for padding
+    const int* __restrict__ rs;              // first local row slot of each chunk (W + 1)
+    const int* __restrict__ row;             // node of each row slot
+    const double* __restrict__ deg;          // weighted degree of each row slot
+};
+
+typedef int ph_iv4 __attribute__((ext_vector_type(4)));
+typedef float ph_fv4 __attribute__((ext_vector_type(4)));
+typedef double ph_dv2 __attribute__((ext_vector_type(2)));
+typedef unsigned ph_uv4 __attribute__((ext_vector_type(4)));
+
+template <typename V>
+__device__ __forceinline__ void ph_weights(const V* __restrict__ val, int i0, double (&w)[8]);
+template <>
+__device__ __forceinline__ void ph_weights<Unit>(const Unit* __restrict__, int, double (&w)[8]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = 1.0;
+}
+template <>
+__device__ __forceinline__ void ph_weights<float>(const float* __restrict__ val, int i0, double (&w)[8]) {
+    const ph_fv4 a = __builtin_nontemporal_load(reinterpret_cast<const ph_fv4*>(val + i0));
+    const ph_fv4 b = __builtin_nontemporal_load(reinterpret_cast<const ph_fv4*>(val + i0) + 1);
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+}
+template <>
+__device__ __forceinline__ void ph_weights<double>(const double* __restrict__ val, int i0, double (&w)[8]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const ph_dv2 a = __builtin_nontemporal_load(reinterpret_cast<const ph_dv2*>(val + i0) + m);
+        w[2 * m] = a.x;
+        w[2 * m + 1] = a.y;
+    }
+}
+
+// Row sums sum_j w_ij x_j of chunk c into a[0 .. rows of c), by one wave.
+template <typename V, typename T>
+__device__ __forceinline__ void ph_chunk_sums(const PhasedCsr<V>& g, int c, const T* __restrict__ x,
+                                              double* a, int lane) {
+    const int r0 = g.rs[c], nr = g.rs[c + 1] - r0;
+    for (int r = lane; r < nr; r += 64) a[r] = 0.0;
+    const int* pc = g.ps + static_cast<int64_t>(c) * (g.P + 1);
+    int s = pc[0];
+    for (int k = 0; k < g.P; ++k) {
+        const int e = pc[k + 1];
+        for (int base = s; base < e; base += 512) {
+            const int i0 = base + lane * 8;
+            const bool act = i0 < e;
+            int j[8];
+            double w[8];
+            unsigned kk[8];
+            if (act) {
+                const ph_iv4 c0 = __builtin_nontemporal_load(reinterpret_cast<const ph_iv4*>(g.col + i0));
+                const ph_iv4 c1 = __builtin_nontemporal_load(reinterpret_cast<const ph_iv4*>(g.col + i0) + 1);
+                const ph_uv4 kv = __builtin_nontemporal_load(reinterpret_cast<const ph_uv4*>(g.key + i0));
+                ph_weights<V>(g.val, i0, w);
+                j[0] = c0.x; j[1] = c0.y; j[2] = c0.z; j[3] = c0.w;
+                j[4] = c1.x; j[5] = c1.y; j[6] = c1.z; j[7] = c1.w;
+                kk[0] = kv.x & 0xFFFFu; kk[1] = kv.x >> 16; kk[2] = kv.y & 0xFFFFu; kk[3] = kv.y >> 16;
+                kk[4] = kv.z & 0xFFFFu; kk[5] = kv.z >> 16; kk[6] = kv.w & 0xFFFFu; kk[7] = kv.w >> 16;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    j[i] = 0;
+                    w[i] = 0.0;
+                    kk[i] = PH_SENT;
+                }
+            }
+            double xv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) xv[i] = act ? static_cast<double>(x[j[i]]) : 0.0;
+            // the lane's runs: the first (hv) is kept, inner runs go to LDS, the last is kept
+            double run = w[0] * xv[0], hv = 0.0;
+            unsigned cur = kk[0];
+            bool multi = false;
+#pragma unroll
+            for (int i = 1; i < 8; ++i) {
+                if (kk[i] != cur) {
+                    if (!multi) {
+                        hv = run;
+                        multi = true;
+                    } else if (cur != PH_SENT) {
+                        a[cur] += run;
+                    }
+                    run = 0.0;
+                    cur = kk[i];
+                }
+                run += w[i] * xv[i];
+            }
+            const unsigned hk = kk[0], tk = cur;
+            if (!multi) hv = run;
+            // lane l continues the last run of lane l - 1 when its first key is that run's key
+            const unsigned tk_prev = __shfl_up(tk, 1, 64);
+            const bool cont = lane > 0 && hk == tk_prev && hk != PH_SENT;
+            // carry chain: a lane with one run that continues adds to the carry it receives
+            double v = multi ? run : hv;
+            bool f = multi || !cont;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const double vu = __shfl_up(v, d, 64);
+                const int fu = __shfl_up(static_cast<int>(f), d, 64);
+                if (lane >= d) {
+                    if (!f) v = vu + v;
+                    f = f || fu;
+                }
+            }
+            const double carry_prev = __shfl_up(v, 1, 64);
+            const double cin = cont ? carry_prev : 0.0;
+            const int cn = __shfl_down(static_cast<int>(cont), 1, 64);
+            const bool cont_next = lane < 63 && cn;
+            if (multi && hk != PH_SENT) a[hk] += cin + hv;
+            if (!cont_next) {
+                if (multi) {
+                    if (tk != PH_SENT) a[tk] += run;
+                } else if (hk != PH_SENT) {
+                    a[hk] += v;
+                }
+            }
+        }
+        s = e;
+    }
+}
+
+// q = (I + L) p - pbar and p^T q (partial slot 0), as k_cg_spmv_pq.
+template <typename V, typename T>
+__global__ void __launch_bounds__(WG) k_cg_spmv_pq_ph(PhasedCsr<V> g, const T* __restrict__ p, T* __restrict__ q,
+                                                      double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double red[NWAVE * 4];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* a = acc[wv];
+    const double shift = ctrl->pbar;
+    double pq = 0.0;
+    for (int c = blockIdx.x * NWAVE + wv; c < g.W; c += gridDim.x * NWAVE) {
+        ph_chunk_sums<V, T>(g, c, p, a, lane);
+        const int r0 = g.rs[c], nr = g.rs[c + 1] - r0;
+        for (int r = lane; r < nr; r += 64) {
+            const int i = g.row[r0 + r];
+            const double pi = static_cast<double>(p[i]);
+            const T qt = static_cast<T>(pi + (g.deg[r0 + r] * pi - a[r]) - shift);
+            q[i] = qt;
+            pq += pi * static_cast<double>(qt);
+        }
+    }
+    double v[1] = {pq};
+    block_sum<1>(v, red);
+    store_partials<1>(v, part);
+}
+
+// y = (I + L) x
+template <typename V>
+__global__ void __launch_bounds__(WG) k_apply_ph(PhasedCsr<V> g, const double* __restrict__ x,
+                                                 double* __restrict__ y) {
+    __shared__ double acc[NWAVE][PH_RMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* a = acc[wv];
+    for (int c = blockIdx.x * NWAVE + wv; c < g.W; c += gridDim.x * NWAVE) {
+        ph_chunk_sums<V, double>(g, c, x, a, lane);
+        const int r0 = g.rs[c], nr = g.rs[c + 1] - r0;
+        for (int r = lane; r < nr; r += 64) {
+            const int i = g.row[r0 + r];
+            const double xi = x[i];
+            y[i] = xi + (g.deg[r0 + r] * xi - a[r]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host build
+
+// Where the layout lives in the plan (byte offsets).
+struct PhasedPlan {
+    PhasedShape s;
+    size_t ps = 0, rs = 0, row = 0, deg = 0, key = 0, col = 0, val = 0;
+};
+
+template <typename V>
+PhasedCsr<V> phased_view(const char* plan, const PhasedPlan& pp) {
+    PhasedCsr<V> g;
+    g.W = pp.s.W;
+    g.P = pp.s.P;
+    g.ps = reinterpret_cast<const int*>(plan + pp.ps);
+    g.col = reinterpret_cast<const int*>(plan + pp.col);
+    g.val = std::is_same<V, Unit>::value ? nullptr : reinterpret_cast<const V*>(plan + pp.val);
+    g.key = reinterpret_cast<const unsigned short*>(plan + pp.key);
+    g.rs = reinterpret_cast<const int*>(plan + pp.rs);
+    g.row = reinterpret_cast<const int*>(plan + pp.row);
+    g.deg = reinterpret_cast<const double*>(plan + pp.deg);
+    return g;
+}
+
+// Runs f(lo, hi) over [0, count) on up to 16 host threads; the split does not
+// change any result (every index is handled by exactly one call). An
+// exception in a thread is passed on after every thread has joined; a thread
+// that cannot be started leaves its range to the calling thread.
+template <typename F>
+void ph_parallel(int count, F f) {
+    const unsigned hc = std::thread::hardware_concurrency();
+    const int nt = std::max(1, std::min<int>({16, hc ? static_cast<int>(hc) : 1, std::max(count, 1)}));
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    std::exception_ptr err[16];
+    std::vector<int> serial;
+    serial.reserve(nt);  // no allocation once threads run
+    for (int t = 0; t < nt; ++t) {
+        const int lo = static_cast<int>(static_cast<int64_t>(count) * t / nt);
+        const int hi = static_cast<int>(static_cast<int64_t>(count) * (t + 1) / nt);
+        std::exception_ptr* slot = &err[t];
+        if (nt == 1) {
+            serial.push_back(t);
+            continue;
+        }
+        try {
+            th.emplace_back([=]() {
+                try {
+                    f(lo, hi);
+                } catch (...) {
+                    *slot = std::current_exception();
+                }
+            });
+        } catch (...) {
+            serial.push_back(t);
+        }
+    }
+    for (int t : serial) {
+        try {
+            f(static_cast<int>(static_cast<int64_t>(count) * t / nt),
+              static_cast<int>(static_cast<int64_t>(count) * (t + 1) / nt));
+        } catch (...) {
+            err[t] = std::current_exception();
+        }
+    }
+    for (auto& t : th) t.join();
+    for (int t = 0; t < nt; ++t)
+        if (err[t]) std::rethrow_exception(err[t]);
+}
+
+// Builds the layout of g into the plan: copies the CSR to the host, deals the
+// rows, sorts the entries by (chunk, phase, local row) with a counting pass
+// per chunk, and copies the result back. Synchronises the stream.
+inline int build_phased(const fj_csr* g, char* plan, const PhasedPlan& pp, hipStream_t st) {
+    const PhasedShape& S = pp.s;
+    const int n = g->n, W = S.W, P = S.P;
+    const int64_t nnz = g->nnz;
+    const size_t vb = g->val_type == FJ_VAL_F64 ? 8 : g->val_type == FJ_VAL_F32 ? 4 : 0;
+    std::vector<int> rp(static_cast<size_t>(n) + 1), col(static_cast<size_t>(nnz));
+    std::vector<unsigned char> val(static_cast<size_t>(nnz) * vb);
+    PH_HIPCHK(hipStreamSynchronize(st));
+    PH_HIPCHK(hipMemcpy(rp.data(), g->row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (nnz > 0) PH_HIPCHK(hipMemcpy(col.data(), g->col_idx, col.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (nnz > 0 && vb) PH_HIPCHK(hipMemcpy(val.data(), g->val, val.size(), hipMemcpyDeviceToHost));
+    auto weight = [&](int64_t e) -> double {
+        if (vb == 8) {
+            double w;
+            std::memcpy(&w, &val[e * 8], 8);
+            return w;
+        }
+        if (vb == 4) {
+            float w;
+            std::memcpy(&w, &val[e * 4], 4);
+            return w;
+        }
+        return 1.0;
+    };
+    // deal 16-row blocks (heavy ones row by row), most entries first, each to
+    // the chunk with the fewest entries that has room (ties: lowest chunk)
+    struct Block {
+        int64_t ent;
+        int b0, b1;
+    };
+    std::vector<Block> blocks;
+    blocks.reserve(static_cast<size_t>(n) / PH_BLOCK + 1);
+    for (int b0 = 0; b0 < n; b0 += PH_BLOCK) {
+        const int b1 = std::min(n, b0 + PH_BLOCK);
+        const int64_t ent = rp[b1] - rp[b0];
+        if (ent > PH_SINGLE_ABOVE) {
+            for (int r = b0; r < b1; ++r) blocks.push_back({rp[r + 1] - rp[r], r, r + 1});
+        } else {
+            blocks.push_back({ent, b0, b1});
+        }
+    }
+    std::stable_sort(blocks.begin(), blocks.end(), [](const Block& x, const Block& y) { return x.ent > y.ent; });
+    using Slot = std::pair<int64_t, int>;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int c = 0; c < W; ++c) heap.push({0, c});
+    std::vector<int> nrows(static_cast<size_t>(W), 0), chunk_of(static_cast<size_t>(n)), lrow_of(static_cast<size_t>(n));
+    std::vector<Slot> aside;
+    for (const Block& b : blocks) {
+        const int len = b.b1 - b.b0;
+        Slot s{};
+        aside.clear();
+        for (;;) {
+            if (heap.empty()) {
+                std::snprintf(g_last_error, sizeof g_last_error, "phased layout: no chunk has room");
+                return FJ_ERR_INTERNAL;
+            }
+            s = heap.top();
+            heap.pop();
+            if (nrows[s.second] + len <= PH_RMAX) break;
+            aside.push_back(s);
+        }
+        for (int r = b.b0; r < b.b1; ++r) {
+            chunk_of[r] = s.second;
+            lrow_of[r] = nrows[s.second]++;
+        }
+        heap.push({s.first + b.ent, s.second});
+        for (const Slot& t : aside) heap.push(t);
+    }
+    std::vector<int> rs(static_cast<size_t>(W) + 1, 0);
+    for (int c = 0; c < W; ++c) rs[c + 1] = rs[c] + nrows[c];
+    std::vector<int> prow(static_cast<size_t>(n));
+    std::vector<double> pdeg(static_cast<size_t>(n));
+    for (int r = 0; r < n; ++r) prow[rs[chunk_of[r]] + lrow_of[r]] = r;
+    // entries per (chunk, phase), padded to multiples of 8
+    std::vector<int64_t> cnt(static_cast<size_t>(W) * P, 0);
+    ph_parallel(W, [&](int lo, int hi) {
+        for (int c = lo; c < hi; ++c) {
+            int64_t* cc = &cnt[static_cast<size_t>(c) * P];
+            for (int a = rs[c]; a < rs[c + 1]; ++a) {
+                const int i = prow[a];
+                double d = 0.0;
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    ++cc[col[e] / S.width];
+                    d += weight(e);
+                }
+                pdeg[a] = d;
+            }
+        }
+    });
+    std::vector<int> ps(static_cast<size_t>(W) * (P + 1));
+    int64_t off = 0;
+    for (int c = 0; c < W; ++c) {
+        for (int k = 0; k < P; ++k) {
+            ps[static_cast<size_t>(c) * (P + 1) + k] = static_cast<int>(off);
+            off += (cnt[static_cast<size_t>(c) * P + k] + 7) / 8 * 8;
+        }
+        ps[static_cast<size_t>(c) * (P + 1) + P] = static_cast<int>(off);
+    }
+    if (off > S.nnzp) {
+        std::snprintf(g_last_error, sizeof g_last_error, "phased layout: %lld slots exceed %lld",
+                      static_cast<long long>(off), static_cast<long long>(S.nnzp));
+        return FJ_ERR_INTERNAL;
+    }
+    const size_t slots = static_cast<size_t>(off);
+    std::vector<int> pcol(slots, 0);
+    std::vector<unsigned char> pval(slots * vb, 0);
+    std::vector<unsigned short> pkey(slots, static_cast<unsigned short>(PH_SENT));
+    ph_parallel(W, [&](int lo, int hi) {
+        std::vector<int64_t> cur(static_cast<size_t>(P));
+        for (int c = lo; c < hi; ++c) {
+            for (int k = 0; k < P; ++k) cur[k] = ps[static_cast<size_t>(c) * (P + 1) + k];
+            for (int a = rs[c]; a < rs[c + 1]; ++a) {
+                const int i = prow[a];
+                const unsigned short lr = static_cast<unsigned short>(a - rs[c]);
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    const int64_t d = cur[col[e] / S.width]++;
+                    pcol[d] = col[e];
+                    if (vb) std::memcpy(&pval[d * vb], &val[static_cast<size_t>(e) * vb], vb);
+                    pkey[d] = lr;
+                }
+            }
+        }
+    });
+    PH_HIPCHK(hipMemcpy(plan + pp.ps, ps.data(), ps.size() * sizeof(int), hipMemcpyHostToDevice));
+    PH_HIPCHK(hipMemcpy(plan + pp.rs, rs.data(), rs.size() * sizeof(int), hipMemcpyHostToDevice));
+    PH_HIPCHK(hipMemcpy(plan + pp.row, prow.data(), prow.size() * sizeof(int), hipMemcpyHostToDevice));
+    PH_HIPCHK(hipMemcpy(plan + pp.deg, pdeg.data(), pdeg.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (slots) {
+        PH_HIPCHK(hipMemcpy(plan + pp.col, pcol.data(), slots * sizeof(int), hipMemcpyHostToDevice));
+        PH_HIPCHK(hipMemcpy(plan + pp.key, pkey.data(), slots * sizeof(unsigned short), hipMemcpyHostToDevice));
+        if (vb) PH_HIPCHK(hipMemcpy(plan + pp.val, pval.data(), slots * vb, hipMemcpyHostToDevice));
+    }
+    return FJ_OK;
+}
+
+#undef PH_HIPCHK
+
+}  // namespace fj

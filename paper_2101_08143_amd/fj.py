@@ -42,12 +42,14 @@ FJ_TWO_SOLVE, FJ_NO_RANGE_CHECK, FJ_VALIDATE_GRAPH, FJ_PROFILE, FJ_NO_TUNE, FJ_W
 FJ_DIAG_PRECOND = 128
 FJ_BLOCK_CG = 256
 FJ_MULTILEVEL = 512
+FJ_WINDOW_SPMV = 1024
+FJ_PHASED_SPMV = 2048
 
 INDEX_NAMES = ("internal_conflict", "disagreement", "polarization", "controversy", "dc_index")
 
 # Every function declared in include/fj.h, in declaration order.
 EXPORTS = ("fj_default_opts", "fj_status_string", "fj_last_error", "fj_plan_bytes", "fj_prepare",
-           "fj_workspace_bytes", "fj_apply", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
+           "fj_workspace_bytes", "fj_apply", "fj_apply_phased", "fj_solve", "fj_apriori_delta", "fj_spmm_choice",
            "fj_spmm_set_choice", "fj_reorder_by_degree", "fj_permute", "fj_hierarchy_create", "fj_hierarchy_shape",
            "fj_hierarchy_destroy",
            "fj_gather_bound", "fj_gather_bound_sliced", "fj_dynamics", "fj_indices", "fj_indices_noalloc",
@@ -125,6 +127,7 @@ def lib():
         L.fj_workspace_bytes.argtypes = [P(fj_csr), i32, P(fj_opts)]
         L.fj_workspace_bytes.restype = sz
         L.fj_apply.argtypes = [P(fj_csr), vp, vp, vp, vp]
+        L.fj_apply_phased.argtypes = [P(fj_csr), vp, vp, vp, vp]
         L.fj_apriori_delta.argtypes = [i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.fj_apriori_delta.restype = ctypes.c_double
         L.fj_spmm_choice.argtypes = [P(fj_csr), i32, i32, P(i32), P(i32), P(i32), P(i32)]
@@ -150,7 +153,7 @@ def lib():
         L.fj_server_step.argtypes = [vp, P(i32)]
         L.fj_server_poll.argtypes = [vp, P(fj_server_done), i32, P(i32)]
         L.fj_server_cancel.argtypes = [vp, ctypes.c_uint64]
-        for name in ("fj_prepare", "fj_apply", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
+        for name in ("fj_prepare", "fj_apply", "fj_apply_phased", "fj_spmm_choice", "fj_spmm_set_choice", "fj_gather_bound",
                      "fj_gather_bound_sliced", "fj_hierarchy_create", "fj_hierarchy_shape", "fj_hierarchy_destroy",
                      "fj_reorder_by_degree", "fj_permute",
                      "fj_dynamics", "fj_solve", "fj_indices", "fj_indices_noalloc", "fj_server_create",
@@ -254,16 +257,17 @@ class Graph:
         return _aligned_empty(torch, nbytes, self.device)
 
 
-def fj_apply(graph: Graph, x, y=None, stream=None):
-    """y = (I + L) x for a device float64 vector x."""
+def fj_apply(graph: Graph, x, y=None, stream=None, phased=False):
+    """y = (I + L) x for a device float64 vector x; phased=True runs
+    fj_apply_phased (the time-phased layout of the plan)."""
     import torch
     assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == graph.n
     if y is None:
         y = torch.empty_like(x)
-    rc = lib().fj_apply(ctypes.byref(graph.csr), _ptr(graph.plan), _ptr(x), _ptr(y),
-                        _stream_handle(torch, stream))
+    fn = lib().fj_apply_phased if phased else lib().fj_apply
+    rc = fn(ctypes.byref(graph.csr), _ptr(graph.plan), _ptr(x), _ptr(y), _stream_handle(torch, stream))
     if rc != FJ_OK:
-        raise FJError(rc, "fj_apply")
+        raise FJError(rc, "fj_apply_phased" if phased else "fj_apply")
     return y
 
 

@@ -305,3 +305,27 @@ def test_reorder_and_permute_argument_errors(lib):
                                         (10, 1, 1, 1, 0, x, x), (-1, 1, 1, 1, 0, x, y)):
         assert lib.fj_permute(n, k, p, xx, ldx, yy, ldy, inv, None) == fj.FJ_ERR_INVALID_ARG
     assert lib.fj_permute(0, 1, None, None, 1, None, 1, 0, None) == fj.FJ_OK
+
+
+def test_phased_layout_arguments(lib):
+    """The plan holds the time-phased layout (about 4 + value + 2 bytes per
+    entry and 16 per node more); FJ_WINDOW_SPMV and FJ_PHASED_SPMV exclude
+    each other; fj_apply_phased checks its arguments (all before device work)."""
+    unit = fj.fj_csr(n=1000, nnz=5000, row_ptr=256, col_idx=512, val=None, val_type=fj.FJ_VAL_UNIT)
+    f64 = fj.fj_csr(n=1000, nnz=5000, row_ptr=256, col_idx=512, val=1024, val_type=fj.FJ_VAL_F64)
+    pu, pd = lib.fj_plan_bytes(ctypes.byref(unit)), lib.fj_plan_bytes(ctypes.byref(f64))
+    assert pd - pu >= 8 * 5000  # the FP64 weights of the layout
+    assert pu >= 6 * 5000 + 12 * 1000
+    out = (fj.fj_indices_t * 1)()
+    o = fj.make_opts(flags=fj.FJ_WINDOW_SPMV | fj.FJ_PHASED_SPMV)
+    rc = lib.fj_indices(ctypes.byref(unit), ctypes.c_void_p(256), 1, ctypes.c_void_p(256), 1,
+                        ctypes.byref(o), ctypes.c_void_p(256), 1 << 30, None, out, None)
+    assert rc == fj.FJ_ERR_INVALID_ARG
+    empty = fj.fj_csr(n=0, nnz=0, row_ptr=None, col_idx=None, val=None, val_type=fj.FJ_VAL_UNIT)
+    assert lib.fj_apply_phased(ctypes.byref(empty), ctypes.c_void_p(256), None, None, None) == fj.FJ_OK
+    assert lib.fj_apply_phased(ctypes.byref(unit), None, ctypes.c_void_p(256), ctypes.c_void_p(512),
+                               None) == fj.FJ_ERR_WORKSPACE
+    assert lib.fj_apply_phased(ctypes.byref(unit), ctypes.c_void_p(256), None, ctypes.c_void_p(512),
+                               None) == fj.FJ_ERR_INVALID_ARG
+    assert lib.fj_apply_phased(ctypes.byref(unit), ctypes.c_void_p(256), ctypes.c_void_p(512),
+                               ctypes.c_void_p(512), None) == fj.FJ_ERR_INVALID_ARG
