@@ -540,12 +540,21 @@ int cg_iteration(Ctx& c, CgState<T>& S) {
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
-        if (int e = grid_for(k_cg_spmv<Vc, T>, c.pl.K, &grid_win)) return e;
+        if (c.use_ph) {
+            if (int e = grid_for(k_cg_spmv_ph<Vc, T>, (c.pl.ph.s.W + NWAVE - 1) / NWAVE, &grid_win)) return e;
+        } else {
+            if (int e = grid_for(k_cg_spmv<Vc, T>, c.pl.K, &grid_win)) return e;
+        }
         if (c.profile) {
             if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
         }
-        k_cg_spmv<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.r, c.minv(), S.q, S.part, S.ctrl);
+        if (c.use_ph)
+            k_cg_spmv_ph<Vc, T><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p, S.r, c.minv(),
+                                                           S.q, S.part, S.ctrl);
+        else
+            k_cg_spmv<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.r, c.minv(), S.q, S.part,
+                                                        S.ctrl);
         HIPCHK(hipGetLastError());
         if (c.profile) {
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof + 1], c.st));
@@ -2082,10 +2091,20 @@ int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double
         int rc = with_graph(g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
             int grid = 1;
-            if (int e = grid_for(k_fj_sweep<Vc>, pl.K, &grid)) return e;
+            // from PH_MIN_N nodes on the sweeps run on the time-phased layout
+            const bool ph = pl.ph.s.ok && n >= PH_MIN_N;
+            if (ph) {
+                if (int e = grid_for(k_fj_sweep_ph<Vc>, (pl.ph.s.W + NWAVE - 1) / NWAVE, &grid)) return e;
+            } else {
+                if (int e = grid_for(k_fj_sweep<Vc>, pl.K, &grid)) return e;
+            }
+            const PhasedCsr<Vc> phg = phased_view<Vc>(static_cast<const char*>(plan), pl.ph);
             auto enqueue = [&](int cnt) -> int {
                 for (int c = 0; c < cnt; ++c, ++queued) {
-                    k_fj_sweep<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, src(queued), s, dst(queued), part, ctrl);
+                    if (ph)
+                        k_fj_sweep_ph<Vc><<<grid, WG, 0, st>>>(phg, src(queued), s, dst(queued), part, ctrl);
+                    else
+                        k_fj_sweep<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, src(queued), s, dst(queued), part, ctrl);
                     HIPCHK(hipGetLastError());
                     k_fin_fj<<<1, WG, 0, st>>>(grid, part, ctrl);
                     HIPCHK(hipGetLastError());

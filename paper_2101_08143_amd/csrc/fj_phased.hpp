@@ -209,6 +209,26 @@ __device__ __forceinline__ void ph_chunk_sums(const PhasedCsr<V>& g, int c, cons
     }
 }
 
+// Every row of every chunk of this wave: op.row(i, x_i, lin, sq, op.load(i))
+// as the window pass calls it, with lin = ((L x)_i) = d_i x_i - sum_j w_ij x_j
+// (AccLin), or lin = sum_j w_ij x_j and sq = d_i (AccRaw).
+template <typename V, typename T, typename Acc, typename Op>
+__device__ __forceinline__ void ph_rows(const PhasedCsr<V>& g, const T* __restrict__ x, Op& op, double* a) {
+    static_assert(!Acc::SQ && !Acc::DEG, "the phased pass forms linear row sums only");
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int c = blockIdx.x * NWAVE + wv; c < g.W; c += gridDim.x * NWAVE) {
+        ph_chunk_sums<V, T>(g, c, x, a, lane);
+        const int r0 = g.rs[c], nr = g.rs[c + 1] - r0;
+        for (int r = lane; r < nr; r += 64) {
+            const int i = g.row[r0 + r];
+            const T xi = x[i];
+            const double d = g.deg[r0 + r];
+            if constexpr (Acc::RAW) op.row(i, xi, a[r], d, op.load(i));
+            else op.row(i, xi, d * static_cast<double>(xi) - a[r], 0.0, op.load(i));
+        }
+    }
+}
+
 // q = (I + L) p - pbar and p^T q (partial slot 0), as k_cg_spmv_pq.
 template <typename V, typename T>
 __global__ void __launch_bounds__(WG) k_cg_spmv_pq_ph(PhasedCsr<V> g, const T* __restrict__ p, T* __restrict__ q,
@@ -216,24 +236,45 @@ __global__ void __launch_bounds__(WG) k_cg_spmv_pq_ph(PhasedCsr<V> g, const T* _
     if (ctrl->done != RUNNING) return;
     __shared__ double acc[NWAVE][PH_RMAX];
     __shared__ double red[NWAVE * 4];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double* a = acc[wv];
-    const double shift = ctrl->pbar;
-    double pq = 0.0;
-    for (int c = blockIdx.x * NWAVE + wv; c < g.W; c += gridDim.x * NWAVE) {
-        ph_chunk_sums<V, T>(g, c, p, a, lane);
-        const int r0 = g.rs[c], nr = g.rs[c + 1] - r0;
-        for (int r = lane; r < nr; r += 64) {
-            const int i = g.row[r0 + r];
-            const double pi = static_cast<double>(p[i]);
-            const T qt = static_cast<T>(pi + (g.deg[r0 + r] * pi - a[r]) - shift);
-            q[i] = qt;
-            pq += pi * static_cast<double>(qt);
-        }
-    }
-    double v[1] = {pq};
+    OpCgSpmvPq<T> op{q, ctrl->pbar};
+    ph_rows<V, T, AccLin>(g, p, op, acc[threadIdx.x >> 6]);
+    double v[1] = {op.pq};
     block_sum<1>(v, red);
     store_partials<1>(v, part);
+}
+
+// q = (I + L) p - pbar with p^T q, r^T M^{-1} q, q^T M^{-1} q (slots 0-2), as k_cg_spmv.
+template <typename V, typename T>
+__global__ void __launch_bounds__(WG) k_cg_spmv_ph(PhasedCsr<V> g, const T* __restrict__ p, const T* __restrict__ r,
+                                                   const float* __restrict__ minv, T* __restrict__ q,
+                                                   double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double red[NWAVE * 4];
+    OpCgSpmv<T> op{r, minv, q, ctrl->pbar};
+    ph_rows<V, T, AccLin>(g, p, op, acc[threadIdx.x >> 6]);
+    double v[3] = {op.pq, op.rmq, op.qmq};
+    block_sum<3>(v, red);
+    store_partials<3>(v, part);
+}
+
+// One FJ step and its largest change (slot 0), as k_fj_sweep.
+template <typename V>
+__global__ void __launch_bounds__(WG) k_fj_sweep_ph(PhasedCsr<V> g, const double* __restrict__ z,
+                                                    const double* __restrict__ s, double* __restrict__ znext,
+                                                    double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done != RUNNING) return;
+    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double red[NWAVE];
+    OpFj op{s, znext};
+    ph_rows<V, double, AccRaw>(g, z, op, acc[threadIdx.x >> 6]);
+    double m = wave_max(op.maxc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) m = fmax(m, red[w]);
+        part[blockIdx.x * NPART] = m;
+    }
 }
 
 // y = (I + L) x
@@ -241,17 +282,8 @@ template <typename V>
 __global__ void __launch_bounds__(WG) k_apply_ph(PhasedCsr<V> g, const double* __restrict__ x,
                                                  double* __restrict__ y) {
     __shared__ double acc[NWAVE][PH_RMAX];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double* a = acc[wv];
-    for (int c = blockIdx.x * NWAVE + wv; c < g.W; c += gridDim.x * NWAVE) {
-        ph_chunk_sums<V, double>(g, c, x, a, lane);
-        const int r0 = g.rs[c], nr = g.rs[c + 1] - r0;
-        for (int r = lane; r < nr; r += 64) {
-            const int i = g.row[r0 + r];
-            const double xi = x[i];
-            y[i] = xi + (g.deg[r0 + r] * xi - a[r]);
-        }
-    }
+    OpApply op{y};
+    ph_rows<V, double, AccLin>(g, x, op, acc[threadIdx.x >> 6]);
 }
 
 // ---------------------------------------------------------------- host build

@@ -146,3 +146,54 @@ def test_default_runs_phased_from_524288_nodes(torch_fj):
     assert rc == fj.FJ_OK
     assert np.linalg.norm(zm.cpu().numpy() - zref) <= 1.1e-10 * np.linalg.norm(s)
     H.close()
+
+
+@pytest.mark.parametrize("name", ["ba3000", "gnp500_f64", "star6001", "isolated9000", "cl100k_unit"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_jacobi_solve_on_phased_spmv_matches_oracle(torch_fj, name, precision):
+    """Jacobi-preconditioned CG (FJ_DIAG_PRECOND) with its SpMV and the three
+    fused dot products on the phased layout (FJ_PHASED_SPMV): every index
+    certified against the oracle."""
+    torch, fj = torch_fj
+    g = GRAPHS[name]()
+    say(f"jacobi phased {name} {precision} n={g.n} nnz={g.nnz}")
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    s = W.opinions("uniform", g.n, 37)
+    ref, _, _ = O.indices(g, s)
+    prec = fj.FJ_FP64 if precision == "fp64" else fj.FJ_MIXED
+    vals, infos, rc = fj.fj_indices(G, torch.from_numpy(s).to("cuda:0"),
+                                    fj.make_opts(eps=EPS, precision=prec,
+                                                 flags=fj.FJ_DIAG_PRECOND | fj.FJ_PHASED_SPMV), check=False)
+    assert rc in (fj.FJ_OK, fj.FJ_ERR_UNCERTIFIABLE), fj.info_dict(infos[0])
+    for j, nm in enumerate(NAMES):
+        diff = abs(vals[0][nm] - ref[nm])
+        assert diff <= infos[0].abs_bound[j] + 1e-12, (nm, diff)
+        if np.isfinite(infos[0].bound[j]):
+            assert diff <= EPS * abs(ref[nm]) and diff <= infos[0].bound[j] * abs(ref[nm]) + 1e-12, (nm, diff)
+
+
+U = np.finfo(np.float64).eps / 2
+
+
+@pytest.mark.parametrize("steps", [1, 5, 40])
+def test_dynamics_on_phased_layout_matches_oracle(torch_fj, steps):
+    """From 524288 nodes on, FJ steps run on the phased layout: each step
+    within a few ulps per term of the oracle's sweep (the step is a
+    max-norm contraction, so per-step errors add up at most linearly), and a
+    restart continues bit for bit."""
+    torch, fj = torch_fj
+    g = GRAPHS["cl600k_f32"]()
+    say(f"dynamics phased cl600k_f32 steps={steps}")
+    G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+    s = np.random.default_rng(31).random(g.n)
+    sd = torch.from_numpy(s).to("cuda:0")
+    z, info = fj.fj_dynamics(G, sd, steps, tol=-1.0)
+    ref, oinfo = O.fj_iterate(g, s, max_sweeps=steps, tol=-1.0)
+    assert info["iters"] == steps == oinfo["sweeps"] and info["status"] == 0
+    dmax = int(np.diff(g.row_ptr).max())
+    err = np.abs(z.cpu().numpy() - ref).max()
+    assert err <= steps * 4.0 * (dmax + 3) * U, err
+    if steps == 5:
+        z2, _ = fj.fj_dynamics(G, sd, 2)
+        z3, _ = fj.fj_dynamics(G, sd, 3, z0=z2)
+        assert torch.equal(z3, z)
