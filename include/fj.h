@@ -180,10 +180,11 @@ size_t fj_plan_bytes(const fj_csr *g);
  * layout of the entries: the rows dealt to wave-sized chunks of about equal
  * entries, each chunk's entries ordered by column range of 131072 nodes
  * ("phase") and by row, so that the whole GPU gathers from one column range
- * at a time and each XCD's L2 holds it. The layout is built on the host:
- * fj_prepare copies the CSR to the host and the layout back, which
- * synchronises `stream` (about a second per 10^8 entries); a graph whose
- * layout would need 2^31 entry slots or more has none. Writes `plan`
+ * at a time and each XCD's L2 holds it. The host deals the rows to the
+ * chunks from row_ptr alone and turns the GPU's counts into offsets; the GPU
+ * counts, sums the degrees and places the entries. fj_prepare therefore
+ * synchronises `stream`. A graph whose layout would need 2^31 entry slots or
+ * more, or more than 2048 phases, has none. Writes `plan`
  * (device, >= fj_plan_bytes, 256-byte aligned; the layout takes about
  * 4 + value bytes + 2 bytes per entry, plus 16 bytes per node).
  * FJ_VALIDATE_GRAPH also checks the CSR contract first. opts may be NULL.

@@ -1947,9 +1947,14 @@ int fj_prepare(const fj_csr* g, const fj_opts* opts, void* plan, size_t plan_byt
             }
             k_pair_coef<<<gv, WG, 0, st>>>(g->n, mate, pw, minv, pc);
             HIPCHK(hipGetLastError());
-            // the time-phased layout, built on the host (synchronises the stream)
-            if (pl.ph.s.ok) return build_phased(g, P, pl.ph, st);
-            return FJ_OK;
+            // the time-phased layout (synchronises the stream)
+            if (!pl.ph.s.ok) return FJ_OK;
+            const int64_t waves = (pl.ph.s.W + NWAVE - 1) / NWAVE;
+            int gc = 1, gp = 1, gf = 1;
+            if (int e = grid_for(k_ph_count<Vc>, waves, &gc)) return e;
+            if (int e = grid_for(k_ph_place<Vc>, waves, &gp)) return e;
+            if (int e = grid_for(k_ph_fill<Vc>, (pl.ph.s.nnzp + WG - 1) / WG, &gf)) return e;
+            return build_phased<Vc>(g, G, P, pl.ph, st, gc, gp, gf);
         });
     });
 }

@@ -31,10 +31,8 @@
 #pragma once
 
 #include <algorithm>
-#include <cstring>
-#include <exception>
 #include <queue>
-#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "fj_guard.hpp"
@@ -57,6 +55,7 @@ constexpr int PH_MIN_N = 524288;         // one-vector solves use the layout fro
 constexpr int PH_BLOCK = 16;             // rows dealt together
 constexpr int PH_SINGLE_ABOVE = 2048;    // a 16-row block with more entries is dealt row by row
 constexpr unsigned PH_SENT = 0xFFFFu;    // key of a padding entry
+constexpr int PH_PMAX = 2048;            // most phases (the placement keeps a cursor per phase in LDS)
 
 struct PhasedShape {
     int W = 0;          // wave-chunks (a multiple of 4)
@@ -76,7 +75,7 @@ inline PhasedShape phased_shape(int n, int64_t nnz) {
     W = std::max<int64_t>(4, (W + 3) / 4 * 4);
     s.W = static_cast<int>(W);
     s.nnzp = nnz + 7 * W * s.P;
-    s.ok = s.nnzp < INT32_MAX && W * (s.P + 1) < INT32_MAX;
+    s.ok = s.nnzp < INT32_MAX && W * (s.P + 1) < INT32_MAX && s.P <= PH_PMAX;
     return s;
 }
 
@@ -309,79 +308,103 @@ PhasedCsr<V> phased_view(const char* plan, const PhasedPlan& pp) {
     return g;
 }
 
-// Runs f(lo, hi) over [0, count) on up to 16 host threads; the split does not
-// change any result (every index is handled by exactly one call). An
-// exception in a thread is passed on after every thread has joined; a thread
-// that cannot be started leaves its range to the calling thread.
-template <typename F>
-void ph_parallel(int count, F f) {
-    const unsigned hc = std::thread::hardware_concurrency();
-    const int nt = std::max(1, std::min<int>({16, hc ? static_cast<int>(hc) : 1, std::max(count, 1)}));
-    std::vector<std::thread> th;
-    th.reserve(nt);
-    std::exception_ptr err[16];
-    std::vector<int> serial;
-    serial.reserve(nt);  // no allocation once threads run
-    for (int t = 0; t < nt; ++t) {
-        const int lo = static_cast<int>(static_cast<int64_t>(count) * t / nt);
-        const int hi = static_cast<int>(static_cast<int64_t>(count) * (t + 1) / nt);
-        std::exception_ptr* slot = &err[t];
-        if (nt == 1) {
-            serial.push_back(t);
-            continue;
-        }
-        try {
-            th.emplace_back([=]() {
-                try {
-                    f(lo, hi);
-                } catch (...) {
-                    *slot = std::current_exception();
-                }
-            });
-        } catch (...) {
-            serial.push_back(t);
+// ------------------------------------------------------- the layout's kernels
+
+// Entries per (chunk, phase) into cnt[c P + k] (zeroed before), and the
+// weighted degree of every row slot, one wave per chunk; a row's weights are
+// summed lane-strided and then by a fixed butterfly.
+template <typename V>
+__global__ void __launch_bounds__(WG) k_ph_count(int W, int P, int width, const int* __restrict__ rs,
+                                                 const int* __restrict__ prow, const int* __restrict__ rp,
+                                                 const int* __restrict__ col, const V* __restrict__ val,
+                                                 int* __restrict__ cnt, double* __restrict__ deg) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int c = blockIdx.x * NWAVE + wv; c < W; c += gridDim.x * NWAVE) {
+        int* cc = cnt + static_cast<int64_t>(c) * P;
+        for (int a = rs[c]; a < rs[c + 1]; ++a) {
+            const int i = prow[a];
+            double d = 0.0;
+            for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+                atomicAdd(&cc[col[e] / width], 1);
+                d += weight_at<V>(val, e);
+            }
+            d = wave_sum(d);
+            if (lane == 0) deg[a] = d;
         }
     }
-    for (int t : serial) {
-        try {
-            f(static_cast<int>(static_cast<int64_t>(count) * t / nt),
-              static_cast<int>(static_cast<int64_t>(count) * (t + 1) / nt));
-        } catch (...) {
-            err[t] = std::current_exception();
-        }
-    }
-    for (auto& t : th) t.join();
-    for (int t = 0; t < nt; ++t)
-        if (err[t]) std::rethrow_exception(err[t]);
 }
 
-// Builds the layout of g into the plan: copies the CSR to the host, deals the
-// rows, sorts the entries by (chunk, phase, local row) with a counting pass
-// per chunk, and copies the result back. Synchronises the stream.
-inline int build_phased(const fj_csr* g, char* plan, const PhasedPlan& pp, hipStream_t st) {
+// Every entry slot to padding: column 0, weight 0, key PH_SENT.
+template <typename V>
+__global__ void __launch_bounds__(WG) k_ph_fill(int64_t slots, int* __restrict__ col, V* __restrict__ val,
+                                                unsigned short* __restrict__ key) {
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * WG + threadIdx.x; e < slots;
+         e += static_cast<int64_t>(gridDim.x) * WG) {
+        col[e] = 0;
+        if constexpr (!std::is_same<V, Unit>::value) val[e] = V(0);
+        key[e] = static_cast<unsigned short>(PH_SENT);
+    }
+}
+
+// Places every entry of chunk c, one wave per chunk: rows in slot order,
+// a row's entries 64 at a time; the lanes that fall in one phase take
+// consecutive slots in lane order (a ballot per distinct phase), so each
+// (chunk, phase) group lists its entries by local row and, within a row, in
+// CSR order, whatever the timing.
+template <typename V>
+__global__ void __launch_bounds__(WG) k_ph_place(int W, int P, int width, const int* __restrict__ ps,
+                                                 const int* __restrict__ rs, const int* __restrict__ prow,
+                                                 const int* __restrict__ rp, const int* __restrict__ col,
+                                                 const V* __restrict__ val, int* __restrict__ pcol,
+                                                 V* __restrict__ pval, unsigned short* __restrict__ pkey) {
+    __shared__ int cur_all[NWAVE][PH_PMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int* cur = cur_all[wv];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int c = blockIdx.x * NWAVE + wv; c < W; c += gridDim.x * NWAVE) {
+        for (int k = lane; k < P; k += 64) cur[k] = ps[static_cast<int64_t>(c) * (P + 1) + k];
+        const int r0 = rs[c];
+        for (int a = r0; a < rs[c + 1]; ++a) {
+            const int i = prow[a];
+            const int e1 = rp[i + 1];
+            const unsigned short lr = static_cast<unsigned short>(a - r0);
+            for (int base = rp[i]; base < e1; base += 64) {
+                const int e = base + lane;
+                const bool act = e < e1;
+                const int j = act ? col[e] : 0;
+                const int k = act ? j / width : -1;
+                uint64_t todo = __ballot(act);
+                while (todo) {
+                    const int first = __builtin_ctzll(todo);
+                    const int k0 = __shfl(k, first, 64);
+                    const uint64_t m = __ballot(k == k0);
+                    const int slot0 = cur[k0];
+                    if (k == k0) {
+                        const int d = slot0 + __builtin_popcountll(m & below);
+                        pcol[d] = j;
+                        if constexpr (!std::is_same<V, Unit>::value) pval[d] = val[e];
+                        pkey[d] = lr;
+                    }
+                    if (lane == first) cur[k0] = slot0 + __builtin_popcountll(m);
+                    todo &= ~m;
+                }
+            }
+        }
+    }
+}
+
+// Builds the layout of g into the plan. The host deals the rows (a greedy,
+// sequential by nature, over about n / 16 blocks, from row_ptr alone) and
+// turns the counts into offsets; the GPU counts, sums the degrees and places
+// the entries. Synchronises the stream.
+template <typename V>
+int build_phased(const fj_csr* g, const Csr<V>& G, char* plan, const PhasedPlan& pp, hipStream_t st,
+                 int grid_count, int grid_place, int grid_fill) {
     const PhasedShape& S = pp.s;
     const int n = g->n, W = S.W, P = S.P;
-    const int64_t nnz = g->nnz;
-    const size_t vb = g->val_type == FJ_VAL_F64 ? 8 : g->val_type == FJ_VAL_F32 ? 4 : 0;
-    std::vector<int> rp(static_cast<size_t>(n) + 1), col(static_cast<size_t>(nnz));
-    std::vector<unsigned char> val(static_cast<size_t>(nnz) * vb);
+    std::vector<int> rp(static_cast<size_t>(n) + 1);
     PH_HIPCHK(hipStreamSynchronize(st));
     PH_HIPCHK(hipMemcpy(rp.data(), g->row_ptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost));
-    if (nnz > 0) PH_HIPCHK(hipMemcpy(col.data(), g->col_idx, col.size() * sizeof(int), hipMemcpyDeviceToHost));
-    if (nnz > 0 && vb) PH_HIPCHK(hipMemcpy(val.data(), g->val, val.size(), hipMemcpyDeviceToHost));
-    auto weight = [&](int64_t e) -> double {
-        if (vb == 8) {
-            double w;
-            std::memcpy(&w, &val[e * 8], 8);
-            return w;
-        }
-        if (vb == 4) {
-            float w;
-            std::memcpy(&w, &val[e * 4], 4);
-            return w;
-        }
-        return 1.0;
-    };
     // deal 16-row blocks (heavy ones row by row), most entries first, each to
     // the chunk with the fewest entries that has room (ties: lowest chunk)
     struct Block {
@@ -429,30 +452,30 @@ inline int build_phased(const fj_csr* g, char* plan, const PhasedPlan& pp, hipSt
     std::vector<int> rs(static_cast<size_t>(W) + 1, 0);
     for (int c = 0; c < W; ++c) rs[c + 1] = rs[c] + nrows[c];
     std::vector<int> prow(static_cast<size_t>(n));
-    std::vector<double> pdeg(static_cast<size_t>(n));
     for (int r = 0; r < n; ++r) prow[rs[chunk_of[r]] + lrow_of[r]] = r;
-    // entries per (chunk, phase), padded to multiples of 8
-    std::vector<int64_t> cnt(static_cast<size_t>(W) * P, 0);
-    ph_parallel(W, [&](int lo, int hi) {
-        for (int c = lo; c < hi; ++c) {
-            int64_t* cc = &cnt[static_cast<size_t>(c) * P];
-            for (int a = rs[c]; a < rs[c + 1]; ++a) {
-                const int i = prow[a];
-                double d = 0.0;
-                for (int e = rp[i]; e < rp[i + 1]; ++e) {
-                    ++cc[col[e] / S.width];
-                    d += weight(e);
-                }
-                pdeg[a] = d;
-            }
-        }
-    });
+    int* d_ps = reinterpret_cast<int*>(plan + pp.ps);
+    int* d_rs = reinterpret_cast<int*>(plan + pp.rs);
+    int* d_row = reinterpret_cast<int*>(plan + pp.row);
+    double* d_deg = reinterpret_cast<double*>(plan + pp.deg);
+    int* d_col = reinterpret_cast<int*>(plan + pp.col);
+    V* d_val = reinterpret_cast<V*>(plan + pp.val);
+    unsigned short* d_key = reinterpret_cast<unsigned short*>(plan + pp.key);
+    PH_HIPCHK(hipMemcpy(d_rs, rs.data(), rs.size() * sizeof(int), hipMemcpyHostToDevice));
+    PH_HIPCHK(hipMemcpy(d_row, prow.data(), prow.size() * sizeof(int), hipMemcpyHostToDevice));
+    // counts (in the offsets' own space, W P <= W (P + 1) ints) and degrees
+    const size_t ncnt = static_cast<size_t>(W) * P;
+    PH_HIPCHK(hipMemsetAsync(d_ps, 0, ncnt * sizeof(int), st));
+    k_ph_count<V><<<grid_count, WG, 0, st>>>(W, P, S.width, d_rs, d_row, G.row_ptr, G.col, G.val, d_ps, d_deg);
+    PH_HIPCHK(hipGetLastError());
+    std::vector<int> cnt(ncnt);
+    PH_HIPCHK(hipMemcpyAsync(cnt.data(), d_ps, ncnt * sizeof(int), hipMemcpyDeviceToHost, st));
+    PH_HIPCHK(hipStreamSynchronize(st));
     std::vector<int> ps(static_cast<size_t>(W) * (P + 1));
     int64_t off = 0;
     for (int c = 0; c < W; ++c) {
         for (int k = 0; k < P; ++k) {
             ps[static_cast<size_t>(c) * (P + 1) + k] = static_cast<int>(off);
-            off += (cnt[static_cast<size_t>(c) * P + k] + 7) / 8 * 8;
+            off += (static_cast<int64_t>(cnt[static_cast<size_t>(c) * P + k]) + 7) / 8 * 8;
         }
         ps[static_cast<size_t>(c) * (P + 1) + P] = static_cast<int>(off);
     }
@@ -461,35 +484,15 @@ inline int build_phased(const fj_csr* g, char* plan, const PhasedPlan& pp, hipSt
                       static_cast<long long>(off), static_cast<long long>(S.nnzp));
         return FJ_ERR_INTERNAL;
     }
-    const size_t slots = static_cast<size_t>(off);
-    std::vector<int> pcol(slots, 0);
-    std::vector<unsigned char> pval(slots * vb, 0);
-    std::vector<unsigned short> pkey(slots, static_cast<unsigned short>(PH_SENT));
-    ph_parallel(W, [&](int lo, int hi) {
-        std::vector<int64_t> cur(static_cast<size_t>(P));
-        for (int c = lo; c < hi; ++c) {
-            for (int k = 0; k < P; ++k) cur[k] = ps[static_cast<size_t>(c) * (P + 1) + k];
-            for (int a = rs[c]; a < rs[c + 1]; ++a) {
-                const int i = prow[a];
-                const unsigned short lr = static_cast<unsigned short>(a - rs[c]);
-                for (int e = rp[i]; e < rp[i + 1]; ++e) {
-                    const int64_t d = cur[col[e] / S.width]++;
-                    pcol[d] = col[e];
-                    if (vb) std::memcpy(&pval[d * vb], &val[static_cast<size_t>(e) * vb], vb);
-                    pkey[d] = lr;
-                }
-            }
-        }
-    });
-    PH_HIPCHK(hipMemcpy(plan + pp.ps, ps.data(), ps.size() * sizeof(int), hipMemcpyHostToDevice));
-    PH_HIPCHK(hipMemcpy(plan + pp.rs, rs.data(), rs.size() * sizeof(int), hipMemcpyHostToDevice));
-    PH_HIPCHK(hipMemcpy(plan + pp.row, prow.data(), prow.size() * sizeof(int), hipMemcpyHostToDevice));
-    PH_HIPCHK(hipMemcpy(plan + pp.deg, pdeg.data(), pdeg.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (slots) {
-        PH_HIPCHK(hipMemcpy(plan + pp.col, pcol.data(), slots * sizeof(int), hipMemcpyHostToDevice));
-        PH_HIPCHK(hipMemcpy(plan + pp.key, pkey.data(), slots * sizeof(unsigned short), hipMemcpyHostToDevice));
-        if (vb) PH_HIPCHK(hipMemcpy(plan + pp.val, pval.data(), slots * vb, hipMemcpyHostToDevice));
+    PH_HIPCHK(hipMemcpy(d_ps, ps.data(), ps.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (off > 0) {
+        k_ph_fill<V><<<grid_fill, WG, 0, st>>>(off, d_col, d_val, d_key);
+        PH_HIPCHK(hipGetLastError());
+        k_ph_place<V><<<grid_place, WG, 0, st>>>(W, P, S.width, d_ps, d_rs, d_row, G.row_ptr, G.col, G.val, d_col,
+                                                 d_val, d_key);
+        PH_HIPCHK(hipGetLastError());
     }
+    PH_HIPCHK(hipStreamSynchronize(st));
     return FJ_OK;
 }
 
