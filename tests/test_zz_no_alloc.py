@@ -60,6 +60,25 @@ def test_noalloc_matches_workspace_entry_point(torch_fj, precision, k):
         _same(fj, a, b)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_noalloc_on_the_phased_layout(torch_fj, precision):
+    """The SpMV on the time-phased layout of the plan: by default on a
+    600K-node graph, forced (FJ_PHASED_SPMV) on a 30K-node one (Jacobi CG);
+    the no-allocation entry point matches fj_indices bit for bit."""
+    torch, fj = torch_fj
+    prec = fj.FJ_MIXED if precision == "mixed" else fj.FJ_FP64
+    for name, g, flags in (("cl600k", W.chung_lu(600_000, 2.2, 12.0, 73, weighted=True), 0),
+                           ("cl30k", W.chung_lu(30_000, 2.5, 8.0, 72), fj.FJ_PHASED_SPMV)):
+        say(f"noalloc phased {name} {precision}")
+        G = fj.Graph.from_csr(g, device="cuda:0", validate=True)
+        s = torch.from_numpy(W.opinions("exp", g.n, 90)).to("cuda:0")
+        o = fj.make_opts(eps=1e-6, precision=prec, flags=flags)
+        a = fj.fj_indices_noalloc(G, s, o, check=False)
+        b = fj.fj_indices(G, s, o, check=False)
+        assert a[2] == fj.FJ_OK, fj.info_dict(a[1][0])
+        _same(fj, a, b)
+
+
 def test_noalloc_rejects_oversized_solve(torch_fj):
     torch, fj = torch_fj
     import ctypes
