@@ -211,18 +211,27 @@ PHASED_MIN_N = 524288
 PH_PHASE_NODES = 131072
 
 
-def phased_shape(n: int):
-    """Wave-chunks W and phases P of the time-phased layout (as fj_prepare)."""
+def phased_shape(n: int, nnz: int):
+    """Wave-chunks W, phases P and the chunk row cap of the time-phased layout
+    (as fj_prepare): short chunks (1248 rows, up to 4096 chunks), or long ones
+    (1600 rows, up to 3072) when the short layout holds a full 512-entry window
+    per chunk and phase."""
     P = -(-n // PH_PHASE_NODES)
-    W = min(4096, -(-n // 256)) if n <= 4096 * 1024 else -(-n // 1024)
-    return max(4, -(-W // 4) * 4), P
+
+    def chunks(rmax, wmax):
+        w = max(-(-n * 6 // (5 * rmax)), min(wmax, -(-n // 256)))
+        return max(4, -(-w // 4) * 4)
+    W, rmax = chunks(1248, 4096), 1248
+    if nnz >= 512 * W * P:
+        W, rmax = chunks(1600, 3072), 1600
+    return W, P, rmax
 
 
 def spmv_ph_layout_bytes(n: int, nnz: int, val_bytes: int) -> int:
     """Bytes the phased SpMV streams at the least (no padding): each entry's
     column, weight and local row once, the chunk tables, each row's node id and
     weighted degree once, p once (an ideal gather) and q written once."""
-    W, P = phased_shape(n)
+    W, P, _ = phased_shape(n, nnz)
     return nnz * (4 + val_bytes + 2) + 4 * W * (P + 1) + 4 * (W + 1) + n * (4 + 8 + 8 + 8)
 
 
@@ -857,8 +866,9 @@ def main():
     phased = pairs and g.n >= PHASED_MIN_N
     b_launch = (spmv_pq_bytes if pairs else spmv_bytes)(g.n, g.nnz, val_bytes)
     vt = {0: "Unit", 4: "float", 8: "double"}[val_bytes]
-    spmv_name = (f"k_cg_spmv_pq_ph<{vt}, double>" if phased else f"k_cg_spmv_pq<{vt}, double>") if pairs \
-        else f"k_cg_spmv<{vt}, double>"
+    ph_rmax = phased_shape(g.n, g.nnz)[2]
+    spmv_name = (f"k_cg_spmv_pq_ph<{vt}, double, {ph_rmax}>" if phased else f"k_cg_spmv_pq<{vt}, double>") \
+        if pairs else f"k_cg_spmv<{vt}, double>"
     avg_ms = fp64["ms_spmv"] / max(fp64["n_spmv"], 1)
     work_ms = fp64["ms_spmv"] / max(fp64["iters"], 1)  # launches past convergence return at once
     bytes_per_launch = b_launch * fp64["iters"] / max(fp64["n_spmv"], 1)  # launches after convergence do no work

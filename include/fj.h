@@ -178,7 +178,8 @@ size_t fj_plan_bytes(const fj_csr *g);
  * coefficients of the 2x2 block preconditioner (see FJ_DIAG_PRECOND), the
  * row-window partition that balances the sparse passes, and the time-phased
  * layout of the entries: the rows dealt to wave-sized chunks of about equal
- * entries, each chunk's entries ordered by column range of 131072 nodes
+ * entries (at most 1248 rows, or 1600 on graphs with many entries per chunk),
+ * each chunk's entries ordered by column range of 131072 nodes
  * ("phase") and by row, so that the whole GPU gathers from one column range
  * at a time and each XCD's L2 holds it. The host deals the rows to the
  * chunks from row_ptr alone and turns the GPU's counts into offsets; the GPU

@@ -479,8 +479,12 @@ int cg_iteration_pair(Ctx& c, CgState<T>& S) {
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
+        const bool lng = c.pl.ph.s.rmax == PH_RMAX_LONG;
+        const int64_t chunk_waves = (c.pl.ph.s.W + NWAVE - 1) / NWAVE;
         if (c.use_ph) {
-            if (int e = grid_for(k_cg_spmv_pq_ph<Vc, T>, (c.pl.ph.s.W + NWAVE - 1) / NWAVE, &grid_win)) return e;
+            if (int e = lng ? grid_for(k_cg_spmv_pq_ph<Vc, T, PH_RMAX_LONG>, chunk_waves, &grid_win)
+                            : grid_for(k_cg_spmv_pq_ph<Vc, T, PH_RMAX_SHORT>, chunk_waves, &grid_win))
+                return e;
         } else {
             if (int e = grid_for(k_cg_spmv_pq<Vc, T>, c.pl.K, &grid_win)) return e;
         }
@@ -488,9 +492,12 @@ int cg_iteration_pair(Ctx& c, CgState<T>& S) {
             if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
         }
-        if (c.use_ph)
-            k_cg_spmv_pq_ph<Vc, T><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p, S.q, S.part,
-                                                              S.ctrl);
+        if (c.use_ph && lng)
+            k_cg_spmv_pq_ph<Vc, T, PH_RMAX_LONG><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p,
+                                                                            S.q, S.part, S.ctrl);
+        else if (c.use_ph)
+            k_cg_spmv_pq_ph<Vc, T, PH_RMAX_SHORT><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p,
+                                                                             S.q, S.part, S.ctrl);
         else
             k_cg_spmv_pq<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.q, S.part, S.ctrl);
         HIPCHK(hipGetLastError());
@@ -540,8 +547,12 @@ int cg_iteration(Ctx& c, CgState<T>& S) {
     int grid_win = 1;
     int rc = with_graph(c.g, [&](auto G) -> int {
         using Vc = typename decltype(G)::value_type;
+        const bool lng = c.pl.ph.s.rmax == PH_RMAX_LONG;
+        const int64_t chunk_waves = (c.pl.ph.s.W + NWAVE - 1) / NWAVE;
         if (c.use_ph) {
-            if (int e = grid_for(k_cg_spmv_ph<Vc, T>, (c.pl.ph.s.W + NWAVE - 1) / NWAVE, &grid_win)) return e;
+            if (int e = lng ? grid_for(k_cg_spmv_ph<Vc, T, PH_RMAX_LONG>, chunk_waves, &grid_win)
+                            : grid_for(k_cg_spmv_ph<Vc, T, PH_RMAX_SHORT>, chunk_waves, &grid_win))
+                return e;
         } else {
             if (int e = grid_for(k_cg_spmv<Vc, T>, c.pl.K, &grid_win)) return e;
         }
@@ -549,9 +560,12 @@ int cg_iteration(Ctx& c, CgState<T>& S) {
             if (int e = profile_events(*c.hs, c.n_prof + 1)) return e;
             HIPCHK(hipEventRecord(c.hs->prof[2 * c.n_prof], c.st));
         }
-        if (c.use_ph)
-            k_cg_spmv_ph<Vc, T><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p, S.r, c.minv(),
-                                                           S.q, S.part, S.ctrl);
+        if (c.use_ph && lng)
+            k_cg_spmv_ph<Vc, T, PH_RMAX_LONG><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p, S.r,
+                                                                         c.minv(), S.q, S.part, S.ctrl);
+        else if (c.use_ph)
+            k_cg_spmv_ph<Vc, T, PH_RMAX_SHORT><<<grid_win, WG, 0, c.st>>>(phased_view<Vc>(c.plan, c.pl.ph), S.p, S.r,
+                                                                          c.minv(), S.q, S.part, S.ctrl);
         else
             k_cg_spmv<Vc, T><<<grid_win, WG, 0, c.st>>>(G, c.desc(), c.pl.K, S.p, S.r, c.minv(), S.q, S.part,
                                                         S.ctrl);
@@ -1994,8 +2008,15 @@ int fj_apply_phased(const fj_csr* g, const void* plan, const double* x, double* 
         return with_graph(g, [&](auto G) -> int {
             using Vc = typename decltype(G)::value_type;
             int grid = 1;
-            if (int rc = grid_for(k_apply_ph<Vc>, (pl.ph.s.W + NWAVE - 1) / NWAVE, &grid)) return rc;
-            k_apply_ph<Vc><<<grid, WG, 0, st>>>(phased_view<Vc>(static_cast<const char*>(plan), pl.ph), x, y);
+            const int64_t chunk_waves = (pl.ph.s.W + NWAVE - 1) / NWAVE;
+            const PhasedCsr<Vc> phg = phased_view<Vc>(static_cast<const char*>(plan), pl.ph);
+            if (pl.ph.s.rmax == PH_RMAX_LONG) {
+                if (int rc = grid_for(k_apply_ph<Vc, PH_RMAX_LONG>, chunk_waves, &grid)) return rc;
+                k_apply_ph<Vc, PH_RMAX_LONG><<<grid, WG, 0, st>>>(phg, x, y);
+            } else {
+                if (int rc = grid_for(k_apply_ph<Vc, PH_RMAX_SHORT>, chunk_waves, &grid)) return rc;
+                k_apply_ph<Vc, PH_RMAX_SHORT><<<grid, WG, 0, st>>>(phg, x, y);
+            }
             HIPCHK(hipGetLastError());
             return FJ_OK;
         });
@@ -2098,16 +2119,24 @@ int fj_dynamics(const fj_csr* g, const void* plan, const double* s, const double
             int grid = 1;
             // from PH_MIN_N nodes on the sweeps run on the time-phased layout
             const bool ph = pl.ph.s.ok && n >= PH_MIN_N;
+            const bool lng = pl.ph.s.rmax == PH_RMAX_LONG;
             if (ph) {
-                if (int e = grid_for(k_fj_sweep_ph<Vc>, (pl.ph.s.W + NWAVE - 1) / NWAVE, &grid)) return e;
+                const int64_t chunk_waves = (pl.ph.s.W + NWAVE - 1) / NWAVE;
+                if (int e = lng ? grid_for(k_fj_sweep_ph<Vc, PH_RMAX_LONG>, chunk_waves, &grid)
+                                : grid_for(k_fj_sweep_ph<Vc, PH_RMAX_SHORT>, chunk_waves, &grid))
+                    return e;
             } else {
                 if (int e = grid_for(k_fj_sweep<Vc>, pl.K, &grid)) return e;
             }
             const PhasedCsr<Vc> phg = phased_view<Vc>(static_cast<const char*>(plan), pl.ph);
             auto enqueue = [&](int cnt) -> int {
                 for (int c = 0; c < cnt; ++c, ++queued) {
-                    if (ph)
-                        k_fj_sweep_ph<Vc><<<grid, WG, 0, st>>>(phg, src(queued), s, dst(queued), part, ctrl);
+                    if (ph && lng)
+                        k_fj_sweep_ph<Vc, PH_RMAX_LONG><<<grid, WG, 0, st>>>(phg, src(queued), s, dst(queued), part,
+                                                                             ctrl);
+                    else if (ph)
+                        k_fj_sweep_ph<Vc, PH_RMAX_SHORT><<<grid, WG, 0, st>>>(phg, src(queued), s, dst(queued), part,
+                                                                              ctrl);
                     else
                         k_fj_sweep<Vc><<<grid, WG, 0, st>>>(G, desc, pl.K, src(queued), s, dst(queued), part, ctrl);
                     HIPCHK(hipGetLastError());

@@ -9,7 +9,7 @@
 //
 //   * The rows are dealt to W wave-chunks (longest-processing-time first over
 //     16-row blocks, so that every chunk holds about nnz / W entries and at
-//     most PH_RMAX rows). A chunk belongs to one wave, which keeps the
+//     most 1248 or 1600 rows). A chunk belongs to one wave, which keeps the
 //     chunk's row sums in LDS.
 //   * The columns are cut into P phases of PH_PHASE_NODES nodes (1 MB of an
 //     FP64 vector). A chunk's entries are stored phase by phase, each phase's
@@ -49,7 +49,21 @@ namespace fj {
         }                                                                                         \
     } while (0)
 
-constexpr int PH_RMAX = 1280;            // rows per wave-chunk (their sums live in LDS)
+// Two chunk geometries: rows per wave-chunk (their sums live in LDS) and the
+// chunk count up to which every chunk is resident at once.
+//   short: 1248 rows, four workgroups (16 waves) per CU, up to 4096 chunks.
+//     For graphs whose chunks hold less than one 512-entry window per phase:
+//     the walk waits on gather latency, and more waves hide more of it.
+//   long: 1600 rows, three workgroups (12 waves) per CU, up to 3072 chunks.
+//     For the others: the walk is bound by the gather rate, and fewer
+//     outstanding misses per CU gather faster (4M-node Chung-Lu graph:
+//     0.67 against 0.85 ms per SpMV).
+constexpr int PH_RMAX_SHORT = 1248, PH_WMAX_SHORT = 4096;
+constexpr int PH_RMAX_LONG = 1600, PH_WMAX_LONG = 3072;
+static_assert(NWAVE * PH_RMAX_SHORT * sizeof(double) + NWAVE * 4 * sizeof(double) <= 160 * 1024 / 4,
+              "short chunks: four workgroups per CU");
+static_assert(NWAVE * PH_RMAX_LONG * sizeof(double) + NWAVE * 4 * sizeof(double) <= 160 * 1024 / 3,
+              "long chunks: three workgroups per CU");
 constexpr int PH_PHASE_NODES = 131072;   // columns per phase
 constexpr int PH_MIN_N = 524288;         // one-vector solves use the layout from this many nodes on
 constexpr int PH_BLOCK = 16;             // rows dealt together
@@ -58,6 +72,7 @@ constexpr unsigned PH_SENT = 0xFFFFu;    // key of a padding entry
 constexpr int PH_PMAX = 2048;            // most phases (the placement keeps a cursor per phase in LDS)
 
 struct PhasedShape {
+    int rmax = PH_RMAX_SHORT;  // rows per chunk at most (PH_RMAX_SHORT or PH_RMAX_LONG)
     int W = 0;          // wave-chunks (a multiple of 4)
     int P = 0;          // phases
     int width = 1;      // columns per phase
@@ -70,9 +85,18 @@ inline PhasedShape phased_shape(int n, int64_t nnz) {
     if (n < 1) return s;
     s.P = static_cast<int>((static_cast<int64_t>(n) + PH_PHASE_NODES - 1) / PH_PHASE_NODES);
     s.width = static_cast<int>((static_cast<int64_t>(n) + s.P - 1) / s.P);
-    int64_t W = n <= 4096 * 1024 ? std::min<int64_t>(4096, (static_cast<int64_t>(n) + 255) / 256)
-                                 : (static_cast<int64_t>(n) + 1023) / 1024;
-    W = std::max<int64_t>(4, (W + 3) / 4 * 4);
+    // about 256 rows per chunk, at most wmax chunks, unless that leaves
+    // chunks of more than rmax / 1.2 rows on average (room for the deal)
+    auto chunks = [&](int rmax, int wmax) {
+        const int64_t by_rows = (static_cast<int64_t>(n) * 6 + 5 * rmax - 1) / (5 * rmax);
+        const int64_t W = std::max<int64_t>(by_rows, std::min<int64_t>(wmax, (static_cast<int64_t>(n) + 255) / 256));
+        return std::max<int64_t>(4, (W + 3) / 4 * 4);
+    };
+    int64_t W = chunks(PH_RMAX_SHORT, PH_WMAX_SHORT);
+    if (nnz >= 512 * W * s.P) {  // a full window per chunk and phase: long chunks
+        s.rmax = PH_RMAX_LONG;
+        W = chunks(PH_RMAX_LONG, PH_WMAX_LONG);
+    }
     s.W = static_cast<int>(W);
     s.nnzp = nnz + 7 * W * s.P;
     s.ok = s.nnzp < INT32_MAX && W * (s.P + 1) < INT32_MAX && s.P <= PH_PMAX;
@@ -229,11 +253,11 @@ __device__ __forceinline__ void ph_rows(const PhasedCsr<V>& g, const T* __restri
 }
 
 // q = (I + L) p - pbar and p^T q (partial slot 0), as k_cg_spmv_pq.
-template <typename V, typename T>
+template <typename V, typename T, int RM>
 __global__ void __launch_bounds__(WG) k_cg_spmv_pq_ph(PhasedCsr<V> g, const T* __restrict__ p, T* __restrict__ q,
                                                       double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double acc[NWAVE][RM];
     __shared__ double red[NWAVE * 4];
     OpCgSpmvPq<T> op{q, ctrl->pbar};
     ph_rows<V, T, AccLin>(g, p, op, acc[threadIdx.x >> 6]);
@@ -243,12 +267,12 @@ __global__ void __launch_bounds__(WG) k_cg_spmv_pq_ph(PhasedCsr<V> g, const T* _
 }
 
 // q = (I + L) p - pbar with p^T q, r^T M^{-1} q, q^T M^{-1} q (slots 0-2), as k_cg_spmv.
-template <typename V, typename T>
+template <typename V, typename T, int RM>
 __global__ void __launch_bounds__(WG) k_cg_spmv_ph(PhasedCsr<V> g, const T* __restrict__ p, const T* __restrict__ r,
                                                    const float* __restrict__ minv, T* __restrict__ q,
                                                    double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double acc[NWAVE][RM];
     __shared__ double red[NWAVE * 4];
     OpCgSpmv<T> op{r, minv, q, ctrl->pbar};
     ph_rows<V, T, AccLin>(g, p, op, acc[threadIdx.x >> 6]);
@@ -258,12 +282,12 @@ __global__ void __launch_bounds__(WG) k_cg_spmv_ph(PhasedCsr<V> g, const T* __re
 }
 
 // One FJ step and its largest change (slot 0), as k_fj_sweep.
-template <typename V>
+template <typename V, int RM>
 __global__ void __launch_bounds__(WG) k_fj_sweep_ph(PhasedCsr<V> g, const double* __restrict__ z,
                                                     const double* __restrict__ s, double* __restrict__ znext,
                                                     double* __restrict__ part, const Ctrl* __restrict__ ctrl) {
     if (ctrl->done != RUNNING) return;
-    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double acc[NWAVE][RM];
     __shared__ double red[NWAVE];
     OpFj op{s, znext};
     ph_rows<V, double, AccRaw>(g, z, op, acc[threadIdx.x >> 6]);
@@ -277,10 +301,10 @@ __global__ void __launch_bounds__(WG) k_fj_sweep_ph(PhasedCsr<V> g, const double
 }
 
 // y = (I + L) x
-template <typename V>
+template <typename V, int RM>
 __global__ void __launch_bounds__(WG) k_apply_ph(PhasedCsr<V> g, const double* __restrict__ x,
                                                  double* __restrict__ y) {
-    __shared__ double acc[NWAVE][PH_RMAX];
+    __shared__ double acc[NWAVE][RM];
     OpApply op{y};
     ph_rows<V, double, AccLin>(g, x, op, acc[threadIdx.x >> 6]);
 }
@@ -439,7 +463,7 @@ int build_phased(const fj_csr* g, const Csr<V>& G, char* plan, const PhasedPlan&
             }
             s = heap.top();
             heap.pop();
-            if (nrows[s.second] + len <= PH_RMAX) break;
+            if (nrows[s.second] + len <= S.rmax) break;
             aside.push_back(s);
         }
         for (int r = b.b0; r < b.b1; ++r) {
