@@ -329,3 +329,34 @@ def test_phased_layout_arguments(lib):
                                None) == fj.FJ_ERR_INVALID_ARG
     assert lib.fj_apply_phased(ctypes.byref(unit), ctypes.c_void_p(256), ctypes.c_void_p(512),
                                ctypes.c_void_p(512), None) == fj.FJ_ERR_INVALID_ARG
+
+
+def _plan_bytes_model(n, nnz, vb):
+    """fj_plan_bytes written out from the plan layout include/fj.h describes:
+    row windows, descriptors, diagonal, matching, flags, then the time-phased
+    layout in bench.py's reading (chunks, phases, slots reserved)."""
+    import bench
+
+    def up(x):
+        return (x + 255) // 256 * 256
+    K = -(-(n + nnz) // 1024)
+    off = 0
+    for size in (4 * (K + 1), 32 * K, 4 * n, 4 * n, 8 * n, 4 * n, 4 * n, 4 * 64):
+        off = up(off + size)
+    W, P, _ = bench.phased_shape(n, nnz)
+    slots = nnz + 7 * W * P
+    for size in (4 * W * (P + 1), 4 * (W + 1), 4 * n, 8 * n, 2 * slots, 4 * slots, vb * slots):
+        off = up(off + size)
+    return off
+
+
+@pytest.mark.parametrize("n,nnz,vt", [(5, 8, 0), (100_000, 1_957_254, 0), (600_000, 7_000_000, 1),
+                                      (1_000_000, 9_991_220, 0), (4_000_000, 119_311_046, 1),
+                                      (4_194_304, 16_777_216, 0), (4_300_000, 8_600_000, 2)])
+def test_plan_bytes_follow_the_phased_shape(lib, n, nnz, vt):
+    """The plan size fj_plan_bytes reports matches the layout written out with
+    bench.py's phased_shape (short or long chunks, phases, reserved slots), so
+    the bench's layout byte counts describe the layout the library builds."""
+    vtype = (fj.FJ_VAL_UNIT, fj.FJ_VAL_F32, fj.FJ_VAL_F64)[vt]
+    csr = fj.fj_csr(n=n, nnz=nnz, row_ptr=256, col_idx=512, val=None if vt == 0 else 1024, val_type=vtype)
+    assert lib.fj_plan_bytes(ctypes.byref(csr)) == _plan_bytes_model(n, nnz, (0, 4, 8)[vt])
