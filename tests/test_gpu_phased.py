@@ -55,7 +55,8 @@ GRAPHS = {
     "hubs12003_f64": hubs_f64,
     "cl100k_unit": lambda: W.chung_lu(100_000, 2.1, 20.0, 14),
     "cl600k_f32": lambda: W.chung_lu(600_000, 2.2, 12.0, 16, weighted=True),  # 5 phases
-    "cycle4300k_w": lambda: W.cycle_graph(4_300_000, 0.8),  # 4200 chunks (more than resident), 33 phases
+    "cycle4300k_w": lambda: W.cycle_graph(4_300_000, 0.8),  # short chunks, more than resident; 33 phases
+    "skewed_cl600k_f64": lambda: W.log_uniform_weights(W.chung_lu(600_000, 2.2, 12.0, 17), 1e4, 6),  # long chunks
 }
 
 
