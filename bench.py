@@ -207,7 +207,7 @@ def solve_bytes(n: int, nnz: int, val_bytes: int, iters: int, pairs: bool) -> di
 # from PHASED_MIN_N nodes on it runs on the time-phased layout of the plan
 # (include/fj.h, FJ_WINDOW_SPMV): k_cg_spmv_pq_ph.
 PAIR_MIN_N = 65536
-PHASED_MIN_N = 524288
+PHASED_MIN_N = 65536
 PH_PHASE_NODES = 131072
 
 
@@ -219,7 +219,8 @@ def phased_shape(n: int, nnz: int):
     P = -(-n // PH_PHASE_NODES)
 
     def chunks(rmax, wmax):
-        w = max(-(-n * 6 // (5 * rmax)), min(wmax, -(-n // 256)))
+        spread = max(-(-n // 256), min(1024, -(-n // 64)))
+        w = max(-(-n * 6 // (5 * rmax)), min(wmax, spread))
         return max(4, -(-w // 4) * 4)
     W, rmax = chunks(1248, 4096), 1248
     if nnz >= 512 * W * P:

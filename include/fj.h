@@ -110,11 +110,11 @@ typedef struct fj_csr {
                                   Not with FJ_DIAG_PRECOND, FJ_BLOCK_CG, FJ_TWO_SOLVE (a 2-column batched
                                   solve), in the server or fj_indices_noalloc */
 #define FJ_WINDOW_SPMV  1024u  /* one-vector solves (any preconditioner): run the CG SpMV on the row windows
-                                  (CSR order) even on graphs of >= 524288 nodes, where by default it runs on the
+                                  (CSR order) even on graphs of >= 65536 nodes, where by default it runs on the
                                   time-phased layout of the plan (see fj_prepare). The index epilogue always
                                   runs on the row windows */
 #define FJ_PHASED_SPMV  2048u  /* one-vector solves: run the CG SpMV on the time-phased layout on any graph (by
-                                  default only from 524288 nodes on). Not with FJ_WINDOW_SPMV */
+                                  default only from 65536 nodes on). Not with FJ_WINDOW_SPMV */
 
 typedef struct fj_hierarchy fj_hierarchy;
 
@@ -376,7 +376,7 @@ int fj_gather_bound_sliced(const fj_csr *g, const void *x, int32_t x_bytes, doub
  * step's largest change, status. Returns FJ_OK when tol was met or tol < 0,
  * FJ_ERR_NOT_CONVERGED when steps ran out first (z still written), and
  * FJ_ERR_BREAKDOWN on a non-finite iterate. Synchronises before returning.
- * From 524288 nodes on the sweeps run on the time-phased layout of the plan
+ * From 65536 nodes on the sweeps run on the time-phased layout of the plan
  * (see fj_prepare), with the weighted degrees the plan holds.
  */
 int fj_dynamics(const fj_csr *g, const void *plan, const double *s, const double *z0, double *z,

@@ -65,7 +65,11 @@ static_assert(NWAVE * PH_RMAX_SHORT * sizeof(double) + NWAVE * 4 * sizeof(double
 static_assert(NWAVE * PH_RMAX_LONG * sizeof(double) + NWAVE * 4 * sizeof(double) <= 160 * 1024 / 3,
               "long chunks: three workgroups per CU");
 constexpr int PH_PHASE_NODES = 131072;   // columns per phase
-constexpr int PH_MIN_N = 524288;         // one-vector solves use the layout from this many nodes on
+// One-vector solves and FJ steps use the layout from this many nodes on (the
+// 2x2-block CG's threshold): certified solves on graphs of 100K to 1M nodes
+// (Chung-Lu, Barabasi-Albert, weights spread over 1e6) took 6-32 % less time
+// than on the row windows; on a 10K-node graph the two were level.
+constexpr int PH_MIN_N = 65536;
 constexpr int PH_BLOCK = 16;             // rows dealt together
 constexpr int PH_SINGLE_ABOVE = 2048;    // a 16-row block with more entries is dealt row by row
 constexpr unsigned PH_SENT = 0xFFFFu;    // key of a padding entry
@@ -85,11 +89,15 @@ inline PhasedShape phased_shape(int n, int64_t nnz) {
     if (n < 1) return s;
     s.P = static_cast<int>((static_cast<int64_t>(n) + PH_PHASE_NODES - 1) / PH_PHASE_NODES);
     s.width = static_cast<int>((static_cast<int64_t>(n) + s.P - 1) / s.P);
-    // about 256 rows per chunk, at most wmax chunks, unless that leaves
-    // chunks of more than rmax / 1.2 rows on average (room for the deal)
+    // about 256 rows per chunk but up to 1024 chunks (at least 64 rows each)
+    // so that mid-size graphs still give every CU a workgroup, at most wmax
+    // chunks, unless that leaves chunks of more than rmax / 1.2 rows on
+    // average (room for the deal)
     auto chunks = [&](int rmax, int wmax) {
-        const int64_t by_rows = (static_cast<int64_t>(n) * 6 + 5 * rmax - 1) / (5 * rmax);
-        const int64_t W = std::max<int64_t>(by_rows, std::min<int64_t>(wmax, (static_cast<int64_t>(n) + 255) / 256));
+        const int64_t nn = n;
+        const int64_t by_rows = (nn * 6 + 5 * rmax - 1) / (5 * rmax);
+        const int64_t spread = std::max<int64_t>((nn + 255) / 256, std::min<int64_t>(1024, (nn + 63) / 64));
+        const int64_t W = std::max<int64_t>(by_rows, std::min<int64_t>(wmax, spread));
         return std::max<int64_t>(4, (W + 3) / 4 * 4);
     };
     int64_t W = chunks(PH_RMAX_SHORT, PH_WMAX_SHORT);

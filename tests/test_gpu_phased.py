@@ -1,7 +1,7 @@
 """The time-phased SpMV (rows dealt to wave-chunks, entries ordered by column
 phase, row sums in LDS) against the CPU oracle, through the C ABI: the bare
 operator (fj_apply_phased) on every graph shape, and CG solves that run their
-SpMV on it (FJ_PHASED_SPMV, and by default from 524288 nodes on)."""
+SpMV on it (FJ_PHASED_SPMV, and by default from 65536 nodes on)."""
 import sys
 
 import numpy as np
@@ -125,9 +125,9 @@ def test_solve_on_phased_spmv_matches_oracle(torch_fj, name, precision):
     assert abs(its["phased"] - its["window"]) <= max(2, its["window"] // 5), its
 
 
-def test_default_runs_phased_from_524288_nodes(torch_fj):
-    """On a 600K-node graph the default one-vector solve is the FJ_PHASED_SPMV
-    solve bit for bit; FJ_WINDOW_SPMV gives the same z within the residual
+def test_default_runs_phased_on_large_graphs(torch_fj):
+    """On a 600K-node and a 100K-node graph the default one-vector solve is the
+    FJ_PHASED_SPMV solve bit for bit; FJ_WINDOW_SPMV gives the same z within the residual
     target; a multilevel solve also runs its SpMV on the layout."""
     torch, fj = torch_fj
     g = W.chung_lu(600_000, 2.2, 12.0, 16, weighted=True)
@@ -143,6 +143,13 @@ def test_default_runs_phased_from_524288_nodes(torch_fj):
     zref, _ = O.solve(g, s, rtol=1e-14)
     for z in (zd, zw):
         assert np.linalg.norm(z.cpu().numpy() - zref) <= 1.1e-10 * np.linalg.norm(s)
+    # a 100K-node graph (short of the L2-sized vector): the default is phased there too
+    g2 = W.chung_lu(100_000, 2.5, 10.0, 3)
+    G2 = fj.Graph.from_csr(g2, device="cuda:0", validate=True)
+    s2 = torch.from_numpy(W.opinions("uniform", g2.n, 30)).to("cuda:0")
+    z2d, _, r1 = fj.fj_solve(G2, s2, fj.make_opts(rtol=1e-10))
+    z2p, _, r2 = fj.fj_solve(G2, s2, fj.make_opts(rtol=1e-10, flags=fj.FJ_PHASED_SPMV))
+    assert r1 == r2 == fj.FJ_OK and torch.equal(z2d, z2p)
     H = fj.Hierarchy(G)
     zm, _, rc = fj.fj_solve(G, sd, fj.make_opts(rtol=1e-10, hierarchy=H))
     assert rc == fj.FJ_OK
@@ -179,7 +186,7 @@ U = np.finfo(np.float64).eps / 2
 
 @pytest.mark.parametrize("steps", [1, 5, 40])
 def test_dynamics_on_phased_layout_matches_oracle(torch_fj, steps):
-    """From 524288 nodes on, FJ steps run on the phased layout: each step
+    """From 65536 nodes on, FJ steps run on the phased layout: each step
     within a few ulps per term of the oracle's sweep (the step is a
     max-norm contraction, so per-step errors add up at most linearly), and a
     restart continues bit for bit."""
