@@ -185,7 +185,7 @@ def spmv_pq_bytes(n: int, nnz: int, val_bytes: int) -> int:
 
 
 def solve_bytes(n: int, nnz: int, val_bytes: int, iters: int, pairs: bool) -> dict:
-    """Algorithmic bytes of one certified FP64 solve in units of the survey's
+    """Algorithmic bytes of one certified FP64 solve in units of the
     per-iteration model B_it = nnz (4 + s_v) + 4 (n + 1) + c_v n 8: c_v counts
     the n-vectors of doubles each iteration moves (an ideal gather reads p
     once). Pair path: SpMV p, q (2); k_pair_dots q, z, mq (3), the partner

@@ -49,7 +49,7 @@ def test_recorded_traffic_lookup():
 
 
 def test_solve_byte_model():
-    """Per-iteration vector streams of the survey's model: 17.5 n-vectors for
+    """Per-iteration vector streams of the solve model: 17.5 n-vectors for
     the pair path, 11 for Jacobi; a solve is iterations plus the epilogue."""
     n, nnz = 4_000_000, 119_311_046
     m = bench.solve_bytes(n, nnz, 4, 11, True)
