@@ -946,6 +946,13 @@ def main():
                                      "time-phased layout orders the gathers by column range over the whole GPU "
                                      "and so runs below this floor",
             "gather_ladder": ladder,
+            "gathers_per_s": g.nnz / (work_ms * 1e-3) if work_ms > 0 else None,
+            "l2_resident_gather_rate": (1e9 * min(ladder["uniform_random_by_footprint"],
+                                                  key=lambda r: r["footprint_MB"])["G_gathers_per_s"]
+                                        if ladder and ladder.get("uniform_random_by_footprint") else None),
+            "gather_rate_note": "one random p_j gather per stored entry: gathers_per_s is the SpMV's, "
+                                "l2_resident_gather_rate the rate of uniform random 8-byte gathers from a "
+                                "2 MB vector (resident in every XCD's L2) on this GPU",
             "measured_copy_GBs": copy_gbs,
             "frac_of_measured_copy": achieved / copy_gbs if copy_gbs > 0 else None,
         },
